@@ -1,0 +1,85 @@
+"""Pins of the oracle's Philox generator and Paired-Sign Probe.
+
+  * Philox4x32-10 against published known-answer vectors (tests/golden).
+  * Definition 3.1 / section 3.3 invariants, for every probe: pi_k is a
+    bijection of [n]; exactly r zeros with r = 1 (n odd) or r in {0, 2}
+    (n even); i is zero iff pi_k(i) >= n - r; partners rho_k(i) =
+    pi_k^{-1}(pi_k(i) xor 1) carry opposite signs, so 1^T z = 0.
+  * Lemma 3.2 statistically: E[z z^T] = H = I - 11^T/n.
+"""
+
+import os
+
+import numpy as np
+import pytest
+
+from oracle import estimator as E
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "philox4x32_10_kat.txt")
+
+
+def test_philox_known_answers():
+    rows = [ln.split() for ln in open(GOLDEN) if ln.strip() and not ln.startswith("#")]
+    assert len(rows) == 3
+    for r in rows:
+        v = [int(x, 16) for x in r]
+        out = E.philox(v[0:4], v[4:6])
+        assert [int(x) for x in out] == v[6:10]
+
+
+@pytest.mark.parametrize("n", list(range(2, 40)) + [63, 64, 65, 255, 256, 257, 1000, 1023, 1024, 1025, 4097])
+def test_probe_invariants(n):
+    nodes = np.arange(n, dtype=np.uint32)
+    rs = set()
+    for k in range(12):
+        pi, z, prm = E.probe(n, 0x1234_5678_9ABC, 5, k)
+        r = int(prm[8])
+        rs.add(r)
+        assert np.array_equal(np.sort(pi), nodes), "pi_k is a bijection"
+        assert r == 1 if n % 2 else r in (0, 2)
+        assert np.array_equal(z == 0, pi >= n - r)
+        assert int((z == 0).sum()) == r
+        assert int(z.astype(np.int64).sum()) == 0
+        inv = np.empty(n, dtype=np.int64)
+        inv[pi] = np.arange(n)
+        act = np.flatnonzero(z != 0)
+        partner = inv[pi[act] ^ 1]
+        assert np.all(z[partner] == -z[act]), "pairs carry opposite signs"
+        assert np.all(partner != act)
+        # sign formula: z = (-1)^(h(pi>>1) + pi), so z*(-1)^pi is constant on a pair
+        sgn = z[act] * (1 - 2 * (pi[act].astype(np.int64) & 1))
+        assert np.all(sgn == z[partner] * (1 - 2 * (pi[partner].astype(np.int64) & 1)))
+    if n % 2 == 0 and n > 2:
+        pass  # coin frequency is checked below over many probes
+
+
+def test_params_ranges_and_coin():
+    P = 2 ** 31 - 1
+    coins = []
+    for k in range(4000):
+        _, _, prm = E.probe(10, 99, 1, k, nodes=np.zeros(1, dtype=np.uint32))
+        a, b, r = int(prm[6]), int(prm[7]), int(prm[8])
+        assert 1 <= a <= P - 1 and 0 <= b <= P - 1
+        coins.append(r == 2)
+    m = np.mean(coins)
+    assert abs(m - 0.5) < 5 * 0.5 / np.sqrt(4000)
+
+
+def test_probe_depends_on_k_uid_seed():
+    base = E.probe(1000, 7, 3, 11)[0]
+    assert not np.array_equal(base, E.probe(1000, 7, 3, 12)[0])
+    assert not np.array_equal(base, E.probe(1000, 7, 4, 11)[0])
+    assert not np.array_equal(base, E.probe(1000, 8, 3, 11)[0])
+    assert np.array_equal(base, E.probe(1000, 7, 3, 11)[0])
+
+
+@pytest.mark.parametrize("n", [5, 8, 13])
+def test_second_moment_is_centering_matrix(n):
+    nk = 60000
+    Z = np.stack([E.probe(n, 4242, 0, k)[1] for k in range(nk)]).astype(np.float64)
+    M = Z.T @ Z / nk
+    H = np.eye(n) - 1.0 / n
+    sd = 1.0 / np.sqrt(nk)
+    assert np.abs(M - H).max() < 5.0 * sd
+    # per-entry diagonal mean is exactly 1 - r/n for each probe; its average -> 1 - 1/n
+    assert np.abs(np.diag(M) - (1 - 1.0 / n)).max() < 5.0 * sd

@@ -1,0 +1,70 @@
+"""Seeded input generators: canonical CSR form and the workload shapes."""
+
+import numpy as np
+import pytest
+import scipy.sparse.csgraph as csgraph
+
+from synth import graphs, queries
+
+
+def _check_canonical(g):
+    rp, col = g.row_ptr, g.col
+    assert rp.dtype == np.int64 and col.dtype == np.int32
+    assert rp[0] == 0 and rp[-1] == col.size
+    assert np.all(np.diff(rp) >= 1), "every node has a neighbour"
+    rows = np.repeat(np.arange(g.n), np.diff(rp))
+    assert np.all(col != rows), "no self-loops"
+    for v in range(0, g.n, max(1, g.n // 200)):
+        nb = col[rp[v]:rp[v + 1]]
+        assert np.all(np.diff(nb) > 0), "sorted, no duplicates"
+    A = g.scipy()
+    assert (A != A.T).nnz == 0, "symmetric"
+    ncomp, _ = csgraph.connected_components(A, directed=False)
+    assert ncomp == 1
+
+
+@pytest.mark.parametrize("maker", [
+    lambda: graphs.complete_graph(6), lambda: graphs.cycle_graph(9),
+    lambda: graphs.path_graph(7), lambda: graphs.random_connected(40, 0.1, 3),
+])
+def test_small_graphs_canonical(maker):
+    _check_canonical(maker())
+
+
+def test_ba1k_shape():
+    g = graphs.workload_graph("ba1k")
+    _check_canonical(g)
+    assert g.n == 1000
+    assert g.nnz == 2 * (6 + 3 * 996)
+    assert g.d_min == 3
+
+
+def test_cl100k_shape():
+    g = graphs.workload_graph("cl100k")
+    _check_canonical(g)
+    assert 95_000 <= g.n <= 100_000
+    assert 9.5 <= g.nnz / g.n <= 10.5
+    assert g.d_min == 1 and g.d_max > 500
+
+
+def test_grid_shape():
+    g = graphs.workload_graph("grid1414")
+    assert g.n == 1414 * 1414
+    assert g.nnz == 2 * (3_995_964 - 199_798)
+    ncomp, _ = csgraph.connected_components(g.scipy(), directed=False)
+    assert ncomp == 1
+    assert g.d_max == 4
+
+
+def test_generators_deterministic():
+    a = graphs.chung_lu(5000, 8.0, 2.5, 11)
+    b = graphs.chung_lu(5000, 8.0, 2.5, 11)
+    assert np.array_equal(a.row_ptr, b.row_ptr) and np.array_equal(a.col, b.col)
+
+
+def test_uniform_pairs():
+    s, t = queries.uniform_pairs(50, 20000, 1)
+    assert np.all(s != t) and s.min() >= 0 and t.max() < 50
+    # uniform over ordered pairs: each node appears as t about 20000/50 times
+    cnt = np.bincount(t, minlength=50)
+    assert abs(cnt.mean() - 400) < 1e-9 and cnt.std() < 60
