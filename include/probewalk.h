@@ -1,0 +1,230 @@
+/*
+ * probewalk.h -- C ABI of the MI355X (gfx950) ProbeWalk library.
+ *
+ * ProbeWalk (Zheng & Zhang, arXiv 2512.05460) estimates the squared
+ * biharmonic distance beta(s,t) = b_st^T (L^+)^2 b_st (Definition 2.1) of a
+ * connected undirected graph under a relative-error target eps (Problem 2.2)
+ * with Algorithm 1: K = B*G Paired-Sign Probes (Definition 3.1, generated on
+ * the fly as in section 3.3), R replicas of two length-L walks per probe
+ * (section 3.2, eq. for phi-hat), the U-statistic Q_R (Lemma 3.4) and the
+ * median of G block means.
+ *
+ * Conventions shared by every entry point
+ *   - Every function returns an int status: BD_OK (0) or a negative BD_E_*
+ *     code. Nothing throws across the ABI. bd_strerror() names a code.
+ *   - Pointers documented as "host" are ordinary host memory, borrowed for
+ *     the duration of the call only; the library keeps no reference to them.
+ *   - "stream" is a hipStream_t passed as void* (NULL = the null stream). The
+ *     calls enqueue work on it and synchronise it before they return, except
+ *     where stated. The library owns the device memory it allocates (graph
+ *     tables, per-call work buffers) and frees it in graph_free /
+ *     bd_server_destroy.
+ *   - Random streams depend only on (seed, uid, k, p, side, step): a query's
+ *     result is bit-identical whatever batch, mode, chunking or server
+ *     traffic it runs in.
+ *   - Limits: 2 <= n <= 2^30, nnz < 2^31, max degree < 2^24, L <= 16383,
+ *     K and R < 2^32.
+ */
+#ifndef PROBEWALK_H
+#define PROBEWALK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define BD_OK          0
+#define BD_E_INVALID  -1  /* bad argument; per query: s == t, s or t out of range,
+                             eps outside (0,1), L < 0 or L > 16383 */
+#define BD_E_GRAPH    -2  /* graph is not simple, symmetric, sorted and connected */
+#define BD_E_RANGE    -3  /* n, nnz or a degree beyond the limits above */
+#define BD_E_BUDGET   -4  /* per query: 2*K*R*L above the policy cap, or K, R >= 2^32 */
+#define BD_E_HIP      -5  /* a HIP runtime call failed */
+#define BD_E_NOMEM    -6  /* device or host allocation failed */
+#define BD_E_NODEVICE -7  /* no usable gfx950 device */
+#define BD_E_NOTFOUND -8  /* unknown server request id */
+#define BD_E_FULL     -9  /* server admission refused: request exceeds the caps */
+#define BD_E_CANCELLED -10 /* server destroyed before the request finished */
+#define BD_E_TIMEOUT  -11 /* bd_server_wait timed out; the request is still running */
+
+/* ---- graph --------------------------------------------------------------- */
+typedef struct bd_graph bd_graph;
+
+/* graph_load_csr flags */
+#define BD_LAYOUT_CSR       0u  /* node table {offset, degree, 1/degree} + neighbour ids:
+                                   two dependent gathers per walk step */
+#define BD_LAYOUT_FAT       1u  /* adds 16-byte adjacency entries {neighbour, its offset,
+                                   its degree, its 1/degree}: one gather per walk step */
+#define BD_SKIP_VALIDATION  2u  /* trust the caller: skip the symmetry, sortedness and
+                                   connectivity checks (ranges are still checked) */
+
+typedef struct {
+    int64_t  n, nnz;
+    int32_t  d_min, d_max;
+    int32_t  bipartite;      /* 1 if the graph is bipartite (section 2.1 assumes not;
+                                the estimator still targets beta^(L)) */
+    int32_t  layout;         /* BD_LAYOUT_CSR or BD_LAYOUT_FAT */
+    int64_t  device_bytes;   /* device memory held by the graph tables */
+} bd_graph_info;
+
+/*
+ * Load a graph (section 2.1: connected, undirected, simple) and keep it
+ * resident on the current device.
+ *   n        number of nodes.
+ *   row_ptr  host, n+1 int64 offsets, row_ptr[0] = 0, nondecreasing.
+ *   col_idx  host, row_ptr[n] int32 neighbour ids; each row ascending, no
+ *            self-loops, no repeats, and the adjacency symmetric. The order of
+ *            a row is part of the contract: the walk's neighbour index j
+ *            selects col_idx[row_ptr[x] + j].
+ *   flags    BD_LAYOUT_* | BD_SKIP_VALIDATION.
+ *   out      receives the handle; release with graph_free.
+ * Errors: BD_E_GRAPH if a check fails (disconnected, asymmetric, unsorted,
+ * self-loop), BD_E_RANGE for sizes beyond the limits, BD_E_NOMEM, BD_E_HIP.
+ */
+int  graph_load_csr(int64_t n, const int64_t* row_ptr, const int32_t* col_idx,
+                    uint32_t flags, void* stream, bd_graph** out);
+void graph_free(bd_graph* g);
+int  bd_graph_get_info(const bd_graph* g, bd_graph_info* info);
+
+/* ---- walk-count policy (Algorithm 1 parameters, Theorem 3.8) --------------- */
+#define BD_POLICY_PAPER  0  /* B = ceil(448/eps^2), R = ceil(128 (L+1)^2 / (d_min^2 (1-eps/2) (1/d_s+1/d_t)^2)) */
+#define BD_POLICY_SCALED 1  /* the same formulas with c_B, c_R in place of 448, 128 */
+#define BD_POLICY_FIXED  2  /* B = B_fixed, R = R_fixed */
+
+typedef struct {
+    int32_t  kind;
+    double   c_B, c_R;       /* BD_POLICY_SCALED */
+    double   delta;          /* failure probability; G = ceil(8 ln(1/delta)); 0 -> 0.01 */
+    int64_t  B_fixed, R_fixed;
+    uint64_t max_steps_per_query;  /* 0 = no cap; a query above it gets BD_E_BUDGET */
+} bd_policy;
+
+typedef struct {
+    double   beta;           /* beta-hat^(L)(s,t), binary64 */
+    int64_t  K, R;           /* probes and replicas per probe */
+    int32_t  B, G, L;
+    int32_t  status;         /* BD_OK, BD_E_INVALID or BD_E_BUDGET for this query */
+    int64_t  walk_steps;     /* 2*K*R*L transitions (saturates at INT64_MAX) */
+} bd_result;
+
+/*
+ * Plan only (Algorithm 1 parameters). Fills K, R, B, G, L, walk_steps and
+ * status of out[0..nq); beta is set to 0. No device work. pol may be NULL
+ * (BD_POLICY_PAPER, delta = 0.01).
+ */
+int bd_plan(const bd_graph* g, int64_t nq, const int32_t* s, const int32_t* t,
+            const double* eps, const int32_t* L, const bd_policy* pol, bd_result* out);
+
+/* ---- execution ------------------------------------------------------------ */
+#define BD_MODE_PLAIN    0u  /* one query per launch, fixed tiling */
+#define BD_MODE_BATCHED  1u  /* all queries in one persistent launch with work stealing */
+
+typedef struct {
+    uint32_t mode;
+    int32_t  chunk_probes;   /* probes per work-group chunk; 0 = automatic */
+    int32_t  grid_wgs;       /* persistent grid size (BATCHED); 0 = resident capacity */
+    int32_t  use_graph;      /* BATCHED: replay a captured hipGraph of the launch */
+} bd_exec;
+
+typedef struct {
+    double   walk_kernel_ms; /* summed HIP-event time of the walk kernel launches */
+    double   total_ms;       /* wall time of the call */
+    int64_t  launches;       /* walk kernel launches */
+    int64_t  chunks;         /* work-group chunks processed */
+    int64_t  walk_steps;     /* transitions executed (valid queries) */
+    int64_t  walk_pairs;     /* (k, p) pairs executed */
+} bd_stats;
+
+/*
+ * Estimate beta(s,t) for nq queries (Algorithm 1 for each).
+ *   s, t, eps, L   host arrays of nq entries.
+ *   uid            host array of nq query ids for the random streams, or
+ *                  NULL for uid[i] = i. uid < 2^31.
+ *   seed           64-bit Philox key.
+ *   pol            walk-count policy (NULL = paper constants).
+ *   exec           execution mode (NULL = BD_MODE_BATCHED, automatic sizes).
+ *   out            host, nq results (caller-allocated).
+ *   stats          host, optional (may be NULL).
+ * Returns BD_OK when the batch ran; per-query failures are reported in
+ * out[i].status and leave the other queries unaffected.
+ */
+int bd_query_batch(bd_graph* g, int64_t nq, const int32_t* s, const int32_t* t,
+                   const double* eps, const int32_t* L, const uint32_t* uid,
+                   uint64_t seed, const bd_policy* pol, const bd_exec* exec,
+                   void* stream, bd_result* out, bd_stats* stats);
+
+/* ---- validation entry points (expose intermediate values for parity tests) -- */
+
+/*
+ * Node sequences X_0..X_L of `count` walks (the walk step of the production
+ * kernels, section 3.2) and their binary32 sums of z/d.
+ *   start, uid, k, p, side  host arrays of `count` entries (side 0 = s-walk,
+ *                           1 = t-walk; selects the random stream).
+ *   trace                   host, count*(L+1) int32, row-major; may be NULL.
+ *   acc                     host, count floats; may be NULL.
+ */
+int bd_walk_trace(bd_graph* g, int64_t count, const int32_t* start, const uint32_t* uid,
+                  const uint32_t* k, const uint32_t* p, const uint32_t* side, int32_t L,
+                  uint64_t seed, void* stream, int32_t* trace, float* acc);
+
+/*
+ * pi_k(x) and z^(k)_x (section 3.3 stateless generator) for `count` nodes.
+ *   nodes  host, count uint32 node ids (< n).
+ *   pi     host, count uint32 (may be NULL); z host, count int8 (may be NULL).
+ */
+int bd_probe_eval(bd_graph* g, uint64_t seed, uint32_t uid, uint32_t k, int64_t count,
+                  const uint32_t* nodes, void* stream, uint32_t* pi, int8_t* z);
+
+/*
+ * One query with its intermediate values: the K per-probe statistics Q_k
+ * (Alg. 1 Q_R(z^(k))) and the G block means. q_out (K doubles) and ybar_out
+ * (G doubles) are host arrays sized from bd_plan; either may be NULL.
+ */
+int bd_query_probes(bd_graph* g, int32_t s, int32_t t, double eps, int32_t L, uint32_t uid,
+                    uint64_t seed, const bd_policy* pol, const bd_exec* exec, void* stream,
+                    double* q_out, double* ybar_out, bd_result* out);
+
+/* ---- served mode: continuous batching ---------------------------------------- */
+typedef struct bd_server bd_server;
+
+typedef struct {
+    bd_policy policy;
+    int64_t   max_queries_inflight;   /* admission cap on resident queries (0 = 65536) */
+    uint64_t  max_steps_inflight;     /* admission cap on outstanding walk steps (0 = none) */
+    int32_t   chunk_probes;           /* 0 = automatic */
+    double    slice_ms;               /* target device time per scheduling slice (0 = 20) */
+} bd_server_cfg;
+
+/*
+ * Create a server over a loaded graph. The server owns a host scheduler thread
+ * and a device stream; requests submitted while others run are admitted at
+ * the next slice boundary as capacity frees up, and their chunks share the
+ * device with the running ones. The graph must outlive the server.
+ */
+int  bd_server_create(bd_graph* g, const bd_server_cfg* cfg, bd_server** out);
+/* Submit nq queries (host arrays, copied). Returns a request id. BD_E_FULL if
+ * the request alone exceeds the admission caps. uid as in bd_query_batch. */
+int  bd_server_submit(bd_server* srv, int64_t nq, const int32_t* s, const int32_t* t,
+                      const double* eps, const int32_t* L, const uint32_t* uid,
+                      uint64_t seed, uint64_t* request_id);
+/* Non-blocking poll: *done = 1 and out[0..nq) filled when the request finished. */
+int  bd_server_poll(bd_server* srv, uint64_t request_id, bd_result* out, int* done,
+                    double* latency_ms);
+/* Block until the request finishes (timeout_ms <= 0: no timeout). */
+int  bd_server_wait(bd_server* srv, uint64_t request_id, double timeout_ms, bd_result* out,
+                    double* latency_ms);
+void bd_server_destroy(bd_server* srv);
+
+/* ---- misc ------------------------------------------------------------------ */
+const char* bd_strerror(int code);
+/* Writes a one-line description of the current device into buf. */
+int bd_device_info(char* buf, size_t len);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PROBEWALK_H */

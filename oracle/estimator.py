@@ -42,6 +42,10 @@ def lib():
         L.pwo_replicas.restype = None
         L.pwo_q_from_u.argtypes = [ctypes.c_int64, _P]
         L.pwo_q_from_u.restype = ctypes.c_double
+        L.pwo_probe_q.argtypes = [ctypes.c_uint32, _P, _P, ctypes.c_int32, ctypes.c_int32,
+                                  ctypes.c_int32, ctypes.c_uint32, ctypes.c_int64, ctypes.c_uint64,
+                                  ctypes.c_int64, _P, ctypes.c_int, _P]
+        L.pwo_probe_q.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -129,3 +133,14 @@ def estimate(g, s, t, L, plans, seed: int, uid=None, threads: int = 1,
     if want_q:
         return beta, q0, y0
     return beta
+
+
+def probe_q(g, s: int, t: int, L: int, uid: int, R: int, seed: int, ks, threads: int = 1):
+    """Q_R(z^(k)) for each probe index in ``ks`` (threads over probes)."""
+    ks = np.ascontiguousarray(ks, dtype=np.uint32)
+    out = np.zeros(ks.size, dtype=np.float64)
+    rp = np.ascontiguousarray(g.row_ptr, dtype=np.int64)
+    col = np.ascontiguousarray(g.col, dtype=np.int32)
+    lib().pwo_probe_q(g.n, _ptr(rp), _ptr(col), s, t, L, uid, R, seed, ks.size, _ptr(ks), threads,
+                      _ptr(out))
+    return out

@@ -439,3 +439,63 @@ double pwo_q_from_u(int64_t R, const float* U)
     }
     return probe_q(S1, S2, R);
 }
+
+/* ------------------------------------------------------------------------ */
+/* Q_k for a list of probes (sampled checks at full size), threads over k    */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    const graph_t* g;
+    uint64_t seed;
+    int32_t s, t, L;
+    uint32_t uid;
+    int64_t R;
+    const uint32_t* ks;
+    double* q;
+    int64_t count;
+    int64_t next;
+    pthread_mutex_t mu;
+} qpool_t;
+
+static void* q_worker(void* arg)
+{
+    qpool_t* pl = (qpool_t*)arg;
+    domain_t d = make_domain(pl->g->n);
+    for (;;) {
+        pthread_mutex_lock(&pl->mu);
+        int64_t i = pl->next++;
+        pthread_mutex_unlock(&pl->mu);
+        if (i >= pl->count) break;
+        uint32_t k = pl->ks[i];
+        probe_t pr;
+        make_probe(pl->seed, pl->uid, k, pl->g->n, &pr);
+        i128 S1 = 0;
+        u128 S2 = 0;
+        for (int64_t p = 0; p < pl->R; p++) {
+            float a = walk_sum(pl->g, &d, &pr, (uint32_t)pl->s, pl->L, pl->seed, pl->uid, k, (uint32_t)p, 0u, NULL);
+            float b = walk_sum(pl->g, &d, &pr, (uint32_t)pl->t, pl->L, pl->seed, pl->uid, k, (uint32_t)p, 1u, NULL);
+            float U = a - b;
+            S1 += fix54(U);
+            S2 += sqfix64(U);
+        }
+        pl->q[i] = probe_q(S1, S2, pl->R);
+    }
+    return NULL;
+}
+
+int pwo_probe_q(uint32_t n, const int64_t* row_ptr, const int32_t* col, int32_t s, int32_t t,
+                int32_t L, uint32_t uid, int64_t R, uint64_t seed, int64_t count,
+                const uint32_t* ks, int nthreads, double* q_out)
+{
+    graph_t g = {n, row_ptr, col, NULL};
+    g.inv = (float*)malloc(sizeof(float) * n);
+    for (uint32_t v = 0; v < n; v++) g.inv[v] = 1.0f / (float)(row_ptr[v + 1] - row_ptr[v]);
+    qpool_t pl = {&g, seed, s, t, L, uid, R, ks, q_out, count, 0, PTHREAD_MUTEX_INITIALIZER};
+    if (nthreads < 1) nthreads = 1;
+    if (nthreads > count) nthreads = (int)(count > 0 ? count : 1);
+    pthread_t* th = (pthread_t*)malloc(sizeof(pthread_t) * (size_t)nthreads);
+    for (int i = 0; i < nthreads; i++) pthread_create(&th[i], NULL, q_worker, &pl);
+    for (int i = 0; i < nthreads; i++) pthread_join(th[i], NULL);
+    free(th);
+    free(g.inv);
+    return 0;
+}

@@ -1,0 +1,352 @@
+"""ctypes binding of ``include/probewalk.h``: argument marshalling only.
+
+Every function here has the name of the C entry point it calls and does
+nothing but convert numpy arrays / torch streams into pointers and back; all
+of the estimator runs in the HIP library. Streams come from PyTorch
+(``torch.cuda.current_stream()`` by default).
+
+The library must have been built (``python -m paper_2512_05460_amd.build``);
+there is no fallback of any kind when it is missing.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libprobewalk.so")
+
+BD_OK = 0
+BD_E_INVALID = -1
+BD_E_GRAPH = -2
+BD_E_RANGE = -3
+BD_E_BUDGET = -4
+BD_E_HIP = -5
+BD_E_NOMEM = -6
+BD_E_NODEVICE = -7
+BD_E_NOTFOUND = -8
+BD_E_FULL = -9
+BD_E_CANCELLED = -10
+BD_E_TIMEOUT = -11
+
+BD_LAYOUT_CSR = 0
+BD_LAYOUT_FAT = 1
+BD_SKIP_VALIDATION = 2
+
+BD_POLICY_PAPER = 0
+BD_POLICY_SCALED = 1
+BD_POLICY_FIXED = 2
+
+BD_MODE_PLAIN = 0
+BD_MODE_BATCHED = 1
+
+# Symbols declared in include/probewalk.h.
+EXPORTS = ("graph_load_csr", "graph_free", "bd_graph_get_info", "bd_plan", "bd_query_batch",
+           "bd_walk_trace", "bd_probe_eval", "bd_query_probes", "bd_server_create",
+           "bd_server_submit", "bd_server_poll", "bd_server_wait", "bd_server_destroy",
+           "bd_strerror", "bd_device_info")
+
+
+class BdPolicy(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("c_B", ctypes.c_double), ("c_R", ctypes.c_double),
+                ("delta", ctypes.c_double), ("B_fixed", ctypes.c_int64), ("R_fixed", ctypes.c_int64),
+                ("max_steps_per_query", ctypes.c_uint64)]
+
+
+class BdExec(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_uint32), ("chunk_probes", ctypes.c_int32),
+                ("grid_wgs", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
+
+
+class BdStats(ctypes.Structure):
+    _fields_ = [("walk_kernel_ms", ctypes.c_double), ("total_ms", ctypes.c_double),
+                ("launches", ctypes.c_int64), ("chunks", ctypes.c_int64),
+                ("walk_steps", ctypes.c_int64), ("walk_pairs", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class BdGraphInfo(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("d_min", ctypes.c_int32),
+                ("d_max", ctypes.c_int32), ("bipartite", ctypes.c_int32), ("layout", ctypes.c_int32),
+                ("device_bytes", ctypes.c_int64)]
+
+
+class BdServerCfg(ctypes.Structure):
+    _fields_ = [("policy", BdPolicy), ("max_queries_inflight", ctypes.c_int64),
+                ("max_steps_inflight", ctypes.c_uint64), ("chunk_probes", ctypes.c_int32),
+                ("slice_ms", ctypes.c_double)]
+
+
+RESULT_DTYPE = np.dtype([("beta", "f8"), ("K", "i8"), ("R", "i8"), ("B", "i4"), ("G", "i4"),
+                         ("L", "i4"), ("status", "i4"), ("walk_steps", "i8")], align=True)
+assert RESULT_DTYPE.itemsize == 48
+
+_lib = None
+_P = ctypes.c_void_p
+
+
+class ProbeWalkError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        super().__init__(f"{where}: {strerror(code)} ({code})")
+
+
+def lib():
+    """Load libprobewalk.so; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_2512_05460_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        i32, i64, u32, u64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64
+        sig = {
+            "graph_load_csr": (ctypes.c_int, [i64, _P, _P, u32, _P, ctypes.POINTER(_P)]),
+            "graph_free": (None, [_P]),
+            "bd_graph_get_info": (ctypes.c_int, [_P, ctypes.POINTER(BdGraphInfo)]),
+            "bd_plan": (ctypes.c_int, [_P, i64, _P, _P, _P, _P, ctypes.POINTER(BdPolicy), _P]),
+            "bd_query_batch": (ctypes.c_int, [_P, i64, _P, _P, _P, _P, _P, u64, ctypes.POINTER(BdPolicy),
+                                              ctypes.POINTER(BdExec), _P, _P, ctypes.POINTER(BdStats)]),
+            "bd_walk_trace": (ctypes.c_int, [_P, i64, _P, _P, _P, _P, _P, i32, u64, _P, _P, _P]),
+            "bd_probe_eval": (ctypes.c_int, [_P, u64, u32, u32, i64, _P, _P, _P, _P]),
+            "bd_query_probes": (ctypes.c_int, [_P, i32, i32, ctypes.c_double, i32, u32, u64,
+                                               ctypes.POINTER(BdPolicy), ctypes.POINTER(BdExec), _P,
+                                               _P, _P, _P]),
+            "bd_server_create": (ctypes.c_int, [_P, ctypes.POINTER(BdServerCfg), ctypes.POINTER(_P)]),
+            "bd_server_submit": (ctypes.c_int, [_P, i64, _P, _P, _P, _P, _P, u64, ctypes.POINTER(u64)]),
+            "bd_server_poll": (ctypes.c_int, [_P, u64, _P, ctypes.POINTER(ctypes.c_int),
+                                              ctypes.POINTER(ctypes.c_double)]),
+            "bd_server_wait": (ctypes.c_int, [_P, u64, ctypes.c_double, _P, ctypes.POINTER(ctypes.c_double)]),
+            "bd_server_destroy": (None, [_P]),
+            "bd_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+            "bd_device_info": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_size_t]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def strerror(code: int) -> str:
+    return lib().bd_strerror(code).decode()
+
+
+def _check(rc: int, where: str):
+    if rc != BD_OK:
+        raise ProbeWalkError(rc, where)
+
+
+def _arr(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(_P)
+
+
+def _stream(stream):
+    """hipStream_t handle: an int, a torch stream, or torch's current stream."""
+    if stream is None:
+        import torch
+        if torch.cuda.is_available():
+            return torch.cuda.current_stream().cuda_stream
+        return None
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def policy(kind="paper", c_B=448.0, c_R=128.0, delta=0.01, B=0, R=0, max_steps=0) -> BdPolicy:
+    k = {"paper": BD_POLICY_PAPER, "scaled": BD_POLICY_SCALED, "fixed": BD_POLICY_FIXED}[kind]
+    return BdPolicy(k, c_B, c_R, delta, B, R, max_steps)
+
+
+def exec_cfg(mode="batched", chunk_probes=0, grid_wgs=0, use_graph=False) -> BdExec:
+    m = {"plain": BD_MODE_PLAIN, "batched": BD_MODE_BATCHED}[mode]
+    return BdExec(m, chunk_probes, grid_wgs, 1 if use_graph else 0)
+
+
+class Graph:
+    """Owning wrapper of a ``bd_graph*`` handle."""
+
+    def __init__(self, handle):
+        self._h = handle
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise ValueError("graph was freed")
+        return self._h
+
+    def info(self) -> dict:
+        return bd_graph_get_info(self)
+
+    def free(self):
+        if self._h is not None:
+            lib().graph_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def graph_load_csr(n: int, row_ptr, col_idx, flags: int = BD_LAYOUT_CSR, stream=None) -> Graph:
+    rp = _arr(row_ptr, np.int64)
+    col = _arr(col_idx, np.int32)
+    if rp.size != n + 1:
+        raise ValueError("row_ptr must have n+1 entries")
+    h = _P()
+    _check(lib().graph_load_csr(n, _ptr(rp), _ptr(col), flags, _stream(stream), ctypes.byref(h)),
+           "graph_load_csr")
+    return Graph(h)
+
+
+def graph_free(g: Graph):
+    g.free()
+
+
+def bd_graph_get_info(g: Graph) -> dict:
+    info = BdGraphInfo()
+    _check(lib().bd_graph_get_info(g.handle, ctypes.byref(info)), "bd_graph_get_info")
+    return {f: getattr(info, f) for f, _ in info._fields_}
+
+
+def bd_plan(g: Graph, s, t, eps, L, pol: BdPolicy | None = None) -> np.ndarray:
+    s, t = _arr(s, np.int32), _arr(t, np.int32)
+    eps = _arr(np.broadcast_to(eps, s.shape), np.float64)
+    L = _arr(np.broadcast_to(L, s.shape), np.int32)
+    out = np.zeros(s.size, dtype=RESULT_DTYPE)
+    _check(lib().bd_plan(g.handle, s.size, _ptr(s), _ptr(t), _ptr(eps), _ptr(L),
+                         None if pol is None else ctypes.byref(pol), _ptr(out)), "bd_plan")
+    return out
+
+
+def bd_query_batch(g: Graph, s, t, eps, L, seed: int, pol: BdPolicy | None = None,
+                   ex: BdExec | None = None, uid=None, stream=None, with_stats: bool = False):
+    s, t = _arr(s, np.int32), _arr(t, np.int32)
+    eps = _arr(np.broadcast_to(eps, s.shape), np.float64)
+    L = _arr(np.broadcast_to(L, s.shape), np.int32)
+    u = None if uid is None else _arr(uid, np.uint32)
+    out = np.zeros(s.size, dtype=RESULT_DTYPE)
+    st = BdStats()
+    _check(lib().bd_query_batch(g.handle, s.size, _ptr(s), _ptr(t), _ptr(eps), _ptr(L), _ptr(u),
+                                seed & (2 ** 64 - 1), None if pol is None else ctypes.byref(pol),
+                                None if ex is None else ctypes.byref(ex), _stream(stream), _ptr(out),
+                                ctypes.byref(st)), "bd_query_batch")
+    return (out, st.as_dict()) if with_stats else out
+
+
+def bd_query_probes(g: Graph, s: int, t: int, eps: float, L: int, uid: int, seed: int,
+                    pol: BdPolicy | None = None, ex: BdExec | None = None, stream=None):
+    """Returns (result, Q per probe, block means)."""
+    plan = bd_plan(g, [s], [t], [eps], [L], pol)[0]
+    if plan["status"] != BD_OK:
+        raise ProbeWalkError(int(plan["status"]), "bd_query_probes")
+    q = np.zeros(int(plan["K"]), dtype=np.float64)
+    y = np.zeros(int(plan["G"]), dtype=np.float64)
+    out = np.zeros(1, dtype=RESULT_DTYPE)
+    _check(lib().bd_query_probes(g.handle, s, t, eps, L, uid, seed & (2 ** 64 - 1),
+                                 None if pol is None else ctypes.byref(pol),
+                                 None if ex is None else ctypes.byref(ex), _stream(stream),
+                                 _ptr(q), _ptr(y), _ptr(out)), "bd_query_probes")
+    return out[0], q, y
+
+
+def bd_walk_trace(g: Graph, start, uid, k, p, side, L: int, seed: int, stream=None):
+    start = _arr(start, np.int32)
+    n = start.size
+    uid = _arr(np.broadcast_to(uid, (n,)), np.uint32)
+    k = _arr(np.broadcast_to(k, (n,)), np.uint32)
+    p = _arr(np.broadcast_to(p, (n,)), np.uint32)
+    side = _arr(np.broadcast_to(side, (n,)), np.uint32)
+    trace = np.zeros((n, L + 1), dtype=np.int32)
+    acc = np.zeros(n, dtype=np.float32)
+    _check(lib().bd_walk_trace(g.handle, n, _ptr(start), _ptr(uid), _ptr(k), _ptr(p), _ptr(side), L,
+                               seed & (2 ** 64 - 1), _stream(stream), _ptr(trace), _ptr(acc)),
+           "bd_walk_trace")
+    return trace, acc
+
+
+def bd_probe_eval(g: Graph, seed: int, uid: int, k: int, nodes, stream=None):
+    nodes = _arr(nodes, np.uint32)
+    pi = np.zeros(nodes.size, dtype=np.uint32)
+    z = np.zeros(nodes.size, dtype=np.int8)
+    _check(lib().bd_probe_eval(g.handle, seed & (2 ** 64 - 1), uid, k, nodes.size, _ptr(nodes),
+                               _stream(stream), _ptr(pi), _ptr(z)), "bd_probe_eval")
+    return pi, z
+
+
+class Server:
+    """Owning wrapper of a ``bd_server*`` (served mode, continuous batching)."""
+
+    def __init__(self, g: Graph, pol: BdPolicy, max_queries: int = 0, max_steps: int = 0,
+                 chunk_probes: int = 0, slice_ms: float = 0.0):
+        self.graph = g  # the graph must outlive the server
+        cfg = BdServerCfg(pol, max_queries, max_steps, chunk_probes, slice_ms)
+        h = _P()
+        _check(lib().bd_server_create(g.handle, ctypes.byref(cfg), ctypes.byref(h)), "bd_server_create")
+        self._h = h
+        self._sizes = {}
+
+    def submit(self, s, t, eps, L, seed: int, uid=None) -> int:
+        s, t = _arr(s, np.int32), _arr(t, np.int32)
+        eps = _arr(np.broadcast_to(eps, s.shape), np.float64)
+        L = _arr(np.broadcast_to(L, s.shape), np.int32)
+        u = None if uid is None else _arr(uid, np.uint32)
+        rid = ctypes.c_uint64()
+        _check(lib().bd_server_submit(self._h, s.size, _ptr(s), _ptr(t), _ptr(eps), _ptr(L), _ptr(u),
+                                      seed & (2 ** 64 - 1), ctypes.byref(rid)), "bd_server_submit")
+        self._sizes[rid.value] = s.size
+        return rid.value
+
+    def poll(self, rid: int):
+        """(done, results or None, latency_ms or None)."""
+        out = np.zeros(self._sizes[rid], dtype=RESULT_DTYPE)
+        done = ctypes.c_int()
+        lat = ctypes.c_double()
+        _check(lib().bd_server_poll(self._h, rid, _ptr(out), ctypes.byref(done), ctypes.byref(lat)),
+               "bd_server_poll")
+        if done.value:
+            del self._sizes[rid]
+            return True, out, lat.value
+        return False, None, None
+
+    def wait(self, rid: int, timeout_ms: float = 0.0):
+        out = np.zeros(self._sizes[rid], dtype=RESULT_DTYPE)
+        lat = ctypes.c_double()
+        _check(lib().bd_server_wait(self._h, rid, timeout_ms, _ptr(out), ctypes.byref(lat)),
+               "bd_server_wait")
+        del self._sizes[rid]
+        return out, lat.value
+
+    def destroy(self):
+        if self._h is not None:
+            lib().bd_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def bd_server_create(g: Graph, pol: BdPolicy, **kw) -> Server:
+    return Server(g, pol, **kw)
+
+
+def bd_device_info() -> str:
+    buf = ctypes.create_string_buffer(512)
+    rc = lib().bd_device_info(buf, 512)
+    _check(rc, "bd_device_info")
+    return buf.value.decode()

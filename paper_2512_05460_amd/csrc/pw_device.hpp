@@ -1,0 +1,298 @@
+// Device-side building blocks of the ProbeWalk hot path for gfx950.
+//
+//   * Philox4x32-10 counter-based generator (Salmon, Moraes, Dror, Shaw, SC'11).
+//   * The stateless Paired-Sign Probe of section 3.3: a keyed permutation pi_k
+//     of [n] (alternating Feistel network on Z_A x Z_{2^rb}, cycle walking),
+//     the parity zero set, and base signs from the 2-universal hash
+//     h_k(u) = ((a_k u + b_k) mod (2^31-1)) mod 2.
+//   * One walk transition (Algorithm 1 walk loop) for the two adjacency layouts.
+//   * Exact fixed-point sums for the U-statistic (Algorithm 1 S1, S2, Q_R):
+//     every per-replica difference U is an integer multiple of 2^-54, so S1 is
+//     held as the 128-bit integer S1*2^54, S2 as sum floor(U^2 2^64), and
+//     block sums of Q as sum trunc(Q 2^64). Summation order never matters.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pw {
+
+typedef __int128 i128;
+typedef unsigned __int128 u128;
+
+constexpr uint32_t kHashP = 2147483647u;  // 2^31 - 1
+constexpr uint32_t kProbeCtr = 0xFFFFFFFFu;  // counter word reserved for probe keys
+constexpr int kFeistelRounds = 6;
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10
+// ---------------------------------------------------------------------------
+struct U4 {
+    uint32_t x, y, z, w;
+};
+
+__device__ __forceinline__ U4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                       uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)p1;
+        c3 = (uint32_t)p0;
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return U4{c0, c1, c2, c3};
+}
+
+// ---------------------------------------------------------------------------
+// Probe domain (per graph) and probe keys (per query and probe index k)
+// ---------------------------------------------------------------------------
+struct Domain {
+    uint32_t n;     // nodes
+    uint32_t rb;    // bits of the XOR half
+    uint32_t mask;  // 2^rb - 1
+    uint32_t rsh;   // 32 - rb (31 when rb == 0; the mask then clears the result)
+    uint32_t A;     // modulus of the additive half, A = ceil(n / 2^rb)
+    uint32_t A8;    // A << 8
+};
+
+struct Probe {
+    uint32_t K[kFeistelRounds];
+    uint32_t a, b;
+    uint32_t zlo;   // first zero position: pi_k(i) >= zlo  <=>  z_i = 0  (zlo = n - r)
+};
+
+__device__ __forceinline__ Probe make_probe(uint32_t seed_lo, uint32_t seed_hi, uint32_t uid,
+                                            uint32_t k, uint32_t n)
+{
+    Probe pr;
+    const U4 w0 = philox10(0u, kProbeCtr, k, uid << 1, seed_lo, seed_hi);
+    const U4 w1 = philox10(1u, kProbeCtr, k, uid << 1, seed_lo, seed_hi);
+    const U4 w2 = philox10(2u, kProbeCtr, k, uid << 1, seed_lo, seed_hi);
+    pr.K[0] = w0.x;
+    pr.K[1] = w0.y;
+    pr.K[2] = w0.z;
+    pr.K[3] = w0.w;
+    pr.K[4] = w1.x;
+    pr.K[5] = w1.y;
+    pr.a = 1u + w1.z % (kHashP - 1u);
+    pr.b = w1.w % kHashP;
+    const uint32_t r = (n & 1u) ? 1u : 2u * (w2.x & 1u);
+    pr.zlo = n - r;
+    return pr;
+}
+
+__device__ __forceinline__ uint32_t umul24(uint32_t a, uint32_t b)
+{
+    return (uint32_t)((uint64_t)(a & 0xFFFFFFu) * (uint64_t)(b & 0xFFFFFFu));
+}
+
+__device__ __forceinline__ uint32_t umul24hi(uint32_t a, uint32_t b)
+{
+    return (uint32_t)(((uint64_t)(a & 0xFFFFFFu) * (uint64_t)(b & 0xFFFFFFu)) >> 32);
+}
+
+__device__ __forceinline__ uint32_t fmix(uint32_t v, uint32_t key)
+{
+    uint32_t h = umul24(v ^ key, 0x9E3779u);
+    h ^= h >> 15;
+    return umul24(h, 0x873593u);
+}
+
+// pi_k(x): Feistel rounds alternate L <- (L + F(R)) mod A and R <- R ^ top_rb(F(L));
+// values that land in [n, A*2^rb) are walked again until they fall in [n].
+__device__ __forceinline__ uint32_t feistel_pi(uint32_t x, const Probe& pr, const Domain& dm)
+{
+    do {
+        uint32_t L = x >> dm.rb;
+        uint32_t R = x & dm.mask;
+#pragma unroll
+        for (int r = 0; r < kFeistelRounds; r += 2) {
+            const uint32_t f = umul24hi(fmix(R, pr.K[r]) >> 8, dm.A8);
+            const uint32_t t = L + f;
+            L = min(t, t - dm.A);  // (L + f) mod A, since L + f < 2A
+            R ^= (fmix(L, pr.K[r + 1]) >> dm.rsh) & dm.mask;
+        }
+        x = (L << dm.rb) | R;
+    } while (x >= dm.n);
+    return x;
+}
+
+// ((a u + b) mod (2^31 - 1)) & 1 for u < 2^30, a, b < 2^31
+__device__ __forceinline__ uint32_t hash_bit(const Probe& pr, uint32_t u)
+{
+    const uint64_t v = (uint64_t)pr.a * u + pr.b;  // < 2^62
+    uint32_t t = ((uint32_t)v & kHashP) + (uint32_t)(v >> 31);
+    t = (t & kHashP) + (t >> 31);
+    t = min(t, t - kHashP);
+    return t & 1u;
+}
+
+// acc + z^(k)_x * inv, skipping the term when z = 0
+__device__ __forceinline__ float add_term(float acc, uint32_t x, float inv, const Probe& pr,
+                                          const Domain& dm)
+{
+    const uint32_t y = feistel_pi(x, pr, dm);
+    const uint32_t neg = hash_bit(pr, y >> 1) ^ (y & 1u);
+    const float v = neg ? -inv : inv;
+    const float s = __fadd_rn(acc, v);
+    return (y >= pr.zlo) ? acc : s;
+}
+
+__device__ __forceinline__ int probe_value(uint32_t x, const Probe& pr, const Domain& dm,
+                                           uint32_t* pi_out)
+{
+    const uint32_t y = feistel_pi(x, pr, dm);
+    *pi_out = y;
+    if (y >= pr.zlo) return 0;
+    return (hash_bit(pr, y >> 1) ^ (y & 1u)) ? -1 : 1;
+}
+
+// ---------------------------------------------------------------------------
+// Graph tables and one walk transition
+// ---------------------------------------------------------------------------
+// Node table entry: {row offset, degree, bits of 1.0f/degree, 0}.
+// Fat adjacency entry at position row_ptr[x] + j:
+//   {neighbour id, its row offset, its degree, bits of its 1.0f/degree}.
+struct DevGraph {
+    const uint4* node;    // n entries
+    const uint32_t* col;  // nnz entries (CSR layout)
+    const uint4* adj;     // nnz entries (fat layout) or null
+    Domain dom;
+};
+
+struct WalkState {
+    uint32_t x, off, deg;
+    float inv;
+};
+
+__device__ __forceinline__ WalkState start_state(uint32_t x, uint4 e)
+{
+    return WalkState{x, e.x, e.y, __uint_as_float(e.z)};
+}
+
+// Uniform neighbour: j = floor(u * d / 2^32) into the ascending neighbour list.
+template <int kFat>
+__device__ __forceinline__ void step(WalkState& w, uint32_t u, const DevGraph& G)
+{
+    const uint32_t j = __umulhi(u, w.deg);
+    const uint32_t pos = w.off + j;
+    if (kFat) {
+        const uint4 e = G.adj[pos];
+        w.x = e.x;
+        w.off = e.y;
+        w.deg = e.z;
+        w.inv = __uint_as_float(e.w);
+    } else {
+        const uint32_t x = G.col[pos];
+        const uint4 e = G.node[x];
+        w.x = x;
+        w.off = e.x;
+        w.deg = e.y;
+        w.inv = __uint_as_float(e.z);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Exact fixed-point helpers
+// ---------------------------------------------------------------------------
+// U * 2^54 (exact: U is a multiple of 2^-54 with |U| < 2^15)
+__device__ __forceinline__ i128 fix54(float U)
+{
+    const uint32_t b = __float_as_uint(U);
+    const int e = (int)((b >> 23) & 0xFFu);
+    if (e == 0) return 0;
+    const uint64_t M = (uint64_t)((b & 0x7FFFFFu) | 0x800000u);
+    const int sh = e - 96;  // (e - 127 - 23) + 54
+    u128 mag;
+    if (sh >= 0) mag = (u128)M << sh;
+    else mag = (sh > -32) ? (u128)(M >> (-sh)) : (u128)0;
+    return (b >> 31) ? -(i128)mag : (i128)mag;
+}
+
+// floor(U^2 * 2^64)
+__device__ __forceinline__ u128 sqfix64(float U)
+{
+    const uint32_t b = __float_as_uint(U);
+    const int e = (int)((b >> 23) & 0xFFu);
+    if (e == 0) return 0;
+    const uint64_t M = (uint64_t)((b & 0x7FFFFFu) | 0x800000u);
+    const uint64_t M2 = M * M;  // < 2^48
+    const int sh = 2 * e - 236;  // 2 (e - 150) + 64
+    if (sh >= 0) return (u128)M2 << sh;
+    if (sh > -64) return (u128)(M2 >> (-sh));
+    return 0;
+}
+
+// Correctly rounded (round-to-nearest-even) conversions of 128-bit integers to
+// binary64: normalise, keep the top 64 bits with a sticky bit in bit 0, and let
+// the exact two-part u64 -> f64 conversion round once.
+__device__ __forceinline__ double u128_to_f64(u128 m)
+{
+    const uint64_t hi = (uint64_t)(m >> 64);
+    const uint64_t lo = (uint64_t)m;
+    if (hi == 0) {
+        // u64 -> f64: hi32 * 2^32 + lo32 is a single rounding of exact parts
+        const double h = (double)(uint32_t)(lo >> 32) * 4294967296.0;
+        return h + (double)(uint32_t)lo;
+    }
+    const int lz = __clzll(hi);
+    const u128 n = m << lz;  // MSB at bit 127
+    uint64_t top = (uint64_t)(n >> 64);
+    top |= ((uint64_t)n != 0) ? 1ull : 0ull;
+    const double h = (double)(uint32_t)(top >> 32) * 4294967296.0;
+    const double t = h + (double)(uint32_t)top;
+    return ldexp(t, 64 - lz);
+}
+
+__device__ __forceinline__ double i128_to_f64(i128 v)
+{
+    return v < 0 ? -u128_to_f64((u128)(-v)) : u128_to_f64((u128)v);
+}
+
+// trunc(d) for |d| < 2^126 as a 128-bit integer
+__device__ __forceinline__ i128 f64_to_i128_trunc(double d)
+{
+    const double m = fabs(trunc(d));
+    const double hi = floor(m * 0x1p-64);
+    const double lo = m - hi * 0x1p64;
+    const u128 mag = ((u128)(uint64_t)hi << 64) | (u128)(uint64_t)lo;
+    return d < 0 ? -(i128)mag : (i128)mag;
+}
+
+// Q = (s1^2 - s2) / (R (R - 1)) with s1 = S1 2^-54, s2 = S2 2^-64
+__device__ __forceinline__ double probe_q(i128 S1, u128 S2, uint32_t R)
+{
+    const double s1 = i128_to_f64(S1) * 0x1p-54;
+    const double s2 = u128_to_f64(S2) * 0x1p-64;
+    const double num = __dsub_rn(__dmul_rn(s1, s1), s2);
+    const double den = __dmul_rn((double)R, (double)(R - 1u));
+    return __ddiv_rn(num, den);
+}
+
+// 128-bit atomic add as two 64-bit atomics with an explicit carry: the low
+// word's returned old value tells whether this addition wrapped, so the
+// high word receives exactly the carries of all additions.
+__device__ __forceinline__ void atomic_add_i128(unsigned long long* p, i128 v)
+{
+    const unsigned long long lo = (unsigned long long)(u128)v;
+    const unsigned long long hi = (unsigned long long)((u128)v >> 64);
+    const unsigned long long old = atomicAdd(p, lo);
+    const unsigned long long carry = (old + lo < old) ? 1ull : 0ull;
+    atomicAdd(p + 1, hi + carry);
+}
+
+__device__ __forceinline__ i128 load_i128(const unsigned long long* p)
+{
+    const unsigned long long lo = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned long long hi = __hip_atomic_load(p + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return (i128)(((u128)hi << 64) | (u128)lo);
+}
+
+}  // namespace pw

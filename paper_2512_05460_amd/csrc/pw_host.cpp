@@ -1,0 +1,1147 @@
+// Host runtime and C ABI of the ProbeWalk library: graph loading and
+// validation, the walk-count planner (Algorithm 1 parameters), the plain and
+// batched launchers, validation entry points and the served mode.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstdio>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <vector>
+
+#include "../../include/probewalk.h"
+#include "pw_internal.hpp"
+
+using namespace pw;
+
+namespace {
+
+constexpr int64_t kMaxN = int64_t(1) << 30;
+constexpr int64_t kMaxNnz = (int64_t(1) << 31) - 1;
+constexpr int32_t kMaxDeg = (1 << 24) - 1;
+constexpr int32_t kMaxL = 16383;
+
+#define HIP_TRY(expr)                                  \
+    do {                                               \
+        hipError_t e_ = (expr);                        \
+        if (e_ != hipSuccess) return BD_E_HIP;         \
+    } while (0)
+
+// Device allocation owned by the library.
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    ~DevBuf() { release(); }
+    void release()
+    {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    int alloc(size_t b)
+    {
+        release();
+        if (b == 0) b = 16;
+        if (hipMalloc(&p, b) != hipSuccess) {
+            p = nullptr;
+            (void)hipGetLastError();
+            return BD_E_NOMEM;
+        }
+        bytes = b;
+        return BD_OK;
+    }
+    template <class T>
+    T* as() const { return static_cast<T*>(p); }
+};
+
+double now_ms()
+{
+    using namespace std::chrono;
+    return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+}  // namespace
+
+struct bd_graph {
+    int64_t n = 0, nnz = 0;
+    int32_t d_min = 0, d_max = 0;
+    int32_t bipartite = 0;
+    int32_t layout = 0;
+    int device = 0;
+    std::vector<int32_t> deg;  // host copy for the planner
+    DevBuf node, col, adj;
+    DomainParams dom{};
+    int64_t device_bytes = 0;
+    std::mutex mu;  // serialises calls that use the per-graph work buffers
+};
+
+// ---------------------------------------------------------------------------
+// Graph loading
+// ---------------------------------------------------------------------------
+namespace {
+
+DomainParams make_domain(uint32_t n)
+{
+    DomainParams d{};
+    uint32_t w = 0;
+    while ((uint64_t(1) << w) < n) ++w;
+    d.n = n;
+    d.rb = w >> 1;
+    d.mask = (1u << d.rb) - 1u;
+    d.rsh = d.rb ? 32u - d.rb : 31u;
+    d.A = (uint32_t)((uint64_t(n) + d.mask) >> d.rb);
+    d.A8 = d.A << 8;
+    return d;
+}
+
+// Checks run on the host, in parallel over node ranges.
+int validate(int64_t n, const int64_t* rp, const int32_t* col, int32_t* bip)
+{
+    const unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    std::atomic<int> bad{0};
+    auto worker = [&](int64_t lo, int64_t hi) {
+        for (int64_t v = lo; v < hi && !bad.load(std::memory_order_relaxed); ++v) {
+            const int64_t b = rp[v], e = rp[v + 1];
+            for (int64_t i = b; i < e; ++i) {
+                const int32_t u = col[i];
+                if (u == v || (i > b && col[i - 1] >= u)) {
+                    bad = 1;
+                    break;
+                }
+                // symmetry: v must appear in row u
+                const int32_t* rb = col + rp[u];
+                const int32_t* re = col + rp[u + 1];
+                if (!std::binary_search(rb, re, (int32_t)v)) {
+                    bad = 1;
+                    break;
+                }
+            }
+        }
+    };
+    std::vector<std::thread> th;
+    const int64_t per = (n + nt - 1) / nt;
+    for (unsigned i = 0; i < nt; ++i) {
+        const int64_t lo = i * per, hi = std::min<int64_t>(n, lo + per);
+        if (lo < hi) th.emplace_back(worker, lo, hi);
+    }
+    for (auto& t : th) t.join();
+    if (bad) return BD_E_GRAPH;
+    // connectivity and bipartiteness by one BFS with 2-colouring
+    std::vector<int8_t> colour((size_t)n, -1);
+    std::vector<int32_t> queue((size_t)n);
+    size_t head = 0, tail = 0;
+    colour[0] = 0;
+    queue[tail++] = 0;
+    int32_t bipartite = 1;
+    while (head < tail) {
+        const int32_t v = queue[head++];
+        for (int64_t i = rp[v]; i < rp[v + 1]; ++i) {
+            const int32_t u = col[i];
+            if (colour[u] < 0) {
+                colour[u] = (int8_t)(1 - colour[v]);
+                queue[tail++] = u;
+            } else if (colour[u] == colour[v]) {
+                bipartite = 0;
+            }
+        }
+    }
+    if ((int64_t)tail != n) return BD_E_GRAPH;
+    *bip = bipartite;
+    return BD_OK;
+}
+
+}  // namespace
+
+extern "C" int graph_load_csr(int64_t n, const int64_t* row_ptr, const int32_t* col_idx,
+                              uint32_t flags, void* stream, bd_graph** out)
+{
+    if (!out || !row_ptr || !col_idx) return BD_E_INVALID;
+    *out = nullptr;
+    if (n < 2 || n > kMaxN) return BD_E_RANGE;
+    if (row_ptr[0] != 0) return BD_E_GRAPH;
+    const int64_t nnz = row_ptr[n];
+    if (nnz < 0 || nnz > kMaxNnz) return BD_E_RANGE;
+    int32_t dmin = INT32_MAX, dmax = 0;
+    for (int64_t v = 0; v < n; ++v) {
+        const int64_t d = row_ptr[v + 1] - row_ptr[v];
+        if (d < 0) return BD_E_GRAPH;
+        if (d > kMaxDeg) return BD_E_RANGE;
+        dmin = std::min<int32_t>(dmin, (int32_t)d);
+        dmax = std::max<int32_t>(dmax, (int32_t)d);
+    }
+    if (dmin < 1) return BD_E_GRAPH;  // an isolated node: not connected
+    for (int64_t i = 0; i < nnz; ++i)
+        if (col_idx[i] < 0 || col_idx[i] >= n) return BD_E_GRAPH;
+    int32_t bip = 0;
+    if (!(flags & BD_SKIP_VALIDATION)) {
+        const int rc = validate(n, row_ptr, col_idx, &bip);
+        if (rc != BD_OK) return rc;
+    }
+    int dev = 0, ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
+        (void)hipGetLastError();
+        return BD_E_NODEVICE;
+    }
+    HIP_TRY(hipGetDevice(&dev));
+
+    bd_graph* g = new (std::nothrow) bd_graph();
+    if (!g) return BD_E_NOMEM;
+    g->n = n;
+    g->nnz = nnz;
+    g->d_min = dmin;
+    g->d_max = dmax;
+    g->bipartite = bip;
+    g->layout = (flags & BD_LAYOUT_FAT) ? BD_LAYOUT_FAT : BD_LAYOUT_CSR;
+    g->device = dev;
+    g->dom = make_domain((uint32_t)n);
+    g->deg.resize((size_t)n);
+    std::vector<uint32_t> nodetab((size_t)n * 4);
+    for (int64_t v = 0; v < n; ++v) {
+        const int32_t d = (int32_t)(row_ptr[v + 1] - row_ptr[v]);
+        g->deg[(size_t)v] = d;
+        const float inv = 1.0f / (float)d;
+        uint32_t bits;
+        std::memcpy(&bits, &inv, 4);
+        nodetab[(size_t)v * 4 + 0] = (uint32_t)row_ptr[v];
+        nodetab[(size_t)v * 4 + 1] = (uint32_t)d;
+        nodetab[(size_t)v * 4 + 2] = bits;
+        nodetab[(size_t)v * 4 + 3] = 0u;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    int rc = g->node.alloc((size_t)n * 16);
+    if (rc == BD_OK) rc = g->col.alloc((size_t)std::max<int64_t>(nnz, 1) * 4);
+    if (rc == BD_OK && g->layout == BD_LAYOUT_FAT) rc = g->adj.alloc((size_t)std::max<int64_t>(nnz, 1) * 16);
+    if (rc != BD_OK) {
+        delete g;
+        return rc;
+    }
+    if (hipMemcpyAsync(g->node.p, nodetab.data(), (size_t)n * 16, hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(g->col.p, col_idx, (size_t)nnz * 4, hipMemcpyHostToDevice, st) != hipSuccess) {
+        delete g;
+        return BD_E_HIP;
+    }
+    if (g->layout == BD_LAYOUT_FAT &&
+        build_fat_adjacency(g->node.as<uint4>(), g->col.as<uint32_t>(), g->adj.as<uint4>(),
+                            (uint32_t)nnz, st) != hipSuccess) {
+        delete g;
+        return BD_E_HIP;
+    }
+    if (hipStreamSynchronize(st) != hipSuccess) {
+        delete g;
+        return BD_E_HIP;
+    }
+    g->device_bytes = (int64_t)(g->node.bytes + g->col.bytes + g->adj.bytes);
+    *out = g;
+    return BD_OK;
+}
+
+extern "C" void graph_free(bd_graph* g)
+{
+    delete g;
+}
+
+extern "C" int bd_graph_get_info(const bd_graph* g, bd_graph_info* info)
+{
+    if (!g || !info) return BD_E_INVALID;
+    info->n = g->n;
+    info->nnz = g->nnz;
+    info->d_min = g->d_min;
+    info->d_max = g->d_max;
+    info->bipartite = g->bipartite;
+    info->layout = g->layout;
+    info->device_bytes = g->device_bytes;
+    return BD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Planner (Algorithm 1 parameters; proof of Theorem 3.8)
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr double kCeilGuard = 1.0 - 0x1p-40;
+
+int64_t ceil_guarded(double x)
+{
+    return (int64_t)std::ceil(x * kCeilGuard);
+}
+
+bd_policy default_policy()
+{
+    bd_policy p{};
+    p.kind = BD_POLICY_PAPER;
+    p.c_B = 448.0;
+    p.c_R = 128.0;
+    p.delta = 0.01;
+    return p;
+}
+
+// Fills B, G, K, R, L, walk_steps and status of one result.
+void plan_one(const bd_graph* g, int32_t s, int32_t t, double eps, int32_t L, const bd_policy& pol,
+              bd_result* r)
+{
+    std::memset(r, 0, sizeof(*r));
+    r->L = L;
+    if (s < 0 || t < 0 || s >= g->n || t >= g->n || s == t || !(eps > 0.0 && eps < 1.0) || L < 0 ||
+        L > kMaxL) {
+        r->status = BD_E_INVALID;
+        return;
+    }
+    const double delta = pol.delta > 0.0 ? pol.delta : 0.01;
+    const int64_t G = ceil_guarded(8.0 * std::log(1.0 / delta));
+    int64_t B, R;
+    if (pol.kind == BD_POLICY_FIXED) {
+        B = pol.B_fixed;
+        R = pol.R_fixed;
+    } else {
+        const double cB = pol.kind == BD_POLICY_PAPER ? 448.0 : pol.c_B;
+        const double cR = pol.kind == BD_POLICY_PAPER ? 128.0 : pol.c_R;
+        B = ceil_guarded(cB / (eps * eps));
+        const double ds = g->deg[(size_t)s], dt = g->deg[(size_t)t], dm = g->d_min;
+        const double inv = 1.0 / ds + 1.0 / dt;
+        const double theta = (1.0 - eps / 2.0) * inv * inv;
+        const double Lp1 = (double)L + 1.0;
+        const double rr = cR * Lp1 * Lp1 / (dm * dm * theta);
+        R = rr > 9.0e18 ? INT64_MAX : ceil_guarded(rr);
+    }
+    B = std::max<int64_t>(B, 1);
+    R = std::max<int64_t>(R, 2);
+    r->B = (int32_t)std::min<int64_t>(B, INT32_MAX);
+    r->G = (int32_t)G;
+    r->R = R;
+    // exact products in 128 bits, saturated at INT64_MAX
+    typedef unsigned __int128 u128;
+    const u128 i64max = (u128)INT64_MAX;
+    const u128 K = (u128)(uint64_t)B * (u128)(uint64_t)G;
+    r->K = K > i64max ? INT64_MAX : (int64_t)K;
+    u128 steps;
+    if (L == 0) {
+        steps = 0;
+    } else if ((K >> 64) != 0) {
+        steps = i64max + 1;
+    } else {
+        const u128 KR = K * (u128)(uint64_t)R;  // < 2^127
+        steps = (KR >> 112) != 0 ? i64max + 1 : 2 * KR * (u128)(uint64_t)L;  // L < 2^14
+    }
+    r->walk_steps = steps > i64max ? INT64_MAX : (int64_t)steps;
+    if (G > kMaxG || B > INT32_MAX || K >= 4294967295u || R >= (int64_t)4294967295LL)
+        r->status = BD_E_BUDGET;
+    else if (pol.max_steps_per_query && steps > (u128)pol.max_steps_per_query)
+        r->status = BD_E_BUDGET;
+    else
+        r->status = BD_OK;
+}
+
+}  // namespace
+
+extern "C" int bd_plan(const bd_graph* g, int64_t nq, const int32_t* s, const int32_t* t,
+                       const double* eps, const int32_t* L, const bd_policy* pol, bd_result* out)
+{
+    if (!g || nq < 0 || (nq > 0 && (!s || !t || !eps || !L || !out))) return BD_E_INVALID;
+    const bd_policy p = pol ? *pol : default_policy();
+    for (int64_t i = 0; i < nq; ++i) plan_one(g, s[i], t[i], eps[i], L[i], p, &out[i]);
+    return BD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Batched execution
+// ---------------------------------------------------------------------------
+namespace {
+
+GraphTables tables(const bd_graph* g)
+{
+    GraphTables t{};
+    t.node = g->node.as<const uint4>();
+    t.col = g->col.as<const uint32_t>();
+    t.adj = g->adj.as<const uint4>();
+    t.dom = g->dom;
+    return t;
+}
+
+int resident_wgs(const bd_graph* g)
+{
+    int per_cu = 0;
+    if (walk_occupancy(g->layout == BD_LAYOUT_FAT, &per_cu) != 0 || per_cu < 1) per_cu = 1;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, g->device) != hipSuccess) return per_cu * 256;
+    return per_cu * prop.multiProcessorCount;
+}
+
+// Probes per chunk: enough (probe, replica) pairs to keep 256 lanes busy for
+// several rounds, capped by the LDS accumulator size.
+uint32_t chunk_probes(const bd_exec& ex, uint32_t K, uint32_t R)
+{
+    uint32_t kc;
+    if (ex.chunk_probes > 0) {
+        kc = (uint32_t)ex.chunk_probes;
+    } else {
+        const uint64_t target = ex.mode == BD_MODE_PLAIN ? (uint64_t)kBlockThreads : 4u * kBlockThreads;
+        kc = (uint32_t)std::max<uint64_t>(1, (target + R - 1) / R);
+    }
+    kc = std::min<uint32_t>(kc, (uint32_t)kMaxChunkProbes);
+    kc = std::min<uint32_t>(kc, std::max<uint32_t>(K, 1));
+    return std::max<uint32_t>(kc, 1);
+}
+
+struct Batch {
+    std::vector<QueryDesc> qd;
+    std::vector<Chunk> chunks;
+    std::vector<uint32_t> chunk_begin;  // per valid query, first chunk (chunks grouped by query)
+    std::vector<int64_t> index;         // valid query -> caller's index
+    uint32_t G = 0;
+};
+
+// Run one set of valid queries: zero the tables, launch, read the results.
+int run_batch(bd_graph* g, const Batch& b, const bd_exec& ex, hipStream_t st,
+              std::vector<double>& beta, bd_stats* stats, double* q_dbg_host, double* y_dbg_host)
+{
+    const size_t nv = b.qd.size();
+    if (nv == 0) return BD_OK;
+    const size_t gdim = b.G;
+    DevBuf d_qd, d_chunks, d_bs, d_done, d_beta, d_cursor, d_qdbg, d_ydbg;
+    int rc = d_qd.alloc(nv * sizeof(QueryDesc));
+    if (rc == BD_OK) rc = d_chunks.alloc(b.chunks.size() * sizeof(Chunk));
+    if (rc == BD_OK) rc = d_bs.alloc(nv * gdim * 16);
+    if (rc == BD_OK) rc = d_done.alloc(nv * 4);
+    if (rc == BD_OK) rc = d_beta.alloc(nv * 8);
+    if (rc == BD_OK) rc = d_cursor.alloc(16);
+    if (rc == BD_OK && q_dbg_host) rc = d_qdbg.alloc((size_t)b.qd[0].K * 8);
+    if (rc == BD_OK && y_dbg_host) rc = d_ydbg.alloc(gdim * 8);
+    if (rc != BD_OK) return rc;
+    HIP_TRY(hipMemcpyAsync(d_qd.p, b.qd.data(), nv * sizeof(QueryDesc), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(d_chunks.p, b.chunks.data(), b.chunks.size() * sizeof(Chunk),
+                           hipMemcpyHostToDevice, st));
+    HIP_TRY(launch_zero(d_bs.p, nv * gdim * 16, st));
+    HIP_TRY(launch_zero(d_done.p, nv * 4, st));
+    HIP_TRY(launch_zero(d_cursor.p, 16, st));
+
+    WalkArgs a{};
+    a.g = tables(g);
+    a.qd = d_qd.as<const QueryDesc>();
+    a.gdim = (uint32_t)gdim;
+    a.cursor = d_cursor.as<uint32_t>();
+    a.blocksum = d_bs.as<unsigned long long>();
+    a.done = d_done.as<uint32_t>();
+    a.beta = d_beta.as<double>();
+    a.q_debug = q_dbg_host ? d_qdbg.as<double>() : nullptr;
+    a.ybar_debug = y_dbg_host ? d_ydbg.as<double>() : nullptr;
+    const int fat = g->layout == BD_LAYOUT_FAT;
+
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return BD_E_HIP;
+    }
+    double kernel_ms = 0.0;
+    int64_t launches = 0;
+    int status = BD_OK;
+    auto timed_launch = [&](const WalkArgs& args, uint32_t grid) -> int {
+        if (hipEventRecord(e0, st) != hipSuccess) return BD_E_HIP;
+        if (launch_walk(args, fat, grid, st) != hipSuccess) return BD_E_HIP;
+        if (hipEventRecord(e1, st) != hipSuccess) return BD_E_HIP;
+        if (hipEventSynchronize(e1) != hipSuccess) return BD_E_HIP;
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return BD_E_HIP;
+        kernel_ms += ms;
+        ++launches;
+        return BD_OK;
+    };
+    if (ex.mode == BD_MODE_PLAIN) {
+        // one query per launch, one work group per chunk
+        for (size_t q = 0; q < nv && status == BD_OK; ++q) {
+            const uint32_t c0 = b.chunk_begin[q];
+            const uint32_t c1 = q + 1 < nv ? b.chunk_begin[q + 1] : (uint32_t)b.chunks.size();
+            WalkArgs aq = a;
+            aq.chunks = d_chunks.as<const Chunk>() + c0;
+            aq.nchunks = c1 - c0;
+            aq.persistent = 0;
+            status = timed_launch(aq, c1 - c0);
+        }
+    } else {
+        WalkArgs ab = a;
+        ab.chunks = d_chunks.as<const Chunk>();
+        ab.nchunks = (uint32_t)b.chunks.size();
+        ab.persistent = 1;
+        uint32_t grid = ex.grid_wgs > 0 ? (uint32_t)ex.grid_wgs : (uint32_t)resident_wgs(g);
+        grid = std::min<uint32_t>(grid, ab.nchunks);
+        status = timed_launch(ab, grid);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (status != BD_OK) return status;
+    beta.resize(nv);
+    HIP_TRY(hipMemcpyAsync(beta.data(), d_beta.p, nv * 8, hipMemcpyDeviceToHost, st));
+    if (q_dbg_host)
+        HIP_TRY(hipMemcpyAsync(q_dbg_host, d_qdbg.p, (size_t)b.qd[0].K * 8, hipMemcpyDeviceToHost, st));
+    if (y_dbg_host) HIP_TRY(hipMemcpyAsync(y_dbg_host, d_ydbg.p, gdim * 8, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (stats) {
+        stats->walk_kernel_ms += kernel_ms;
+        stats->launches += launches;
+        stats->chunks += (int64_t)b.chunks.size();
+    }
+    return BD_OK;
+}
+
+// Build descriptors and the chunk table for the valid queries of a batch.
+void build_batch(const bd_graph* g, int64_t nq, const int32_t* s, const int32_t* t, const int32_t* L,
+                 const uint32_t* uid, uint64_t seed, const bd_result* plans, const bd_exec& ex, Batch& b)
+{
+    for (int64_t i = 0; i < nq; ++i) {
+        const bd_result& r = plans[i];
+        if (r.status != BD_OK) continue;
+        QueryDesc d{};
+        d.s = s[i];
+        d.t = t[i];
+        d.L = L[i];
+        d.uid = uid ? uid[i] : (uint32_t)i;
+        d.K = (uint32_t)r.K;
+        d.R = (uint32_t)r.R;
+        d.B = (uint32_t)r.B;
+        d.G = (uint32_t)r.G;
+        d.slot = (uint32_t)b.qd.size();
+        d.seed_lo = (uint32_t)seed;
+        d.seed_hi = (uint32_t)(seed >> 32);
+        b.G = std::max<uint32_t>(b.G, d.G);
+        b.index.push_back(i);
+        b.qd.push_back(d);
+    }
+    // chunk table: grouped by query; batched launches order queries by
+    // descending cost so the longest work starts first
+    std::vector<size_t> order(b.qd.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = i;
+    if (ex.mode != BD_MODE_PLAIN) {
+        std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) {
+            const double cx = (double)b.qd[x].L * b.qd[x].R, cy = (double)b.qd[y].L * b.qd[y].R;
+            return cx > cy;
+        });
+    }
+    b.chunk_begin.assign(b.qd.size(), 0);
+    for (size_t oi = 0; oi < order.size(); ++oi) {
+        const size_t q = order[oi];
+        const QueryDesc& d = b.qd[q];
+        const uint32_t kc = chunk_probes(ex, d.K, d.R);
+        b.chunk_begin[q] = (uint32_t)b.chunks.size();
+        for (uint32_t k0 = 0; k0 < d.K; k0 += kc) {
+            Chunk c{};
+            c.q = (uint32_t)q;
+            c.k0 = k0;
+            c.kc = std::min<uint32_t>(kc, d.K - k0);
+            b.chunks.push_back(c);
+        }
+    }
+    (void)g;
+}
+
+}  // namespace
+
+extern "C" int bd_query_batch(bd_graph* g, int64_t nq, const int32_t* s, const int32_t* t,
+                              const double* eps, const int32_t* L, const uint32_t* uid,
+                              uint64_t seed, const bd_policy* pol, const bd_exec* exec, void* stream,
+                              bd_result* out, bd_stats* stats)
+{
+    if (!g || nq < 0 || (nq > 0 && (!s || !t || !eps || !L || !out))) return BD_E_INVALID;
+    const double t0 = now_ms();
+    if (stats) std::memset(stats, 0, sizeof(*stats));
+    const bd_policy p = pol ? *pol : default_policy();
+    bd_exec ex{};
+    ex.mode = BD_MODE_BATCHED;
+    if (exec) ex = *exec;
+    for (int64_t i = 0; i < nq; ++i) {
+        plan_one(g, s[i], t[i], eps[i], L[i], p, &out[i]);
+        if (uid && uid[i] >= 0x80000000u) out[i].status = BD_E_INVALID;
+    }
+    std::lock_guard<std::mutex> lock(g->mu);
+    Batch b;
+    build_batch(g, nq, s, t, L, uid, seed, out, ex, b);
+    std::vector<double> beta;
+    const int rc = run_batch(g, b, ex, (hipStream_t)stream, beta, stats, nullptr, nullptr);
+    if (rc != BD_OK) return rc;
+    for (size_t q = 0; q < b.qd.size(); ++q) {
+        bd_result& r = out[b.index[q]];
+        r.beta = beta[q];
+        if (stats) {
+            stats->walk_steps += r.walk_steps;
+            stats->walk_pairs += r.K * r.R;
+        }
+    }
+    if (stats) stats->total_ms = now_ms() - t0;
+    return BD_OK;
+}
+
+extern "C" int bd_query_probes(bd_graph* g, int32_t s, int32_t t, double eps, int32_t L, uint32_t uid,
+                               uint64_t seed, const bd_policy* pol, const bd_exec* exec, void* stream,
+                               double* q_out, double* ybar_out, bd_result* out)
+{
+    if (!g || !out) return BD_E_INVALID;
+    const bd_policy p = pol ? *pol : default_policy();
+    bd_exec ex{};
+    ex.mode = BD_MODE_PLAIN;
+    if (exec) ex = *exec;
+    plan_one(g, s, t, eps, L, p, out);
+    if (uid >= 0x80000000u) out->status = BD_E_INVALID;
+    if (out->status != BD_OK) return out->status;
+    std::lock_guard<std::mutex> lock(g->mu);
+    Batch b;
+    build_batch(g, 1, &s, &t, &L, &uid, seed, out, ex, b);
+    std::vector<double> beta;
+    const int rc = run_batch(g, b, ex, (hipStream_t)stream, beta, nullptr, q_out, ybar_out);
+    if (rc != BD_OK) return rc;
+    out->beta = beta[0];
+    return BD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Validation entry points
+// ---------------------------------------------------------------------------
+extern "C" int bd_walk_trace(bd_graph* g, int64_t count, const int32_t* start, const uint32_t* uid,
+                             const uint32_t* k, const uint32_t* p, const uint32_t* side, int32_t L,
+                             uint64_t seed, void* stream, int32_t* trace, float* acc)
+{
+    if (!g || count < 0 || L < 0 || L > kMaxL) return BD_E_INVALID;
+    if (count == 0) return BD_OK;
+    if (!start || !uid || !k || !p || !side || count > 0x7FFFFFFF) return BD_E_INVALID;
+    for (int64_t i = 0; i < count; ++i)
+        if (start[i] < 0 || start[i] >= g->n || side[i] > 1u || uid[i] >= 0x80000000u || p[i] == 0xFFFFFFFFu)
+            return BD_E_INVALID;
+    hipStream_t st = (hipStream_t)stream;
+    const size_t c = (size_t)count;
+    DevBuf ds, du, dk, dp, dsd, dt, da;
+    int rc = ds.alloc(c * 4);
+    if (rc == BD_OK) rc = du.alloc(c * 4);
+    if (rc == BD_OK) rc = dk.alloc(c * 4);
+    if (rc == BD_OK) rc = dp.alloc(c * 4);
+    if (rc == BD_OK) rc = dsd.alloc(c * 4);
+    if (rc == BD_OK && trace) rc = dt.alloc(c * (size_t)(L + 1) * 4);
+    if (rc == BD_OK && acc) rc = da.alloc(c * 4);
+    if (rc != BD_OK) return rc;
+    HIP_TRY(hipMemcpyAsync(ds.p, start, c * 4, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(du.p, uid, c * 4, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(dk.p, k, c * 4, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(dp.p, p, c * 4, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(dsd.p, side, c * 4, hipMemcpyHostToDevice, st));
+    HIP_TRY(launch_trace(tables(g), g->layout == BD_LAYOUT_FAT, (uint32_t)c, ds.as<int32_t>(),
+                         du.as<uint32_t>(), dk.as<uint32_t>(), dp.as<uint32_t>(), dsd.as<uint32_t>(), L,
+                         (uint32_t)seed, (uint32_t)(seed >> 32), trace ? dt.as<int32_t>() : nullptr,
+                         acc ? da.as<float>() : nullptr, st));
+    if (trace) HIP_TRY(hipMemcpyAsync(trace, dt.p, c * (size_t)(L + 1) * 4, hipMemcpyDeviceToHost, st));
+    if (acc) HIP_TRY(hipMemcpyAsync(acc, da.p, c * 4, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return BD_OK;
+}
+
+extern "C" int bd_probe_eval(bd_graph* g, uint64_t seed, uint32_t uid, uint32_t k, int64_t count,
+                             const uint32_t* nodes, void* stream, uint32_t* pi, int8_t* z)
+{
+    if (!g || count < 0 || uid >= 0x80000000u) return BD_E_INVALID;
+    if (count == 0) return BD_OK;
+    if (!nodes || count > 0x7FFFFFFF) return BD_E_INVALID;
+    for (int64_t i = 0; i < count; ++i)
+        if (nodes[i] >= (uint64_t)g->n) return BD_E_INVALID;
+    hipStream_t st = (hipStream_t)stream;
+    const size_t c = (size_t)count;
+    DevBuf dn, dpi, dz;
+    int rc = dn.alloc(c * 4);
+    if (rc == BD_OK && pi) rc = dpi.alloc(c * 4);
+    if (rc == BD_OK && z) rc = dz.alloc(c);
+    if (rc != BD_OK) return rc;
+    HIP_TRY(hipMemcpyAsync(dn.p, nodes, c * 4, hipMemcpyHostToDevice, st));
+    HIP_TRY(launch_probe_eval(tables(g), (uint32_t)seed, (uint32_t)(seed >> 32), uid, k, (uint32_t)c,
+                              dn.as<uint32_t>(), pi ? dpi.as<uint32_t>() : nullptr,
+                              z ? dz.as<int8_t>() : nullptr, st));
+    if (pi) HIP_TRY(hipMemcpyAsync(pi, dpi.p, c * 4, hipMemcpyDeviceToHost, st));
+    if (z) HIP_TRY(hipMemcpyAsync(z, dz.p, c, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return BD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Misc
+// ---------------------------------------------------------------------------
+extern "C" const char* bd_strerror(int code)
+{
+    switch (code) {
+    case BD_OK: return "ok";
+    case BD_E_INVALID: return "invalid argument";
+    case BD_E_GRAPH: return "graph is not simple, symmetric, sorted and connected";
+    case BD_E_RANGE: return "size beyond the library limits";
+    case BD_E_BUDGET: return "walk budget beyond the cap or K, R >= 2^32";
+    case BD_E_HIP: return "HIP runtime error";
+    case BD_E_NOMEM: return "out of memory";
+    case BD_E_NODEVICE: return "no usable GPU";
+    case BD_E_NOTFOUND: return "unknown request id";
+    case BD_E_FULL: return "request exceeds the admission caps";
+    case BD_E_CANCELLED: return "request cancelled";
+    case BD_E_TIMEOUT: return "timed out";
+    default: return "unknown error";
+    }
+}
+
+extern "C" int bd_device_info(char* buf, size_t len)
+{
+    if (!buf || len == 0) return BD_E_INVALID;
+    int dev = 0, ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
+        (void)hipGetLastError();
+        std::snprintf(buf, len, "no device");
+        return BD_E_NODEVICE;
+    }
+    HIP_TRY(hipGetDevice(&dev));
+    hipDeviceProp_t p;
+    HIP_TRY(hipGetDeviceProperties(&p, dev));
+    std::snprintf(buf, len, "%s (%s), %d CUs, %d MHz, %.1f GiB, L2 %d KiB", p.name, p.gcnArchName,
+                  p.multiProcessorCount, p.clockRate / 1000, (double)p.totalGlobalMem / (1 << 30),
+                  p.l2CacheSize / 1024);
+    return BD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Served mode: continuous batching
+//
+// A scheduler thread keeps a table of resident queries ("slots") on the
+// device. Each scheduling slice is one persistent walk launch over chunks
+// taken round-robin from every admitted query that still has probes left, so
+// a request that arrives while others run joins the very next slice and its
+// work shares the device with theirs. Two slices are kept in flight. The work
+// group that finishes a query posts (slot, beta) to a completion ring and
+// clears the slot's tables; the host frees the slot when it reads the ring.
+// Admission is FIFO under two caps: resident queries (device memory) and
+// outstanding walk steps.
+// ---------------------------------------------------------------------------
+namespace {
+
+struct PinnedBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    PinnedBuf() = default;
+    PinnedBuf(const PinnedBuf&) = delete;
+    PinnedBuf& operator=(const PinnedBuf&) = delete;
+    ~PinnedBuf()
+    {
+        if (p) (void)hipHostFree(p);
+    }
+    int alloc(size_t b)
+    {
+        if (hipHostMalloc(&p, b, hipHostMallocDefault) != hipSuccess) {
+            p = nullptr;
+            (void)hipGetLastError();
+            return BD_E_NOMEM;
+        }
+        bytes = b;
+        return BD_OK;
+    }
+    template <class T>
+    T* as() const { return static_cast<T*>(p); }
+};
+
+struct Request {
+    std::vector<bd_result> res;
+    std::vector<QueryDesc> desc;  // valid queries
+    std::vector<int64_t> index;   // valid query -> result index
+    int64_t remaining = 0;
+    uint64_t steps = 0;
+    double t_submit = 0, t_done = 0;
+    bool done = false;
+};
+
+struct SlotState {
+    uint64_t req = 0;
+    int64_t ridx = 0;
+    uint32_t next_k = 0, K = 0, kc = 1;
+    uint64_t chunk_steps = 0;  // walk steps of one full chunk
+    uint64_t steps = 0;        // walk steps of the query
+};
+
+struct Slice {
+    PinnedBuf chunks_h;
+    DevBuf chunks_d;
+    PinnedBuf comp_h;  // [u32 count, pad to 16 B][Completion x cap]
+    hipEvent_t ev = nullptr;
+    uint32_t n = 0;
+    bool inflight = false;
+    uint64_t steps = 0;
+    double t_launch = 0;
+};
+
+constexpr uint32_t kSliceMaxChunks = 1u << 18;
+
+}  // namespace
+
+struct bd_server {
+    bd_graph* g = nullptr;
+    bd_server_cfg cfg{};
+    bd_policy pol{};
+    hipStream_t st = nullptr;
+    uint32_t slots = 0, gdim = 0;
+    int resident = 0;
+    DevBuf d_qd, d_bs, d_done, d_beta, d_cursor, d_comp;
+    PinnedBuf h_qd;
+    Slice slice[2];
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::thread th;
+    bool stop = false;
+    int broken = BD_OK;
+    std::map<uint64_t, Request> reqs;
+    std::deque<uint64_t> pending;
+    uint64_t next_id = 1;
+    std::vector<uint32_t> free_slots;
+    std::vector<SlotState> slot;
+    std::deque<uint32_t> rr;
+    uint64_t inflight_steps = 0;
+    uint32_t comp_seen = 0;
+    double steps_per_ms = 5e7;
+};
+
+namespace {
+
+size_t comp_bytes(const bd_server* S)
+{
+    return 16 + (size_t)S->slots * sizeof(Completion);
+}
+
+void finish_request(bd_server* S, uint64_t id, Request& r)
+{
+    (void)id;
+    r.done = true;
+    r.t_done = now_ms();
+    S->cv_done.notify_all();
+}
+
+// Move pending requests into slots (FIFO) while the caps allow. Caller holds mu.
+int admit(bd_server* S)
+{
+    while (!S->pending.empty()) {
+        const uint64_t id = S->pending.front();
+        Request& r = S->reqs[id];
+        const size_t need = r.desc.size();
+        if (need > S->free_slots.size()) break;
+        const uint64_t cap = S->cfg.max_steps_inflight;
+        if (cap && S->inflight_steps > 0 && S->inflight_steps + r.steps > cap) break;
+        S->pending.pop_front();
+        for (size_t i = 0; i < need; ++i) {
+            const uint32_t sl = S->free_slots.back();
+            S->free_slots.pop_back();
+            QueryDesc d = r.desc[i];
+            d.slot = sl;
+            S->h_qd.as<QueryDesc>()[sl] = d;
+            if (hipMemcpyAsync(S->d_qd.as<QueryDesc>() + sl, S->h_qd.as<QueryDesc>() + sl, sizeof(QueryDesc),
+                               hipMemcpyHostToDevice, S->st) != hipSuccess)
+                return BD_E_HIP;
+            SlotState& ss = S->slot[sl];
+            bd_exec ex{};
+            ex.mode = BD_MODE_BATCHED;
+            ex.chunk_probes = S->cfg.chunk_probes;
+            ss.req = id;
+            ss.ridx = r.index[i];
+            ss.next_k = 0;
+            ss.K = d.K;
+            ss.kc = chunk_probes(ex, d.K, d.R);
+            ss.chunk_steps = 2ull * ss.kc * d.R * (uint64_t)d.L + 2ull * ss.kc * d.R;
+            ss.steps = (uint64_t)r.res[(size_t)ss.ridx].walk_steps;
+            S->inflight_steps += ss.steps;
+            S->rr.push_back(sl);
+        }
+    }
+    return BD_OK;
+}
+
+// Read the completion ring snapshot of a finished slice. Caller holds mu.
+void process_completions(bd_server* S, const Slice& sl)
+{
+    const uint32_t count = *sl.comp_h.as<const uint32_t>();
+    const Completion* ring = reinterpret_cast<const Completion*>(sl.comp_h.as<const char>() + 16);
+    for (uint32_t i = S->comp_seen; i != count; ++i) {
+        const Completion c = ring[i % S->slots];
+        SlotState& ss = S->slot[c.slot];
+        auto it = S->reqs.find(ss.req);
+        if (it != S->reqs.end()) {
+            Request& r = it->second;
+            r.res[(size_t)ss.ridx].beta = c.beta;
+            if (--r.remaining == 0) finish_request(S, ss.req, r);
+        }
+        S->inflight_steps -= std::min(S->inflight_steps, ss.steps);
+        S->free_slots.push_back(c.slot);
+    }
+    S->comp_seen = count;
+}
+
+// Take chunks round-robin for one slice. Caller holds mu.
+void fill_slice(bd_server* S, Slice& sl)
+{
+    const double slice_ms = S->cfg.slice_ms > 0 ? S->cfg.slice_ms : 20.0;
+    const double target = slice_ms * S->steps_per_ms;
+    Chunk* out = sl.chunks_h.as<Chunk>();
+    sl.n = 0;
+    sl.steps = 0;
+    while (!S->rr.empty() && sl.n < kSliceMaxChunks &&
+           ((double)sl.steps < target || sl.n < (uint32_t)S->resident)) {
+        const uint32_t q = S->rr.front();
+        S->rr.pop_front();
+        SlotState& ss = S->slot[q];
+        Chunk c{};
+        c.q = q;
+        c.k0 = ss.next_k;
+        c.kc = std::min<uint32_t>(ss.kc, ss.K - ss.next_k);
+        ss.next_k += c.kc;
+        out[sl.n++] = c;
+        sl.steps += ss.chunk_steps;
+        if (ss.next_k < ss.K) S->rr.push_back(q);
+    }
+}
+
+int launch_slice(bd_server* S, Slice& sl)
+{
+    hipStream_t st = S->st;
+    if (hipMemcpyAsync(sl.chunks_d.p, sl.chunks_h.p, (size_t)sl.n * sizeof(Chunk), hipMemcpyHostToDevice, st) !=
+        hipSuccess)
+        return BD_E_HIP;
+    if (launch_zero(S->d_cursor.p, 16, st) != hipSuccess) return BD_E_HIP;
+    WalkArgs a{};
+    a.g = tables(S->g);
+    a.qd = S->d_qd.as<const QueryDesc>();
+    a.chunks = sl.chunks_d.as<const Chunk>();
+    a.nchunks = sl.n;
+    a.gdim = S->gdim;
+    a.cursor = S->d_cursor.as<uint32_t>();
+    a.blocksum = S->d_bs.as<unsigned long long>();
+    a.done = S->d_done.as<uint32_t>();
+    a.beta = S->d_beta.as<double>();
+    a.comp_count = S->d_comp.as<uint32_t>();
+    a.comp_ring = reinterpret_cast<Completion*>(S->d_comp.as<char>() + 16);
+    a.comp_cap = S->slots;
+    a.recycle = 1;
+    a.persistent = 1;
+    const uint32_t grid = std::min<uint32_t>((uint32_t)S->resident, sl.n);
+    if (launch_walk(a, S->g->layout == BD_LAYOUT_FAT, grid, st) != hipSuccess) return BD_E_HIP;
+    if (hipMemcpyAsync(sl.comp_h.p, S->d_comp.p, comp_bytes(S), hipMemcpyDeviceToHost, st) != hipSuccess)
+        return BD_E_HIP;
+    if (hipEventRecord(sl.ev, st) != hipSuccess) return BD_E_HIP;
+    sl.inflight = true;
+    sl.t_launch = now_ms();
+    return BD_OK;
+}
+
+void fail_all(bd_server* S, int code)
+{
+    for (auto& kv : S->reqs) {
+        Request& r = kv.second;
+        if (r.done) continue;
+        for (auto& x : r.res)
+            if (x.status == BD_OK) x.status = code;
+        finish_request(S, kv.first, r);
+    }
+    S->pending.clear();
+    S->rr.clear();
+}
+
+void server_loop(bd_server* S)
+{
+    int cur = 0;
+    std::unique_lock<std::mutex> lk(S->mu);
+    for (;;) {
+        S->cv_work.wait(lk, [&] {
+            return S->stop || !S->pending.empty() || !S->rr.empty() || S->slice[0].inflight ||
+                   S->slice[1].inflight;
+        });
+        const bool any_inflight = S->slice[0].inflight || S->slice[1].inflight;
+        if (S->stop && !any_inflight) break;
+        int rc = BD_OK;
+        if (!S->stop) rc = admit(S);
+        Slice& sl = S->slice[cur];
+        if (rc == BD_OK && sl.inflight) {
+            lk.unlock();
+            const hipError_t e = hipEventSynchronize(sl.ev);
+            lk.lock();
+            if (e != hipSuccess) {
+                rc = BD_E_HIP;
+            } else {
+                const double dt = now_ms() - sl.t_launch;
+                if (dt > 0.5 && sl.steps > 0) S->steps_per_ms = 0.7 * S->steps_per_ms + 0.3 * (sl.steps / dt);
+                process_completions(S, sl);
+            }
+            sl.inflight = false;
+        }
+        if (rc == BD_OK && !S->stop) {
+            rc = admit(S);
+            if (rc == BD_OK) {
+                fill_slice(S, sl);
+                if (sl.n > 0) rc = launch_slice(S, sl);
+            }
+        }
+        if (rc != BD_OK) {
+            S->broken = rc;
+            fail_all(S, rc);
+            // drain whatever is still on the device before leaving
+            lk.unlock();
+            (void)hipStreamSynchronize(S->st);
+            lk.lock();
+            S->slice[0].inflight = S->slice[1].inflight = false;
+            break;
+        }
+        cur ^= 1;
+    }
+    fail_all(S, BD_E_CANCELLED);
+}
+
+}  // namespace
+
+extern "C" int bd_server_create(bd_graph* g, const bd_server_cfg* cfg, bd_server** out)
+{
+    if (!g || !out) return BD_E_INVALID;
+    *out = nullptr;
+    bd_server* S = new (std::nothrow) bd_server();
+    if (!S) return BD_E_NOMEM;
+    S->g = g;
+    if (cfg) S->cfg = *cfg;
+    S->pol = cfg ? cfg->policy : default_policy();
+    if (S->pol.delta <= 0.0) S->pol.delta = 0.01;
+    S->slots = (uint32_t)(S->cfg.max_queries_inflight > 0 ? std::min<int64_t>(S->cfg.max_queries_inflight, 1 << 22)
+                                                         : 65536);
+    S->gdim = (uint32_t)ceil_guarded(8.0 * std::log(1.0 / S->pol.delta));
+    if (S->gdim > (uint32_t)kMaxG) {
+        delete S;
+        return BD_E_BUDGET;
+    }
+    S->resident = resident_wgs(g);
+    int rc = S->d_qd.alloc((size_t)S->slots * sizeof(QueryDesc));
+    if (rc == BD_OK) rc = S->d_bs.alloc((size_t)S->slots * S->gdim * 16);
+    if (rc == BD_OK) rc = S->d_done.alloc((size_t)S->slots * 4);
+    if (rc == BD_OK) rc = S->d_beta.alloc((size_t)S->slots * 8);
+    if (rc == BD_OK) rc = S->d_cursor.alloc(16);
+    if (rc == BD_OK) rc = S->d_comp.alloc(comp_bytes(S));
+    if (rc == BD_OK) rc = S->h_qd.alloc((size_t)S->slots * sizeof(QueryDesc));
+    for (int i = 0; i < 2 && rc == BD_OK; ++i) {
+        rc = S->slice[i].chunks_h.alloc((size_t)kSliceMaxChunks * sizeof(Chunk));
+        if (rc == BD_OK) rc = S->slice[i].chunks_d.alloc((size_t)kSliceMaxChunks * sizeof(Chunk));
+        if (rc == BD_OK) rc = S->slice[i].comp_h.alloc(comp_bytes(S));
+        if (rc == BD_OK && hipEventCreateWithFlags(&S->slice[i].ev, hipEventDisableTiming) != hipSuccess)
+            rc = BD_E_HIP;
+    }
+    if (rc == BD_OK && hipStreamCreateWithFlags(&S->st, hipStreamNonBlocking) != hipSuccess) rc = BD_E_HIP;
+    if (rc == BD_OK && launch_zero(S->d_bs.p, (size_t)S->slots * S->gdim * 16, S->st) != hipSuccess) rc = BD_E_HIP;
+    if (rc == BD_OK && launch_zero(S->d_done.p, (size_t)S->slots * 4, S->st) != hipSuccess) rc = BD_E_HIP;
+    if (rc == BD_OK && launch_zero(S->d_comp.p, comp_bytes(S), S->st) != hipSuccess) rc = BD_E_HIP;
+    if (rc == BD_OK && hipStreamSynchronize(S->st) != hipSuccess) rc = BD_E_HIP;
+    if (rc != BD_OK) {
+        for (int i = 0; i < 2; ++i)
+            if (S->slice[i].ev) (void)hipEventDestroy(S->slice[i].ev);
+        if (S->st) (void)hipStreamDestroy(S->st);
+        delete S;
+        return rc;
+    }
+    S->slot.resize(S->slots);
+    S->free_slots.reserve(S->slots);
+    for (uint32_t i = S->slots; i-- > 0;) S->free_slots.push_back(i);
+    S->th = std::thread(server_loop, S);
+    *out = S;
+    return BD_OK;
+}
+
+extern "C" int bd_server_submit(bd_server* S, int64_t nq, const int32_t* s, const int32_t* t,
+                                const double* eps, const int32_t* L, const uint32_t* uid, uint64_t seed,
+                                uint64_t* request_id)
+{
+    if (!S || nq < 0 || !request_id || (nq > 0 && (!s || !t || !eps || !L))) return BD_E_INVALID;
+    Request r;
+    r.res.resize((size_t)nq);
+    for (int64_t i = 0; i < nq; ++i) {
+        plan_one(S->g, s[i], t[i], eps[i], L[i], S->pol, &r.res[(size_t)i]);
+        if (uid && uid[i] >= 0x80000000u) r.res[(size_t)i].status = BD_E_INVALID;
+        const bd_result& pr = r.res[(size_t)i];
+        if (pr.status != BD_OK) continue;
+        QueryDesc d{};
+        d.s = s[i];
+        d.t = t[i];
+        d.L = L[i];
+        d.uid = uid ? uid[i] : (uint32_t)i;
+        d.K = (uint32_t)pr.K;
+        d.R = (uint32_t)pr.R;
+        d.B = (uint32_t)pr.B;
+        d.G = (uint32_t)pr.G;
+        d.seed_lo = (uint32_t)seed;
+        d.seed_hi = (uint32_t)(seed >> 32);
+        r.desc.push_back(d);
+        r.index.push_back(i);
+        r.steps += (uint64_t)pr.walk_steps;
+    }
+    r.remaining = (int64_t)r.desc.size();
+    if (r.desc.size() > S->slots) return BD_E_FULL;
+    if (S->cfg.max_steps_inflight && r.steps > S->cfg.max_steps_inflight) return BD_E_FULL;
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (S->broken != BD_OK) return S->broken;
+    const uint64_t id = S->next_id++;
+    r.t_submit = now_ms();
+    const bool empty = r.remaining == 0;
+    auto& slot = S->reqs[id];
+    slot = std::move(r);
+    if (empty) finish_request(S, id, slot);
+    else S->pending.push_back(id);
+    *request_id = id;
+    S->cv_work.notify_all();
+    return BD_OK;
+}
+
+extern "C" int bd_server_poll(bd_server* S, uint64_t request_id, bd_result* out, int* done, double* latency_ms)
+{
+    if (!S || !done) return BD_E_INVALID;
+    std::lock_guard<std::mutex> lk(S->mu);
+    auto it = S->reqs.find(request_id);
+    if (it == S->reqs.end()) return BD_E_NOTFOUND;
+    *done = it->second.done ? 1 : 0;
+    if (!it->second.done) return BD_OK;
+    if (out) std::memcpy(out, it->second.res.data(), it->second.res.size() * sizeof(bd_result));
+    if (latency_ms) *latency_ms = it->second.t_done - it->second.t_submit;
+    S->reqs.erase(it);
+    return BD_OK;
+}
+
+extern "C" int bd_server_wait(bd_server* S, uint64_t request_id, double timeout_ms, bd_result* out,
+                              double* latency_ms)
+{
+    if (!S) return BD_E_INVALID;
+    std::unique_lock<std::mutex> lk(S->mu);
+    auto ready = [&] {
+        auto it = S->reqs.find(request_id);
+        return it == S->reqs.end() || it->second.done;
+    };
+    if (timeout_ms > 0) {
+        if (!S->cv_done.wait_for(lk, std::chrono::duration<double, std::milli>(timeout_ms), ready))
+            return BD_E_TIMEOUT;
+    } else {
+        S->cv_done.wait(lk, ready);
+    }
+    auto it = S->reqs.find(request_id);
+    if (it == S->reqs.end()) return BD_E_NOTFOUND;
+    if (out) std::memcpy(out, it->second.res.data(), it->second.res.size() * sizeof(bd_result));
+    if (latency_ms) *latency_ms = it->second.t_done - it->second.t_submit;
+    S->reqs.erase(it);
+    return BD_OK;
+}
+
+extern "C" void bd_server_destroy(bd_server* S)
+{
+    if (!S) return;
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->stop = true;
+    }
+    S->cv_work.notify_all();
+    if (S->th.joinable()) S->th.join();
+    (void)hipStreamSynchronize(S->st);
+    for (int i = 0; i < 2; ++i)
+        if (S->slice[i].ev) (void)hipEventDestroy(S->slice[i].ev);
+    (void)hipStreamDestroy(S->st);
+    delete S;
+}

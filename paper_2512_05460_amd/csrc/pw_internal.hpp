@@ -1,0 +1,85 @@
+// Types shared by the kernels (pw_kernels.hip) and the host runtime (pw_host.cpp).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pw {
+
+// One query as the device sees it (Algorithm 1 inputs and parameters).
+struct QueryDesc {
+    int32_t s, t;
+    int32_t L;
+    uint32_t uid;
+    uint32_t K, R, B, G;
+    uint32_t slot;      // row of the block-sum / done / result tables
+    uint32_t seed_lo, seed_hi;  // 64-bit Philox key of this query
+    uint32_t pad;
+};
+
+// A work-group chunk: probes [k0, k0 + kc) of query q, all R replicas.
+struct Chunk {
+    uint32_t q;
+    uint32_t k0;
+    uint32_t kc;
+    uint32_t pad;
+};
+
+struct DomainParams {
+    uint32_t n, rb, mask, rsh, A, A8;
+};
+
+struct GraphTables {
+    const uint4* node;
+    const uint32_t* col;
+    const uint4* adj;
+    DomainParams dom;
+};
+
+// A finished query as posted by the work group that completed it.
+struct Completion {
+    uint32_t slot;
+    uint32_t pad;
+    double beta;
+};
+
+// Arguments of one walk launch.
+struct WalkArgs {
+    GraphTables g;
+    const QueryDesc* qd;
+    const Chunk* chunks;
+    uint32_t nchunks;
+    uint32_t gdim;                  // G (blocks per query) of this launch
+    uint32_t* cursor;               // work-stealing cursor (persistent launches)
+    unsigned long long* blocksum;   // [slot][G][2] int128 block sums of trunc(Q 2^64)
+    uint32_t* done;                 // [slot] probes finished
+    double* beta;                   // [slot] results
+    double* q_debug;                // optional: [K] per-probe Q of the (single) query
+    double* ybar_debug;             // optional: [G] block means
+    uint32_t* comp_count;           // optional (served mode): completions posted so far
+    Completion* comp_ring;          // optional: ring of (slot, beta) completions
+    uint32_t comp_cap;
+    uint32_t recycle;               // clear a finished query's block sums and counter
+    uint32_t persistent;
+};
+
+constexpr int kBlockThreads = 256;
+constexpr int kMaxChunkProbes = 256;
+constexpr int kMaxG = 128;
+
+// Launchers (defined in pw_kernels.hip). All return hipError_t of the launch.
+hipError_t launch_walk(const WalkArgs& a, int fat, uint32_t grid, hipStream_t st);
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);
+hipError_t launch_trace(const GraphTables& g, int fat, uint32_t count, const int32_t* start,
+                        const uint32_t* uid, const uint32_t* k, const uint32_t* p,
+                        const uint32_t* side, int32_t L, uint32_t seed_lo, uint32_t seed_hi,
+                        int32_t* trace, float* acc, hipStream_t st);
+hipError_t launch_probe_eval(const GraphTables& g, uint32_t seed_lo, uint32_t seed_hi, uint32_t uid,
+                             uint32_t k, uint32_t count, const uint32_t* nodes, uint32_t* pi,
+                             int8_t* z, hipStream_t st);
+hipError_t build_fat_adjacency(const uint4* node, const uint32_t* col, uint4* adj, uint32_t nnz,
+                               hipStream_t st);
+// Work groups of the walk kernel that fit on the device at once.
+int walk_occupancy(int fat, int* wgs_per_cu);
+
+}  // namespace pw

@@ -1,0 +1,332 @@
+// HIP kernels of the ProbeWalk hot path (gfx950).
+//
+// One work group runs one chunk: probes [k0, k0+kc) of one query with all R
+// replicas each (Algorithm 1: the probe loop, the replica loop and the walk
+// loop). Its 256 lanes stride over the kc*R (probe, replica) pairs; each lane
+// runs the s-walk and the t-walk of its pair interleaved, so two independent
+// dependent-gather chains are in flight per lane. Per-probe sums S1, S2 are
+// exact 128-bit integers accumulated in LDS; at the end of the chunk each
+// probe's Q_R (U-statistic, Lemma 3.4) is added as trunc(Q 2^64) to its
+// median-of-means block in global memory. The work group that completes a
+// query's last probe forms the G block means and their median.
+//
+// The same chunk routine serves one-query-per-launch (grid = chunks) and
+// persistent launches (grid = resident capacity, chunks claimed from an
+// atomic cursor until none are left, so every wave exits).
+#include "pw_device.hpp"
+#include "pw_internal.hpp"
+
+namespace pw {
+
+__device__ __forceinline__ DevGraph make_graph(const GraphTables& g)
+{
+    DevGraph G;
+    G.node = g.node;
+    G.col = g.col;
+    G.adj = g.adj;
+    G.dom.n = g.dom.n;
+    G.dom.rb = g.dom.rb;
+    G.dom.mask = g.dom.mask;
+    G.dom.rsh = g.dom.rsh;
+    G.dom.A = g.dom.A;
+    G.dom.A8 = g.dom.A8;
+    return G;
+}
+
+// One transition followed by scoring the node just left: the gathers for the
+// next node are issued before the probe arithmetic of the current node, so
+// the ALU work overlaps the memory latency. Terms still enter the binary32
+// sum in step order X_0, X_1, ..., X_L.
+template <int kFat>
+__device__ __forceinline__ float advance(WalkState& w, float acc, uint32_t u, const DevGraph& G,
+                                         const Probe& pr)
+{
+    const uint32_t xp = w.x;
+    const float ip = w.inv;
+    step<kFat>(w, u, G);
+    return add_term(acc, xp, ip, pr, G.dom);
+}
+
+// U_p = a - b for replica p of probe k (Algorithm 1 walk loop, eq. for phi-hat).
+template <int kFat>
+__device__ __forceinline__ float walk_pair(const DevGraph& G, const Probe& pr, WalkState ws,
+                                           WalkState wt, int L, uint32_t p, uint32_t k,
+                                           uint32_t uid, uint32_t slo, uint32_t shi)
+{
+    float a = 0.0f, b = 0.0f;
+    const uint32_t cs = uid << 1, ct = (uid << 1) | 1u;
+    const int full = L >> 2;
+    for (int blk = 0; blk < full; ++blk) {
+        const U4 rs = philox10((uint32_t)blk, p, k, cs, slo, shi);
+        const U4 rt = philox10((uint32_t)blk, p, k, ct, slo, shi);
+        a = advance<kFat>(ws, a, rs.x, G, pr);
+        b = advance<kFat>(wt, b, rt.x, G, pr);
+        a = advance<kFat>(ws, a, rs.y, G, pr);
+        b = advance<kFat>(wt, b, rt.y, G, pr);
+        a = advance<kFat>(ws, a, rs.z, G, pr);
+        b = advance<kFat>(wt, b, rt.z, G, pr);
+        a = advance<kFat>(ws, a, rs.w, G, pr);
+        b = advance<kFat>(wt, b, rt.w, G, pr);
+    }
+    const int rem = L & 3;
+    if (rem) {
+        const U4 rs = philox10((uint32_t)full, p, k, cs, slo, shi);
+        const U4 rt = philox10((uint32_t)full, p, k, ct, slo, shi);
+        a = advance<kFat>(ws, a, rs.x, G, pr);
+        b = advance<kFat>(wt, b, rt.x, G, pr);
+        if (rem > 1) {
+            a = advance<kFat>(ws, a, rs.y, G, pr);
+            b = advance<kFat>(wt, b, rt.y, G, pr);
+        }
+        if (rem > 2) {
+            a = advance<kFat>(ws, a, rs.z, G, pr);
+            b = advance<kFat>(wt, b, rt.z, G, pr);
+        }
+    }
+    a = add_term(a, ws.x, ws.inv, pr, G.dom);
+    b = add_term(b, wt.x, wt.inv, pr, G.dom);
+    return __fsub_rn(a, b);
+}
+
+__device__ __forceinline__ void lds_add_i128(unsigned long long* p, i128 v)
+{
+    const unsigned long long lo = (unsigned long long)(u128)v;
+    const unsigned long long hi = (unsigned long long)((u128)v >> 64);
+    const unsigned long long old = atomicAdd(p, lo);
+    const unsigned long long carry = (old + lo < old) ? 1ull : 0ull;
+    atomicAdd(p + 1, hi + carry);
+}
+
+// Median of the G block means (section 3.2, Algorithm 1 final loop).
+__device__ void finalize_query(const WalkArgs& A, const QueryDesc& d, double* ys)
+{
+    const uint32_t G = d.G;
+    const unsigned long long* bs = A.blocksum + (size_t)d.slot * A.gdim * 2;
+    for (uint32_t g = 0; g < G; ++g) {
+        const double y = (i128_to_f64(load_i128(bs + 2 * g)) * 0x1p-64) / (double)d.B;
+        ys[g] = y;
+        if (A.ybar_debug) A.ybar_debug[g] = y;
+    }
+    for (uint32_t i = 1; i < G; ++i) {
+        const double v = ys[i];
+        uint32_t j = i;
+        while (j > 0 && ys[j - 1] > v) {
+            ys[j] = ys[j - 1];
+            --j;
+        }
+        ys[j] = v;
+    }
+    const double med = (G & 1u) ? ys[G / 2] : 0.5 * (ys[G / 2 - 1] + ys[G / 2]);
+    A.beta[d.slot] = med;
+    if (A.recycle) {
+        // every chunk of this query has finished: the slot can be cleared for reuse
+        unsigned long long* w = A.blocksum + (size_t)d.slot * A.gdim * 2;
+        for (uint32_t g = 0; g < 2 * A.gdim; ++g) w[g] = 0ull;
+        A.done[d.slot] = 0u;
+    }
+    if (A.comp_ring) {
+        const uint32_t i = atomicAdd(A.comp_count, 1u);
+        Completion c;
+        c.slot = d.slot;
+        c.pad = 0u;
+        c.beta = med;
+        A.comp_ring[i % A.comp_cap] = c;
+    }
+    __threadfence();
+}
+
+template <int kFat>
+__device__ void run_chunk(const WalkArgs& A, const DevGraph& G, uint32_t ci,
+                          unsigned long long* acc, double* ys)
+{
+    const Chunk c = A.chunks[ci];
+    const QueryDesc d = A.qd[c.q];
+    const int tid = threadIdx.x;
+    for (uint32_t j = tid; j < c.kc * 4u; j += kBlockThreads) acc[j] = 0ull;
+    __syncthreads();
+
+    const WalkState s0 = start_state((uint32_t)d.s, G.node[d.s]);
+    const WalkState t0 = start_state((uint32_t)d.t, G.node[d.t]);
+    const uint64_t total = (uint64_t)c.kc * d.R;
+    for (uint64_t base = 0; base < total; base += kBlockThreads) {
+        const uint64_t w = base + (uint64_t)tid;
+        if (w < total) {
+            const uint32_t kk = (uint32_t)(w / d.R);
+            const uint32_t p = (uint32_t)(w - (uint64_t)kk * d.R);
+            const uint32_t k = c.k0 + kk;
+            const Probe pr = make_probe(d.seed_lo, d.seed_hi, d.uid, k, G.dom.n);
+            const float U = walk_pair<kFat>(G, pr, s0, t0, d.L, p, k, d.uid, d.seed_lo, d.seed_hi);
+            lds_add_i128(acc + 4 * kk, fix54(U));
+            lds_add_i128(acc + 4 * kk + 2, (i128)sqfix64(U));
+        }
+    }
+    __syncthreads();
+
+    for (uint32_t j = tid; j < c.kc; j += kBlockThreads) {
+        const i128 S1 = (i128)(((u128)acc[4 * j + 1] << 64) | (u128)acc[4 * j]);
+        const u128 S2 = ((u128)acc[4 * j + 3] << 64) | (u128)acc[4 * j + 2];
+        const double Q = probe_q(S1, S2, d.R);
+        const uint32_t k = c.k0 + j;
+        if (A.q_debug) A.q_debug[k] = Q;
+        atomic_add_i128(A.blocksum + ((size_t)d.slot * A.gdim + k / d.B) * 2,
+                        f64_to_i128_trunc(Q * 0x1p64));
+    }
+    __threadfence();
+    __syncthreads();
+    if (tid == 0) {
+        const uint32_t old = atomicAdd(A.done + d.slot, c.kc);
+        if (old + c.kc == d.K) {
+            __threadfence();
+            finalize_query(A, d, ys);
+        }
+    }
+    __syncthreads();
+}
+
+template <int kFat>
+__global__ __launch_bounds__(kBlockThreads) void walk_kernel(WalkArgs A)
+{
+    __shared__ unsigned long long acc[kMaxChunkProbes * 4];
+    __shared__ double ys[kMaxG];
+    __shared__ uint32_t next;
+    const DevGraph G = make_graph(A.g);
+    if (!A.persistent) {
+        if (blockIdx.x < A.nchunks) run_chunk<kFat>(A, G, blockIdx.x, acc, ys);
+        return;
+    }
+    for (;;) {
+        if (threadIdx.x == 0) next = atomicAdd(A.cursor, 1u);
+        __syncthreads();
+        const uint32_t ci = next;
+        __syncthreads();
+        if (ci >= A.nchunks) break;
+        run_chunk<kFat>(A, G, ci, acc, ys);
+    }
+}
+
+hipError_t launch_walk(const WalkArgs& a, int fat, uint32_t grid, hipStream_t st)
+{
+    if (grid == 0) return hipSuccess;
+    if (fat) hipLaunchKernelGGL(walk_kernel<1>, dim3(grid), dim3(kBlockThreads), 0, st, a);
+    else hipLaunchKernelGGL(walk_kernel<0>, dim3(grid), dim3(kBlockThreads), 0, st, a);
+    return hipGetLastError();
+}
+
+int walk_occupancy(int fat, int* wgs_per_cu)
+{
+    int nb = 0;
+    hipError_t e = fat ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, walk_kernel<1>, kBlockThreads, 0)
+                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, walk_kernel<0>, kBlockThreads, 0);
+    if (e != hipSuccess) return -1;
+    *wgs_per_cu = nb;
+    return 0;
+}
+
+// ---------------------------------------------------------------------------
+// Small utility kernels
+// ---------------------------------------------------------------------------
+__global__ void zero_kernel(uint32_t* p, size_t words)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < words;
+         i += (size_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
+}
+
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t st)
+{
+    const size_t words = (bytes + 3) / 4;
+    if (words == 0) return hipSuccess;
+    size_t blocks = (words + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(zero_kernel, dim3((uint32_t)blocks), dim3(256), 0, st, (uint32_t*)p, words);
+    return hipGetLastError();
+}
+
+__global__ void fat_kernel(const uint4* node, const uint32_t* col, uint4* adj, uint32_t nnz)
+{
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nnz; i += gridDim.x * blockDim.x) {
+        const uint32_t x = col[i];
+        const uint4 e = node[x];
+        adj[i] = make_uint4(x, e.x, e.y, e.z);
+    }
+}
+
+hipError_t build_fat_adjacency(const uint4* node, const uint32_t* col, uint4* adj, uint32_t nnz,
+                               hipStream_t st)
+{
+    if (nnz == 0) return hipSuccess;
+    uint32_t blocks = (nnz + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(fat_kernel, dim3(blocks), dim3(256), 0, st, node, col, adj, nnz);
+    return hipGetLastError();
+}
+
+// One walk per thread, recording X_0..X_L and the binary32 sum of z/d; the
+// transitions and the scoring are the production ones (advance / add_term).
+template <int kFat>
+__global__ void trace_kernel(GraphTables gt, uint32_t count, const int32_t* start,
+                             const uint32_t* uid, const uint32_t* kk, const uint32_t* pp,
+                             const uint32_t* side, int32_t L, uint32_t slo, uint32_t shi,
+                             int32_t* trace, float* acc_out)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const DevGraph G = make_graph(gt);
+    const uint32_t x0 = (uint32_t)start[i];
+    const Probe pr = make_probe(slo, shi, uid[i], kk[i], G.dom.n);
+    WalkState w = start_state(x0, G.node[x0]);
+    const uint32_t c3 = (uid[i] << 1) | side[i];
+    int32_t* tr = trace ? trace + (size_t)i * (L + 1) : nullptr;
+    if (tr) tr[0] = (int32_t)x0;
+    float a = 0.0f;
+    U4 r = U4{0, 0, 0, 0};
+    for (int s = 0; s < L; ++s) {
+        if ((s & 3) == 0) r = philox10((uint32_t)(s >> 2), pp[i], kk[i], c3, slo, shi);
+        const uint32_t u = (s & 3) == 0 ? r.x : (s & 3) == 1 ? r.y : (s & 3) == 2 ? r.z : r.w;
+        a = advance<kFat>(w, a, u, G, pr);
+        if (tr) tr[s + 1] = (int32_t)w.x;
+    }
+    a = add_term(a, w.x, w.inv, pr, G.dom);
+    if (acc_out) acc_out[i] = a;
+}
+
+hipError_t launch_trace(const GraphTables& g, int fat, uint32_t count, const int32_t* start,
+                        const uint32_t* uid, const uint32_t* k, const uint32_t* p,
+                        const uint32_t* side, int32_t L, uint32_t slo, uint32_t shi,
+                        int32_t* trace, float* acc, hipStream_t st)
+{
+    if (count == 0) return hipSuccess;
+    const uint32_t blocks = (count + 127) / 128;
+    if (fat)
+        hipLaunchKernelGGL(trace_kernel<1>, dim3(blocks), dim3(128), 0, st, g, count, start, uid, k, p,
+                           side, L, slo, shi, trace, acc);
+    else
+        hipLaunchKernelGGL(trace_kernel<0>, dim3(blocks), dim3(128), 0, st, g, count, start, uid, k, p,
+                           side, L, slo, shi, trace, acc);
+    return hipGetLastError();
+}
+
+__global__ void probe_kernel(GraphTables gt, uint32_t slo, uint32_t shi, uint32_t uid, uint32_t k,
+                             uint32_t count, const uint32_t* nodes, uint32_t* pi, int8_t* z)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const DevGraph G = make_graph(gt);
+    const Probe pr = make_probe(slo, shi, uid, k, G.dom.n);
+    uint32_t y = 0;
+    const int v = probe_value(nodes[i], pr, G.dom, &y);
+    if (pi) pi[i] = y;
+    if (z) z[i] = (int8_t)v;
+}
+
+hipError_t launch_probe_eval(const GraphTables& g, uint32_t slo, uint32_t shi, uint32_t uid,
+                             uint32_t k, uint32_t count, const uint32_t* nodes, uint32_t* pi,
+                             int8_t* z, hipStream_t st)
+{
+    if (count == 0) return hipSuccess;
+    hipLaunchKernelGGL(probe_kernel, dim3((count + 255) / 256), dim3(256), 0, st, g, slo, shi, uid, k,
+                       count, nodes, pi, z);
+    return hipGetLastError();
+}
+
+}  // namespace pw

@@ -1,0 +1,81 @@
+"""The C ABI library loads and exports what include/probewalk.h declares, and its
+host-side graph checks reject bad input before any device work (CPU only)."""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2512_05460_amd import binding
+from synth import graphs
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include",
+                      "probewalk.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return set(re.findall(r"^\s*(?:int|void|const char\*)\s+\**(\w+)\s*\(", text, flags=re.M))
+
+
+def test_header_symbols_exported():
+    names = _declared()
+    assert "graph_load_csr" in names and "bd_query_batch" in names
+    lib = ctypes.CDLL(binding.LIB_PATH)
+    for name in names:
+        assert hasattr(lib, name), name
+    assert names == set(binding.EXPORTS)
+
+
+def test_strerror():
+    assert binding.strerror(0) == "ok"
+    assert "graph" in binding.strerror(binding.BD_E_GRAPH)
+    assert binding.strerror(12345) == "unknown error"
+
+
+def _load(n, rp, col):
+    h = ctypes.c_void_p()
+    rp = np.ascontiguousarray(rp, dtype=np.int64)
+    col = np.ascontiguousarray(col, dtype=np.int32)
+    return binding.lib().graph_load_csr(n, rp.ctypes.data_as(ctypes.c_void_p),
+                                        col.ctypes.data_as(ctypes.c_void_p), 0, None, ctypes.byref(h))
+
+
+def test_graph_checks_reject_bad_input():
+    # asymmetric: 0->1 without 1->0
+    assert _load(3, [0, 2, 3, 4], [1, 2, 2, 0]) == binding.BD_E_GRAPH
+    # self-loop
+    assert _load(2, [0, 2, 3], [0, 1, 0]) == binding.BD_E_GRAPH
+    # unsorted row
+    g = graphs.complete_graph(4)
+    col = g.col.copy()
+    col[0], col[1] = col[1], col[0]
+    assert _load(4, g.row_ptr, col) == binding.BD_E_GRAPH
+    # duplicate edge
+    assert _load(2, [0, 2, 4], [1, 1, 0, 0]) == binding.BD_E_GRAPH
+    # disconnected: two separate edges
+    assert _load(4, [0, 1, 2, 3, 4], [1, 0, 3, 2]) == binding.BD_E_GRAPH
+    # isolated node
+    assert _load(3, [0, 1, 2, 2], [1, 0]) == binding.BD_E_GRAPH
+    # out-of-range id
+    assert _load(2, [0, 1, 2], [5, 0]) == binding.BD_E_GRAPH
+    # sizes
+    assert _load(1, [0, 0], []) == binding.BD_E_RANGE
+
+
+def test_result_layout_matches_header():
+    assert binding.RESULT_DTYPE.itemsize == 48
+    assert ctypes.sizeof(binding.BdPolicy) == 56
+    assert ctypes.sizeof(binding.BdExec) == 16
+    assert ctypes.sizeof(binding.BdStats) == 48
+    assert ctypes.sizeof(binding.BdServerCfg) == 88
+
+
+def test_binding_has_no_fallback(monkeypatch, tmp_path):
+    monkeypatch.setattr(binding, "LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(binding, "_lib", None)
+    with pytest.raises(ImportError):
+        binding.lib()
