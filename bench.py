@@ -1,0 +1,217 @@
+"""Throughput benchmark of the ProbeWalk hot path on one MI355X.
+
+Workload: Chung-Lu graph n=100,000, mean degree 10, exponent 2.5, largest
+connected component (99,163 nodes, 997,038 adjacency entries); uniform (s,t)
+pairs; eps = 0.05, L = 1000; walk counts from the scaled policy of Algorithm 1
+(constants in paper_2512_05460_amd/budgets.py). One step = one batch of
+queries run in the plain mode (one query per launch, fixed tiling). The same
+batch is also run in the batched (persistent, work-stealing) mode.
+
+Prints one JSON line. The graph and the query descriptors are resident on the
+device before the timed region; each query's descriptor travels host->device
+inside the call (48 bytes) and its result device->host.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+WORKLOAD = "cl100k"
+EPS = 0.05
+L = 1000
+BYTES_PER_STEP = 12   # next node id + its row offset and degree (4 + 4 + 4 bytes)
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(g, s, t, plans, seed, target_s=20.0):
+    """The oracle on a bounded sample: each of `threads` queries runs its first
+    few probes at the full R and L; queries/s is the measured step rate divided
+    by the mean full-query step count."""
+    from oracle import estimator as E
+
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    threads = max(1, min(16, cores))
+    nq = threads
+    sub = [plans[i] for i in range(nq)]
+    per_probe = np.array([2 * p[3] * L for p in sub], dtype=np.float64)
+    # calibrate probe counts for ~target_s of work: oracle speed ~1.5e7 steps/s/thread
+    kend = np.maximum(1, np.minimum([p[2] for p in sub], (1.5e7 * target_s / per_probe).astype(np.int64)))
+    t0 = time.perf_counter()
+    E.estimate(g, s[:nq], t[:nq], L, sub, seed, uid=np.arange(nq), threads=threads, k_end=kend)
+    dt = time.perf_counter() - t0
+    steps = float((kend * per_probe).sum())
+    full = np.array([2.0 * p[2] * p[3] * L for p in plans], dtype=np.float64)
+    sps = steps / dt
+    return {"value": sps / full.mean(), "unit": "queries/s", "cores": threads, "kind": "oracle",
+            "walk_steps_per_s": sps,
+            "sample": (f"{nq} of the step's queries, first {int(kend.min())}-{int(kend.max())} probes each at "
+                       f"full R and L, one query per thread; {steps:.3e} walk steps in {dt:.1f} s; "
+                       "queries/s = steps/s / mean full-query steps")}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--queries", type=int, default=64, help="queries per step")
+    ap.add_argument("--layout", choices=["csr", "fat"], default="csr")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calib", type=int, default=0,
+                    help="also run a torch copy of this many MiB (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: the estimator's queries shard across GPUs "
+              "with no exchange but a few block sums, and this build measures one GPU's share.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2512_05460_amd import binding as B
+    from paper_2512_05460_amd.budgets import BUDGETS, budget_policy
+    from synth import graphs, queries
+
+    torch.cuda.set_device(0)
+    dev = B.bd_device_info()
+    log("device:", dev)
+    g = graphs.workload_graph(WORKLOAD)
+    s_all, t_all = queries.uniform_pairs(g.n, 4096, graphs.GRAPH_SEED + 1 + graphs.QUERY_SEED_OFFSET)
+    nq = args.queries
+    s, t = s_all[:nq], t_all[:nq]
+    layout = B.BD_LAYOUT_FAT if args.layout == "fat" else B.BD_LAYOUT_CSR
+    dg = B.graph_load_csr(g.n, g.row_ptr, g.col, layout)
+    pol = budget_policy(WORKLOAD)
+    seed = graphs.PHILOX_SEED
+    plan = B.bd_plan(dg, s, t, EPS, L, pol)
+    assert np.all(plan["status"] == 0), plan["status"]
+    steps_per_batch = float(plan["walk_steps"].sum())
+    log(f"batch: {nq} queries, K={int(plan['K'][0])}, R median {int(np.median(plan['R']))} "
+        f"max {int(plan['R'].max())}, {steps_per_batch:.3e} walk steps")
+    plain = B.exec_cfg("plain")
+    stream = torch.cuda.current_stream()
+
+    def run_plain():
+        lat, kms, launches = [], 0.0, 0
+        for i in range(nq):
+            t0 = time.perf_counter()
+            r, st = B.bd_query_batch(dg, s[i:i + 1], t[i:i + 1], EPS, L, seed, pol, plain, uid=[i],
+                                     stream=stream, with_stats=True)
+            lat.append((time.perf_counter() - t0) * 1e3)
+            kms += st["walk_kernel_ms"]
+            launches += st["launches"]
+            assert r["status"][0] == 0
+        return lat, kms, launches
+
+    for w in range(args.warmup):
+        log(f"warmup {w + 1}/{args.warmup}")
+        run_plain()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lat_all, kms_all, launches_all = [], 0.0, 0
+    for k in range(args.steps):
+        lat, kms, launches = run_plain()
+        lat_all += lat
+        kms_all += kms
+        launches_all += launches
+        log(f"step {k + 1}/{args.steps}: {sum(lat):.0f} ms")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    qps = nq * args.steps / elapsed
+    walk_sps = steps_per_batch * args.steps / elapsed
+    kernel_sps = steps_per_batch * args.steps / (kms_all / 1e3)
+    achieved_gbs = kernel_sps * BYTES_PER_STEP / 1e9
+
+    extra = {}
+    if not args.no_batched:
+        log("batched mode, same batch")
+        B.bd_query_batch(dg, s, t, EPS, L, seed, pol, B.exec_cfg("batched"), stream=stream)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        r, st = B.bd_query_batch(dg, s, t, EPS, L, seed, pol, B.exec_cfg("batched"), stream=stream,
+                                 with_stats=True)
+        torch.cuda.synchronize()
+        dtb = time.perf_counter() - t1
+        extra["batched"] = {"queries_per_s": nq / dtb, "walk_steps_per_s": steps_per_batch / dtb,
+                            "kernel_ms": st["walk_kernel_ms"], "vs_plain": (nq / dtb) / qps}
+    if args.copy_calib:
+        n = args.copy_calib * (1 << 20) // 4
+        x = torch.empty(n, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+        extra["copy_calib_bytes"] = n * 4
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import planner as OP
+        c_B, c_R, _ = BUDGETS[WORKLOAD]
+        op = OP.Policy("scaled", c_B=c_B, c_R=c_R)
+        plans = [OP.plan(EPS, L, int(g.deg[s[i]]), int(g.deg[t[i]]), g.d_min, op) for i in range(nq)]
+        log("cpu baseline (oracle, bounded sample)")
+        cpu = cpu_baseline(g, s, t, plans, seed)
+
+    c_B, c_R, how = BUDGETS[WORKLOAD]
+    out = {
+        "metric": "queries/s at eps=0.05, L=1000",
+        "value": qps,
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": ("Chung-Lu n=100,000 mean degree 10 exponent 2.5 LCC; uniform (s,t) pairs; "
+                         "eps=0.05, L=1000; plain mode, one query per launch"),
+            "queries_per_step": nq,
+            "layout": args.layout,
+            "policy": {"kind": "scaled", "c_B": c_B, "c_R": c_R, "delta": 0.01, "calibration": how},
+            "K": int(plan["K"][0]), "R_median": int(np.median(plan["R"])),
+            "walk_steps_per_step": steps_per_batch,
+        },
+        "walk_steps_per_s": walk_sps,
+        "latency_ms": {"p50": float(np.percentile(lat_all, 50)), "p99": float(np.percentile(lat_all, 99))},
+        "roofline": {
+            "bound": "hbm",
+            "achieved": achieved_gbs,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved_gbs / HBM_PEAK_GBS,
+            "traffic": None,
+            "kernel": "walk_kernel",
+            "avg_launch_ms": kms_all / max(1, launches_all),
+            "kernel_walk_steps_per_s": kernel_sps,
+            "bytes_per_step": BYTES_PER_STEP,
+        },
+        "cpu_baseline": cpu,
+        "device": dev,
+        **extra,
+    }
+    print(json.dumps(out), flush=True)
+    dg.free()
+
+
+if __name__ == "__main__":
+    main()

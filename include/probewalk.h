@@ -60,13 +60,19 @@ typedef struct bd_graph bd_graph;
                                    its degree, its 1/degree}: one gather per walk step */
 #define BD_SKIP_VALIDATION  2u  /* trust the caller: skip the symmetry, sortedness and
                                    connectivity checks (ranges are still checked) */
+#define BD_RELABEL_DEGREE   4u  /* store nodes in descending-degree order (locality of the
+                                   node table); ids at the ABI, neighbour order and every
+                                   result are unchanged */
+#define BD_LAYOUT_COMPACT   8u  /* 32-bit row offsets + 3-byte neighbour ids, 1/degree
+                                   recomputed: the smallest footprint (n <= 2^24; not with
+                                   BD_LAYOUT_FAT or BD_RELABEL_DEGREE) */
 
 typedef struct {
     int64_t  n, nnz;
     int32_t  d_min, d_max;
     int32_t  bipartite;      /* 1 if the graph is bipartite (section 2.1 assumes not;
                                 the estimator still targets beta^(L)) */
-    int32_t  layout;         /* BD_LAYOUT_CSR or BD_LAYOUT_FAT */
+    int32_t  layout;         /* 0 CSR, 1 fat, 2 compact */
     int64_t  device_bytes;   /* device memory held by the graph tables */
 } bd_graph_info;
 
@@ -186,6 +192,26 @@ int bd_probe_eval(bd_graph* g, uint64_t seed, uint32_t uid, uint32_t k, int64_t 
 int bd_query_probes(bd_graph* g, int32_t s, int32_t t, double eps, int32_t L, uint32_t uid,
                     uint64_t seed, const bd_policy* pol, const bd_exec* exec, void* stream,
                     double* q_out, double* ybar_out, bd_result* out);
+
+/* ---- measurement -------------------------------------------------------------- */
+typedef struct {
+    double  ms;               /* kernel time (HIP events) */
+    double  steps_per_s;      /* transitions per second */
+    double  gathers_per_s;    /* dependent loads per second (2 per step, or 1 with BD_LAYOUT_FAT) */
+    int64_t steps;            /* transitions executed */
+    int32_t chains_per_lane;
+    int32_t work_groups;
+} bd_roofline;
+
+/*
+ * Random-gather roofline of the loaded graph (measurement for section 3.2's walk
+ * loop): lanes run `chains_per_lane` (1, 2, 4 or 8) independent chains of
+ * `steps` transitions with exactly the walk kernel's dependent loads on the
+ * same tables, but a cheap xorshift instead of Philox and no probe arithmetic.
+ * work_groups = 0 picks 4x the resident capacity.
+ */
+int bd_gather_roofline(bd_graph* g, int32_t chains_per_lane, int32_t steps, int32_t work_groups,
+                       void* stream, bd_roofline* out);
 
 /* ---- served mode: continuous batching ---------------------------------------- */
 typedef struct bd_server bd_server;

@@ -7,6 +7,11 @@ of the estimator runs in the HIP library. Streams come from PyTorch
 
 The library must have been built (``python -m paper_2512_05460_amd.build``);
 there is no fallback of any kind when it is missing.
+
+PyTorch ships its own HIP runtime under the same SONAME as the system one.
+``lib()`` imports torch before loading ``libprobewalk.so`` so that the
+library binds to the runtime torch already loaded: one HIP runtime per
+process, in which torch's streams and our calls live together.
 """
 
 from __future__ import annotations
@@ -35,6 +40,8 @@ BD_E_TIMEOUT = -11
 BD_LAYOUT_CSR = 0
 BD_LAYOUT_FAT = 1
 BD_SKIP_VALIDATION = 2
+BD_RELABEL_DEGREE = 4
+BD_LAYOUT_COMPACT = 8
 
 BD_POLICY_PAPER = 0
 BD_POLICY_SCALED = 1
@@ -47,7 +54,7 @@ BD_MODE_BATCHED = 1
 EXPORTS = ("graph_load_csr", "graph_free", "bd_graph_get_info", "bd_plan", "bd_query_batch",
            "bd_walk_trace", "bd_probe_eval", "bd_query_probes", "bd_server_create",
            "bd_server_submit", "bd_server_poll", "bd_server_wait", "bd_server_destroy",
-           "bd_strerror", "bd_device_info")
+           "bd_strerror", "bd_device_info", "bd_gather_roofline")
 
 
 class BdPolicy(ctypes.Structure):
@@ -74,6 +81,12 @@ class BdGraphInfo(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("d_min", ctypes.c_int32),
                 ("d_max", ctypes.c_int32), ("bipartite", ctypes.c_int32), ("layout", ctypes.c_int32),
                 ("device_bytes", ctypes.c_int64)]
+
+
+class BdRoofline(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double), ("steps_per_s", ctypes.c_double),
+                ("gathers_per_s", ctypes.c_double), ("steps", ctypes.c_int64),
+                ("chains_per_lane", ctypes.c_int32), ("work_groups", ctypes.c_int32)]
 
 
 class BdServerCfg(ctypes.Structure):
@@ -103,6 +116,8 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with "
                               "`python -m paper_2512_05460_amd.build`")
+        import torch  # noqa: F401  (bind to the HIP runtime torch loads)
+
         L = ctypes.CDLL(LIB_PATH)
         i32, i64, u32, u64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64
         sig = {
@@ -125,6 +140,7 @@ def lib():
             "bd_server_destroy": (None, [_P]),
             "bd_strerror": (ctypes.c_char_p, [ctypes.c_int]),
             "bd_device_info": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_size_t]),
+            "bd_gather_roofline": (ctypes.c_int, [_P, i32, i32, i32, _P, ctypes.POINTER(BdRoofline)]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -350,3 +366,11 @@ def bd_device_info() -> str:
     rc = lib().bd_device_info(buf, 512)
     _check(rc, "bd_device_info")
     return buf.value.decode()
+
+
+def bd_gather_roofline(g: Graph, chains_per_lane: int = 4, steps: int = 2000, work_groups: int = 0,
+                       stream=None) -> dict:
+    r = BdRoofline()
+    _check(lib().bd_gather_roofline(g.handle, chains_per_lane, steps, work_groups, _stream(stream),
+                                    ctypes.byref(r)), "bd_gather_roofline")
+    return {f: getattr(r, f) for f, _ in r._fields_}

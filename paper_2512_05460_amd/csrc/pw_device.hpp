@@ -157,13 +157,25 @@ __device__ __forceinline__ int probe_value(uint32_t x, const Probe& pr, const Do
 // ---------------------------------------------------------------------------
 // Graph tables and one walk transition
 // ---------------------------------------------------------------------------
-// Node table entry: {row offset, degree, bits of 1.0f/degree, 0}.
-// Fat adjacency entry at position row_ptr[x] + j:
-//   {neighbour id, its row offset, its degree, bits of its 1.0f/degree}.
+// Node table entry, indexed by the internal (storage) id of a node:
+//   {row offset, degree, bits of 1.0f/degree, original id}.
+// Internal ids may be a relabelling of the caller's ids (hubs first, for
+// locality); rows keep the caller's neighbour order, and the probe is always
+// evaluated on the original id, so trajectories do not depend on the storage.
+// Fat adjacency entry at position row_offset(x) + j:
+//   {neighbour's original id, its row offset, its degree, bits of its 1.0f/degree}.
+//
+// Compact layout (ids as given, n <= 2^24): row offsets rp[0..n] as uint32 and
+// neighbour ids packed in 3 bytes each; 1.0f/degree is recomputed (correctly
+// rounded) at every step instead of stored.
+constexpr int kLayoutCsr = 0, kLayoutFat = 1, kLayoutCompact = 2;
+
 struct DevGraph {
-    const uint4* node;    // n entries
-    const uint32_t* col;  // nnz entries (CSR layout)
-    const uint4* adj;     // nnz entries (fat layout) or null
+    const uint4* node;      // n entries (CSR and fat layouts)
+    const uint32_t* col;    // nnz entries (CSR layout)
+    const uint4* adj;       // nnz entries (fat layout)
+    const uint32_t* rp;     // n + 1 entries (compact layout)
+    const uint32_t* col24;  // 3 nnz bytes + padding, read as aligned words (compact layout)
     Domain dom;
 };
 
@@ -172,27 +184,57 @@ struct WalkState {
     float inv;
 };
 
-__device__ __forceinline__ WalkState start_state(uint32_t x, uint4 e)
+__device__ __forceinline__ WalkState start_state(uint4 e)
 {
-    return WalkState{x, e.x, e.y, __uint_as_float(e.z)};
+    return WalkState{e.w, e.x, e.y, __uint_as_float(e.z)};
+}
+
+// Row offset and degree of node x in the compact layout (one 8-byte load).
+__device__ __forceinline__ void compact_row(const DevGraph& G, uint32_t x, WalkState& w)
+{
+    const uint32_t b = G.rp[x];
+    const uint32_t e = G.rp[x + 1];
+    w.x = x;
+    w.off = b;
+    w.deg = e - b;
+    w.inv = __fdiv_rn(1.0f, (float)w.deg);
+}
+
+// Walk state at internal id x (the start of a walk).
+template <int kLayout>
+__device__ __forceinline__ WalkState start_at(const DevGraph& G, uint32_t x)
+{
+    if (kLayout == kLayoutCompact) {
+        WalkState w;
+        compact_row(G, x, w);
+        return w;
+    }
+    return start_state(G.node[x]);
 }
 
 // Uniform neighbour: j = floor(u * d / 2^32) into the ascending neighbour list.
-template <int kFat>
+template <int kLayout>
 __device__ __forceinline__ void step(WalkState& w, uint32_t u, const DevGraph& G)
 {
     const uint32_t j = __umulhi(u, w.deg);
     const uint32_t pos = w.off + j;
-    if (kFat) {
+    if (kLayout == kLayoutFat) {
         const uint4 e = G.adj[pos];
         w.x = e.x;
         w.off = e.y;
         w.deg = e.z;
         w.inv = __uint_as_float(e.w);
+    } else if (kLayout == kLayoutCompact) {
+        // the 3 bytes at byte offset 3*pos lie in the aligned 8 bytes at word (3*pos)/4
+        const uint32_t o = pos * 3u;
+        const uint32_t wi = o >> 2;
+        const uint32_t lo = G.col24[wi];
+        const uint32_t hi = G.col24[wi + 1];
+        const uint32_t x = __builtin_amdgcn_alignbit(hi, lo, (o & 3u) * 8u) & 0xFFFFFFu;
+        compact_row(G, x, w);
     } else {
-        const uint32_t x = G.col[pos];
-        const uint4 e = G.node[x];
-        w.x = x;
+        const uint4 e = G.node[G.col[pos]];
+        w.x = e.w;
         w.off = e.x;
         w.deg = e.y;
         w.inv = __uint_as_float(e.z);

@@ -77,10 +77,11 @@ struct bd_graph {
     int64_t n = 0, nnz = 0;
     int32_t d_min = 0, d_max = 0;
     int32_t bipartite = 0;
-    int32_t layout = 0;
+    int32_t layout = 0;  // 0 CSR, 1 fat, 2 compact (kLayout* of the kernels)
     int device = 0;
-    std::vector<int32_t> deg;  // host copy for the planner
-    DevBuf node, col, adj;
+    std::vector<int32_t> deg;        // host copy for the planner, by caller id
+    std::vector<uint32_t> internal;  // caller id -> storage id (empty: identity)
+    DevBuf node, col, adj, rp32, col24;
     DomainParams dom{};
     int64_t device_bytes = 0;
     std::mutex mu;  // serialises calls that use the per-graph work buffers
@@ -181,6 +182,10 @@ extern "C" int graph_load_csr(int64_t n, const int64_t* row_ptr, const int32_t* 
         dmax = std::max<int32_t>(dmax, (int32_t)d);
     }
     if (dmin < 1) return BD_E_GRAPH;  // an isolated node: not connected
+    if (flags & BD_LAYOUT_COMPACT) {
+        if (flags & (BD_LAYOUT_FAT | BD_RELABEL_DEGREE)) return BD_E_INVALID;
+        if (n > (int64_t(1) << 24) || 3 * nnz + 8 > (int64_t)UINT32_MAX) return BD_E_RANGE;
+    }
     for (int64_t i = 0; i < nnz; ++i)
         if (col_idx[i] < 0 || col_idx[i] >= n) return BD_E_GRAPH;
     int32_t bip = 0;
@@ -202,36 +207,87 @@ extern "C" int graph_load_csr(int64_t n, const int64_t* row_ptr, const int32_t* 
     g->d_min = dmin;
     g->d_max = dmax;
     g->bipartite = bip;
-    g->layout = (flags & BD_LAYOUT_FAT) ? BD_LAYOUT_FAT : BD_LAYOUT_CSR;
+    g->layout = (flags & BD_LAYOUT_COMPACT) ? 2 : (flags & BD_LAYOUT_FAT) ? 1 : 0;
     g->device = dev;
     g->dom = make_domain((uint32_t)n);
     g->deg.resize((size_t)n);
+    for (int64_t v = 0; v < n; ++v) g->deg[(size_t)v] = (int32_t)(row_ptr[v + 1] - row_ptr[v]);
+    // storage order: caller order, or descending degree (ties by id)
+    std::vector<uint32_t> order;  // storage id -> caller id
+    std::vector<int32_t> relabelled;
+    const int32_t* col_store = col_idx;
+    if (flags & BD_RELABEL_DEGREE) {
+        order.resize((size_t)n);
+        for (int64_t v = 0; v < n; ++v) order[(size_t)v] = (uint32_t)v;
+        std::stable_sort(order.begin(), order.end(),
+                         [&](uint32_t a, uint32_t b) { return g->deg[a] > g->deg[b]; });
+        g->internal.resize((size_t)n);
+        for (int64_t i = 0; i < n; ++i) g->internal[order[(size_t)i]] = (uint32_t)i;
+        relabelled.resize((size_t)nnz);
+        int64_t pos = 0;
+        for (int64_t i = 0; i < n; ++i) {
+            const uint32_t v = order[(size_t)i];
+            for (int64_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e)
+                relabelled[(size_t)pos++] = (int32_t)g->internal[(size_t)col_idx[e]];
+        }
+        col_store = relabelled.data();
+    }
     std::vector<uint32_t> nodetab((size_t)n * 4);
-    for (int64_t v = 0; v < n; ++v) {
-        const int32_t d = (int32_t)(row_ptr[v + 1] - row_ptr[v]);
-        g->deg[(size_t)v] = d;
+    int64_t off = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        const uint32_t v = order.empty() ? (uint32_t)i : order[(size_t)i];
+        const int32_t d = g->deg[v];
         const float inv = 1.0f / (float)d;
         uint32_t bits;
         std::memcpy(&bits, &inv, 4);
-        nodetab[(size_t)v * 4 + 0] = (uint32_t)row_ptr[v];
-        nodetab[(size_t)v * 4 + 1] = (uint32_t)d;
-        nodetab[(size_t)v * 4 + 2] = bits;
-        nodetab[(size_t)v * 4 + 3] = 0u;
+        nodetab[(size_t)i * 4 + 0] = (uint32_t)off;
+        nodetab[(size_t)i * 4 + 1] = (uint32_t)d;
+        nodetab[(size_t)i * 4 + 2] = bits;
+        nodetab[(size_t)i * 4 + 3] = v;
+        off += d;
     }
     hipStream_t st = (hipStream_t)stream;
-    int rc = g->node.alloc((size_t)n * 16);
-    if (rc == BD_OK) rc = g->col.alloc((size_t)std::max<int64_t>(nnz, 1) * 4);
-    if (rc == BD_OK && g->layout == BD_LAYOUT_FAT) rc = g->adj.alloc((size_t)std::max<int64_t>(nnz, 1) * 16);
-    if (rc != BD_OK) {
-        delete g;
-        return rc;
+    int rc = BD_OK;
+    std::vector<uint32_t> rp32, packed;
+    if (g->layout == 2) {
+        // compact: 32-bit row offsets, 3-byte neighbour ids (little endian), 8 bytes of padding
+        rp32.resize((size_t)n + 1);
+        for (int64_t v = 0; v <= n; ++v) rp32[(size_t)v] = (uint32_t)row_ptr[v];
+        const size_t bytes = (size_t)(3 * nnz + 8);
+        packed.assign((bytes + 3) / 4, 0u);
+        uint8_t* b = reinterpret_cast<uint8_t*>(packed.data());
+        for (int64_t i = 0; i < nnz; ++i) {
+            const uint32_t v = (uint32_t)col_idx[i];
+            b[3 * i + 0] = (uint8_t)v;
+            b[3 * i + 1] = (uint8_t)(v >> 8);
+            b[3 * i + 2] = (uint8_t)(v >> 16);
+        }
+        rc = g->rp32.alloc(rp32.size() * 4);
+        if (rc == BD_OK) rc = g->col24.alloc(packed.size() * 4);
+        if (rc != BD_OK) {
+            delete g;
+            return rc;
+        }
+        if (hipMemcpyAsync(g->rp32.p, rp32.data(), rp32.size() * 4, hipMemcpyHostToDevice, st) != hipSuccess ||
+            hipMemcpyAsync(g->col24.p, packed.data(), packed.size() * 4, hipMemcpyHostToDevice, st) != hipSuccess) {
+            delete g;
+            return BD_E_HIP;
+        }
+    } else {
+        rc = g->node.alloc((size_t)n * 16);
+        if (rc == BD_OK) rc = g->col.alloc((size_t)std::max<int64_t>(nnz, 1) * 4);
+        if (rc == BD_OK && g->layout == 1) rc = g->adj.alloc((size_t)std::max<int64_t>(nnz, 1) * 16);
+        if (rc != BD_OK) {
+            delete g;
+            return rc;
+        }
+        if (hipMemcpyAsync(g->node.p, nodetab.data(), (size_t)n * 16, hipMemcpyHostToDevice, st) != hipSuccess ||
+            hipMemcpyAsync(g->col.p, col_store, (size_t)nnz * 4, hipMemcpyHostToDevice, st) != hipSuccess) {
+            delete g;
+            return BD_E_HIP;
+        }
     }
-    if (hipMemcpyAsync(g->node.p, nodetab.data(), (size_t)n * 16, hipMemcpyHostToDevice, st) != hipSuccess ||
-        hipMemcpyAsync(g->col.p, col_idx, (size_t)nnz * 4, hipMemcpyHostToDevice, st) != hipSuccess) {
-        delete g;
-        return BD_E_HIP;
-    }
-    if (g->layout == BD_LAYOUT_FAT &&
+    if (g->layout == 1 &&
         build_fat_adjacency(g->node.as<uint4>(), g->col.as<uint32_t>(), g->adj.as<uint4>(),
                             (uint32_t)nnz, st) != hipSuccess) {
         delete g;
@@ -241,7 +297,7 @@ extern "C" int graph_load_csr(int64_t n, const int64_t* row_ptr, const int32_t* 
         delete g;
         return BD_E_HIP;
     }
-    g->device_bytes = (int64_t)(g->node.bytes + g->col.bytes + g->adj.bytes);
+    g->device_bytes = (int64_t)(g->node.bytes + g->col.bytes + g->adj.bytes + g->rp32.bytes + g->col24.bytes);
     *out = g;
     return BD_OK;
 }
@@ -358,20 +414,27 @@ extern "C" int bd_plan(const bd_graph* g, int64_t nq, const int32_t* s, const in
 // ---------------------------------------------------------------------------
 namespace {
 
+uint32_t storage_id(const bd_graph* g, int32_t v)
+{
+    return g->internal.empty() ? (uint32_t)v : g->internal[(size_t)v];
+}
+
 GraphTables tables(const bd_graph* g)
 {
     GraphTables t{};
     t.node = g->node.as<const uint4>();
     t.col = g->col.as<const uint32_t>();
     t.adj = g->adj.as<const uint4>();
+    t.rp = g->rp32.as<const uint32_t>();
+    t.col24 = g->col24.as<const uint32_t>();
     t.dom = g->dom;
     return t;
 }
 
-int resident_wgs(const bd_graph* g)
+int resident_wgs(const bd_graph* g, int uniform)
 {
     int per_cu = 0;
-    if (walk_occupancy(g->layout == BD_LAYOUT_FAT, &per_cu) != 0 || per_cu < 1) per_cu = 1;
+    if (walk_occupancy(g->layout, uniform, &per_cu) != 0 || per_cu < 1) per_cu = 1;
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, g->device) != hipSuccess) return per_cu * 256;
     return per_cu * prop.multiProcessorCount;
@@ -399,6 +462,7 @@ struct Batch {
     std::vector<uint32_t> chunk_begin;  // per valid query, first chunk (chunks grouped by query)
     std::vector<int64_t> index;         // valid query -> caller's index
     uint32_t G = 0;
+    uint32_t n_uniform = 0;             // chunks [0, n_uniform) belong to queries with R >= kUniformMinR
 };
 
 // Run one set of valid queries: zero the tables, launch, read the results.
@@ -435,7 +499,7 @@ int run_batch(bd_graph* g, const Batch& b, const bd_exec& ex, hipStream_t st,
     a.beta = d_beta.as<double>();
     a.q_debug = q_dbg_host ? d_qdbg.as<double>() : nullptr;
     a.ybar_debug = y_dbg_host ? d_ydbg.as<double>() : nullptr;
-    const int fat = g->layout == BD_LAYOUT_FAT;
+    const int layout = g->layout;
 
     hipEvent_t e0 = nullptr, e1 = nullptr;
     HIP_TRY(hipEventCreate(&e0));
@@ -446,9 +510,10 @@ int run_batch(bd_graph* g, const Batch& b, const bd_exec& ex, hipStream_t st,
     double kernel_ms = 0.0;
     int64_t launches = 0;
     int status = BD_OK;
-    auto timed_launch = [&](const WalkArgs& args, uint32_t grid) -> int {
+    auto timed_launch = [&](const WalkArgs& args, int uniform, uint32_t grid) -> int {
+        if (grid == 0) return BD_OK;
         if (hipEventRecord(e0, st) != hipSuccess) return BD_E_HIP;
-        if (launch_walk(args, fat, grid, st) != hipSuccess) return BD_E_HIP;
+        if (launch_walk(args, layout, uniform, grid, st) != hipSuccess) return BD_E_HIP;
         if (hipEventRecord(e1, st) != hipSuccess) return BD_E_HIP;
         if (hipEventSynchronize(e1) != hipSuccess) return BD_E_HIP;
         float ms = 0.f;
@@ -466,16 +531,23 @@ int run_batch(bd_graph* g, const Batch& b, const bd_exec& ex, hipStream_t st,
             aq.chunks = d_chunks.as<const Chunk>() + c0;
             aq.nchunks = c1 - c0;
             aq.persistent = 0;
-            status = timed_launch(aq, c1 - c0);
+            status = timed_launch(aq, b.qd[q].R >= kUniformMinR, c1 - c0);
         }
     } else {
-        WalkArgs ab = a;
-        ab.chunks = d_chunks.as<const Chunk>();
-        ab.nchunks = (uint32_t)b.chunks.size();
-        ab.persistent = 1;
-        uint32_t grid = ex.grid_wgs > 0 ? (uint32_t)ex.grid_wgs : (uint32_t)resident_wgs(g);
-        grid = std::min<uint32_t>(grid, ab.nchunks);
-        status = timed_launch(ab, grid);
+        // chunks of queries with R >= kUniformMinR come first (wave-uniform
+        // kernel), then the rest; one persistent launch each, own cursor
+        const uint32_t parts[3] = {0u, b.n_uniform, (uint32_t)b.chunks.size()};
+        for (int part = 0; part < 2 && status == BD_OK; ++part) {
+            WalkArgs ab = a;
+            ab.chunks = d_chunks.as<const Chunk>() + parts[part];
+            ab.nchunks = parts[part + 1] - parts[part];
+            ab.cursor = d_cursor.as<uint32_t>() + part;
+            ab.persistent = 1;
+            const int uniform = part == 0;
+            uint32_t grid = ex.grid_wgs > 0 ? (uint32_t)ex.grid_wgs : (uint32_t)resident_wgs(g, uniform);
+            grid = std::min<uint32_t>(grid, ab.nchunks);
+            status = timed_launch(ab, uniform, grid);
+        }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -502,8 +574,8 @@ void build_batch(const bd_graph* g, int64_t nq, const int32_t* s, const int32_t*
         const bd_result& r = plans[i];
         if (r.status != BD_OK) continue;
         QueryDesc d{};
-        d.s = s[i];
-        d.t = t[i];
+        d.s = (int32_t)storage_id(g, s[i]);
+        d.t = (int32_t)storage_id(g, t[i]);
         d.L = L[i];
         d.uid = uid ? uid[i] : (uint32_t)i;
         d.K = (uint32_t)r.K;
@@ -523,6 +595,8 @@ void build_batch(const bd_graph* g, int64_t nq, const int32_t* s, const int32_t*
     for (size_t i = 0; i < order.size(); ++i) order[i] = i;
     if (ex.mode != BD_MODE_PLAIN) {
         std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) {
+            const bool ux = b.qd[x].R >= kUniformMinR, uy = b.qd[y].R >= kUniformMinR;
+            if (ux != uy) return ux;
             const double cx = (double)b.qd[x].L * b.qd[x].R, cy = (double)b.qd[y].L * b.qd[y].R;
             return cx > cy;
         });
@@ -533,6 +607,7 @@ void build_batch(const bd_graph* g, int64_t nq, const int32_t* s, const int32_t*
         const QueryDesc& d = b.qd[q];
         const uint32_t kc = chunk_probes(ex, d.K, d.R);
         b.chunk_begin[q] = (uint32_t)b.chunks.size();
+        if (ex.mode != BD_MODE_PLAIN && d.R >= kUniformMinR) b.n_uniform += (d.K + kc - 1) / kc;
         for (uint32_t k0 = 0; k0 < d.K; k0 += kc) {
             Chunk c{};
             c.q = (uint32_t)q;
@@ -626,12 +701,14 @@ extern "C" int bd_walk_trace(bd_graph* g, int64_t count, const int32_t* start, c
     if (rc == BD_OK && trace) rc = dt.alloc(c * (size_t)(L + 1) * 4);
     if (rc == BD_OK && acc) rc = da.alloc(c * 4);
     if (rc != BD_OK) return rc;
-    HIP_TRY(hipMemcpyAsync(ds.p, start, c * 4, hipMemcpyHostToDevice, st));
+    std::vector<int32_t> start_store(start, start + c);
+    for (auto& v : start_store) v = (int32_t)storage_id(g, v);
+    HIP_TRY(hipMemcpyAsync(ds.p, start_store.data(), c * 4, hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(du.p, uid, c * 4, hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(dk.p, k, c * 4, hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(dp.p, p, c * 4, hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(dsd.p, side, c * 4, hipMemcpyHostToDevice, st));
-    HIP_TRY(launch_trace(tables(g), g->layout == BD_LAYOUT_FAT, (uint32_t)c, ds.as<int32_t>(),
+    HIP_TRY(launch_trace(tables(g), g->layout, (uint32_t)c, ds.as<int32_t>(),
                          du.as<uint32_t>(), dk.as<uint32_t>(), dp.as<uint32_t>(), dsd.as<uint32_t>(), L,
                          (uint32_t)seed, (uint32_t)(seed >> 32), trace ? dt.as<int32_t>() : nullptr,
                          acc ? da.as<float>() : nullptr, st));
@@ -663,6 +740,44 @@ extern "C" int bd_probe_eval(bd_graph* g, uint64_t seed, uint32_t uid, uint32_t 
     if (pi) HIP_TRY(hipMemcpyAsync(pi, dpi.p, c * 4, hipMemcpyDeviceToHost, st));
     if (z) HIP_TRY(hipMemcpyAsync(z, dz.p, c, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
+    return BD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Gather roofline
+// ---------------------------------------------------------------------------
+extern "C" int bd_gather_roofline(bd_graph* g, int32_t chains_per_lane, int32_t steps, int32_t work_groups,
+                                  void* stream, bd_roofline* out)
+{
+    if (!g || !out || steps < 1 ||
+        (chains_per_lane != 1 && chains_per_lane != 2 && chains_per_lane != 4 && chains_per_lane != 8))
+        return BD_E_INVALID;
+    hipStream_t st = (hipStream_t)stream;
+    uint32_t grid = work_groups > 0 ? (uint32_t)work_groups : 4u * (uint32_t)resident_wgs(g, 1);
+    DevBuf sink;
+    int rc = sink.alloc((size_t)grid * kBlockThreads * 4);
+    if (rc != BD_OK) return rc;
+    const int fat = g->layout == 1;
+    // warm-up launch (caches, clocks), then the timed one
+    HIP_TRY(launch_gather(tables(g), g->layout, chains_per_lane, grid, std::min(steps, 64), 1u, sink.as<uint32_t>(), st));
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    HIP_TRY(hipEventRecord(e0, st));
+    HIP_TRY(launch_gather(tables(g), g->layout, chains_per_lane, grid, steps, 2u, sink.as<uint32_t>(), st));
+    HIP_TRY(hipEventRecord(e1, st));
+    HIP_TRY(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    const double n = (double)grid * kBlockThreads * chains_per_lane * steps;
+    out->ms = ms;
+    out->steps = (int64_t)n;
+    out->steps_per_s = n / (ms * 1e-3);
+    out->gathers_per_s = out->steps_per_s * (fat ? 1.0 : 2.0);
+    out->chains_per_lane = chains_per_lane;
+    out->work_groups = (int32_t)grid;
     return BD_OK;
 }
 
@@ -761,6 +876,7 @@ struct SlotState {
     uint32_t next_k = 0, K = 0, kc = 1;
     uint64_t chunk_steps = 0;  // walk steps of one full chunk
     uint64_t steps = 0;        // walk steps of the query
+    bool uniform = false;      // R >= kUniformMinR
 };
 
 struct Slice {
@@ -769,6 +885,7 @@ struct Slice {
     PinnedBuf comp_h;  // [u32 count, pad to 16 B][Completion x cap]
     hipEvent_t ev = nullptr;
     uint32_t n = 0;
+    uint32_t n_uniform = 0;  // chunks [0, n_uniform) have R >= kUniformMinR
     bool inflight = false;
     uint64_t steps = 0;
     double t_launch = 0;
@@ -784,7 +901,7 @@ struct bd_server {
     bd_policy pol{};
     hipStream_t st = nullptr;
     uint32_t slots = 0, gdim = 0;
-    int resident = 0;
+    int resident[2] = {0, 0};  // resident work groups: [0] small-R kernel, [1] wave-uniform kernel
     DevBuf d_qd, d_bs, d_done, d_beta, d_cursor, d_comp;
     PinnedBuf h_qd;
     Slice slice[2];
@@ -850,6 +967,7 @@ int admit(bd_server* S)
             ss.kc = chunk_probes(ex, d.K, d.R);
             ss.chunk_steps = 2ull * ss.kc * d.R * (uint64_t)d.L + 2ull * ss.kc * d.R;
             ss.steps = (uint64_t)r.res[(size_t)ss.ridx].walk_steps;
+            ss.uniform = d.R >= kUniformMinR;
             S->inflight_steps += ss.steps;
             S->rr.push_back(sl);
         }
@@ -885,8 +1003,9 @@ void fill_slice(bd_server* S, Slice& sl)
     Chunk* out = sl.chunks_h.as<Chunk>();
     sl.n = 0;
     sl.steps = 0;
-    while (!S->rr.empty() && sl.n < kSliceMaxChunks &&
-           ((double)sl.steps < target || sl.n < (uint32_t)S->resident)) {
+    std::vector<Chunk> small;  // chunks of queries with R < kUniformMinR go after the others
+    while (!S->rr.empty() && sl.n + small.size() < kSliceMaxChunks &&
+           ((double)sl.steps < target || sl.n + small.size() < (size_t)S->resident[1])) {
         const uint32_t q = S->rr.front();
         S->rr.pop_front();
         SlotState& ss = S->slot[q];
@@ -895,10 +1014,13 @@ void fill_slice(bd_server* S, Slice& sl)
         c.k0 = ss.next_k;
         c.kc = std::min<uint32_t>(ss.kc, ss.K - ss.next_k);
         ss.next_k += c.kc;
-        out[sl.n++] = c;
+        if (ss.uniform) out[sl.n++] = c;
+        else small.push_back(c);
         sl.steps += ss.chunk_steps;
         if (ss.next_k < ss.K) S->rr.push_back(q);
     }
+    sl.n_uniform = sl.n;
+    for (const Chunk& c : small) out[sl.n++] = c;
 }
 
 int launch_slice(bd_server* S, Slice& sl)
@@ -908,6 +1030,7 @@ int launch_slice(bd_server* S, Slice& sl)
         hipSuccess)
         return BD_E_HIP;
     if (launch_zero(S->d_cursor.p, 16, st) != hipSuccess) return BD_E_HIP;
+    // the slice's chunk table holds the wave-uniform chunks first
     WalkArgs a{};
     a.g = tables(S->g);
     a.qd = S->d_qd.as<const QueryDesc>();
@@ -923,8 +1046,16 @@ int launch_slice(bd_server* S, Slice& sl)
     a.comp_cap = S->slots;
     a.recycle = 1;
     a.persistent = 1;
-    const uint32_t grid = std::min<uint32_t>((uint32_t)S->resident, sl.n);
-    if (launch_walk(a, S->g->layout == BD_LAYOUT_FAT, grid, st) != hipSuccess) return BD_E_HIP;
+    const uint32_t parts[3] = {0u, sl.n_uniform, sl.n};
+    for (int part = 0; part < 2; ++part) {
+        WalkArgs ap = a;
+        ap.chunks = sl.chunks_d.as<const Chunk>() + parts[part];
+        ap.nchunks = parts[part + 1] - parts[part];
+        ap.cursor = S->d_cursor.as<uint32_t>() + part;
+        const uint32_t grid = std::min<uint32_t>((uint32_t)S->resident[part == 0], ap.nchunks);
+        if (grid && launch_walk(ap, S->g->layout, part == 0, grid, st) != hipSuccess)
+            return BD_E_HIP;
+    }
     if (hipMemcpyAsync(sl.comp_h.p, S->d_comp.p, comp_bytes(S), hipMemcpyDeviceToHost, st) != hipSuccess)
         return BD_E_HIP;
     if (hipEventRecord(sl.ev, st) != hipSuccess) return BD_E_HIP;
@@ -1014,7 +1145,8 @@ extern "C" int bd_server_create(bd_graph* g, const bd_server_cfg* cfg, bd_server
         delete S;
         return BD_E_BUDGET;
     }
-    S->resident = resident_wgs(g);
+    S->resident[0] = resident_wgs(g, 0);
+    S->resident[1] = resident_wgs(g, 1);
     int rc = S->d_qd.alloc((size_t)S->slots * sizeof(QueryDesc));
     if (rc == BD_OK) rc = S->d_bs.alloc((size_t)S->slots * S->gdim * 16);
     if (rc == BD_OK) rc = S->d_done.alloc((size_t)S->slots * 4);
@@ -1062,8 +1194,8 @@ extern "C" int bd_server_submit(bd_server* S, int64_t nq, const int32_t* s, cons
         const bd_result& pr = r.res[(size_t)i];
         if (pr.status != BD_OK) continue;
         QueryDesc d{};
-        d.s = s[i];
-        d.t = t[i];
+        d.s = (int32_t)storage_id(S->g, s[i]);
+        d.t = (int32_t)storage_id(S->g, t[i]);
         d.L = L[i];
         d.uid = uid ? uid[i] : (uint32_t)i;
         d.K = (uint32_t)pr.K;

@@ -8,7 +8,7 @@ namespace pw {
 
 // One query as the device sees it (Algorithm 1 inputs and parameters).
 struct QueryDesc {
-    int32_t s, t;
+    int32_t s, t;       // internal (storage) ids of the endpoints
     int32_t L;
     uint32_t uid;
     uint32_t K, R, B, G;
@@ -33,6 +33,8 @@ struct GraphTables {
     const uint4* node;
     const uint32_t* col;
     const uint4* adj;
+    const uint32_t* rp;
+    const uint32_t* col24;
     DomainParams dom;
 };
 
@@ -66,11 +68,16 @@ struct WalkArgs {
 constexpr int kBlockThreads = 256;
 constexpr int kMaxChunkProbes = 256;
 constexpr int kMaxG = 128;
+// Probes with at least this many replicas are run one probe per wave block
+// (wave-uniform probe keys); fewer replicas use the per-lane mapping.
+constexpr uint32_t kUniformMinR = 48;
 
 // Launchers (defined in pw_kernels.hip). All return hipError_t of the launch.
-hipError_t launch_walk(const WalkArgs& a, int fat, uint32_t grid, hipStream_t st);
+// uniform: every chunk of the launch has R >= kUniformMinR.
+// layout: 0 CSR, 1 fat, 2 compact.
+hipError_t launch_walk(const WalkArgs& a, int layout, int uniform, uint32_t grid, hipStream_t st);
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);
-hipError_t launch_trace(const GraphTables& g, int fat, uint32_t count, const int32_t* start,
+hipError_t launch_trace(const GraphTables& g, int layout, uint32_t count, const int32_t* start,
                         const uint32_t* uid, const uint32_t* k, const uint32_t* p,
                         const uint32_t* side, int32_t L, uint32_t seed_lo, uint32_t seed_hi,
                         int32_t* trace, float* acc, hipStream_t st);
@@ -79,7 +86,10 @@ hipError_t launch_probe_eval(const GraphTables& g, uint32_t seed_lo, uint32_t se
                              int8_t* z, hipStream_t st);
 hipError_t build_fat_adjacency(const uint4* node, const uint32_t* col, uint4* adj, uint32_t nnz,
                                hipStream_t st);
+// Gather-roofline microbenchmark: `chains` in {1, 2, 4, 8} chains per lane.
+hipError_t launch_gather(const GraphTables& g, int layout, int chains, uint32_t grid, int32_t steps, uint32_t seed,
+                         uint32_t* sink, hipStream_t st);
 // Work groups of the walk kernel that fit on the device at once.
-int walk_occupancy(int fat, int* wgs_per_cu);
+int walk_occupancy(int layout, int uniform, int* wgs_per_cu);
 
 }  // namespace pw

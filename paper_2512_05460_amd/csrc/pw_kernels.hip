@@ -24,6 +24,8 @@ __device__ __forceinline__ DevGraph make_graph(const GraphTables& g)
     G.node = g.node;
     G.col = g.col;
     G.adj = g.adj;
+    G.rp = g.rp;
+    G.col24 = g.col24;
     G.dom.n = g.dom.n;
     G.dom.rb = g.dom.rb;
     G.dom.mask = g.dom.mask;
@@ -37,18 +39,18 @@ __device__ __forceinline__ DevGraph make_graph(const GraphTables& g)
 // next node are issued before the probe arithmetic of the current node, so
 // the ALU work overlaps the memory latency. Terms still enter the binary32
 // sum in step order X_0, X_1, ..., X_L.
-template <int kFat>
+template <int kLayout>
 __device__ __forceinline__ float advance(WalkState& w, float acc, uint32_t u, const DevGraph& G,
                                          const Probe& pr)
 {
     const uint32_t xp = w.x;
     const float ip = w.inv;
-    step<kFat>(w, u, G);
+    step<kLayout>(w, u, G);
     return add_term(acc, xp, ip, pr, G.dom);
 }
 
 // U_p = a - b for replica p of probe k (Algorithm 1 walk loop, eq. for phi-hat).
-template <int kFat>
+template <int kLayout>
 __device__ __forceinline__ float walk_pair(const DevGraph& G, const Probe& pr, WalkState ws,
                                            WalkState wt, int L, uint32_t p, uint32_t k,
                                            uint32_t uid, uint32_t slo, uint32_t shi)
@@ -59,28 +61,28 @@ __device__ __forceinline__ float walk_pair(const DevGraph& G, const Probe& pr, W
     for (int blk = 0; blk < full; ++blk) {
         const U4 rs = philox10((uint32_t)blk, p, k, cs, slo, shi);
         const U4 rt = philox10((uint32_t)blk, p, k, ct, slo, shi);
-        a = advance<kFat>(ws, a, rs.x, G, pr);
-        b = advance<kFat>(wt, b, rt.x, G, pr);
-        a = advance<kFat>(ws, a, rs.y, G, pr);
-        b = advance<kFat>(wt, b, rt.y, G, pr);
-        a = advance<kFat>(ws, a, rs.z, G, pr);
-        b = advance<kFat>(wt, b, rt.z, G, pr);
-        a = advance<kFat>(ws, a, rs.w, G, pr);
-        b = advance<kFat>(wt, b, rt.w, G, pr);
+        a = advance<kLayout>(ws, a, rs.x, G, pr);
+        b = advance<kLayout>(wt, b, rt.x, G, pr);
+        a = advance<kLayout>(ws, a, rs.y, G, pr);
+        b = advance<kLayout>(wt, b, rt.y, G, pr);
+        a = advance<kLayout>(ws, a, rs.z, G, pr);
+        b = advance<kLayout>(wt, b, rt.z, G, pr);
+        a = advance<kLayout>(ws, a, rs.w, G, pr);
+        b = advance<kLayout>(wt, b, rt.w, G, pr);
     }
     const int rem = L & 3;
     if (rem) {
         const U4 rs = philox10((uint32_t)full, p, k, cs, slo, shi);
         const U4 rt = philox10((uint32_t)full, p, k, ct, slo, shi);
-        a = advance<kFat>(ws, a, rs.x, G, pr);
-        b = advance<kFat>(wt, b, rt.x, G, pr);
+        a = advance<kLayout>(ws, a, rs.x, G, pr);
+        b = advance<kLayout>(wt, b, rt.x, G, pr);
         if (rem > 1) {
-            a = advance<kFat>(ws, a, rs.y, G, pr);
-            b = advance<kFat>(wt, b, rt.y, G, pr);
+            a = advance<kLayout>(ws, a, rs.y, G, pr);
+            b = advance<kLayout>(wt, b, rt.y, G, pr);
         }
         if (rem > 2) {
-            a = advance<kFat>(ws, a, rs.z, G, pr);
-            b = advance<kFat>(wt, b, rt.z, G, pr);
+            a = advance<kLayout>(ws, a, rs.z, G, pr);
+            b = advance<kLayout>(wt, b, rt.z, G, pr);
         }
     }
     a = add_term(a, ws.x, ws.inv, pr, G.dom);
@@ -135,7 +137,7 @@ __device__ void finalize_query(const WalkArgs& A, const QueryDesc& d, double* ys
     __threadfence();
 }
 
-template <int kFat>
+template <int kLayout, int kUniform>
 __device__ void run_chunk(const WalkArgs& A, const DevGraph& G, uint32_t ci,
                           unsigned long long* acc, double* ys)
 {
@@ -145,19 +147,42 @@ __device__ void run_chunk(const WalkArgs& A, const DevGraph& G, uint32_t ci,
     for (uint32_t j = tid; j < c.kc * 4u; j += kBlockThreads) acc[j] = 0ull;
     __syncthreads();
 
-    const WalkState s0 = start_state((uint32_t)d.s, G.node[d.s]);
-    const WalkState t0 = start_state((uint32_t)d.t, G.node[d.t]);
-    const uint64_t total = (uint64_t)c.kc * d.R;
-    for (uint64_t base = 0; base < total; base += kBlockThreads) {
-        const uint64_t w = base + (uint64_t)tid;
-        if (w < total) {
-            const uint32_t kk = (uint32_t)(w / d.R);
-            const uint32_t p = (uint32_t)(w - (uint64_t)kk * d.R);
+    const WalkState s0 = start_at<kLayout>(G, (uint32_t)d.s);
+    const WalkState t0 = start_at<kLayout>(G, (uint32_t)d.t);
+    if (kUniform) {
+        // Each wave takes blocks of 64 consecutive replicas of one probe, so the
+        // probe index and every probe key are uniform across the wave (scalar
+        // registers); only the last block of a probe runs partially masked.
+        const uint32_t wave = __builtin_amdgcn_readfirstlane((uint32_t)tid >> 6);
+        const uint32_t lane = (uint32_t)tid & 63u;
+        const uint32_t nb = (d.R + 63u) >> 6;
+        const uint32_t units = c.kc * nb;
+        for (uint32_t u = wave; u < units; u += kBlockThreads / 64) {
+            const uint32_t kk = u / nb;
+            const uint32_t p = (u - kk * nb) * 64u + lane;
             const uint32_t k = c.k0 + kk;
-            const Probe pr = make_probe(d.seed_lo, d.seed_hi, d.uid, k, G.dom.n);
-            const float U = walk_pair<kFat>(G, pr, s0, t0, d.L, p, k, d.uid, d.seed_lo, d.seed_hi);
-            lds_add_i128(acc + 4 * kk, fix54(U));
-            lds_add_i128(acc + 4 * kk + 2, (i128)sqfix64(U));
+            if (p < d.R) {
+                const Probe pr = make_probe(d.seed_lo, d.seed_hi, d.uid, k, G.dom.n);
+                const float U = walk_pair<kLayout>(G, pr, s0, t0, d.L, p, k, d.uid, d.seed_lo, d.seed_hi);
+                lds_add_i128(acc + 4 * kk, fix54(U));
+                lds_add_i128(acc + 4 * kk + 2, (i128)sqfix64(U));
+            }
+        }
+    } else {
+        // Few replicas per probe: lanes stride over (probe, replica) pairs so
+        // that one wave covers several probes.
+        const uint64_t total = (uint64_t)c.kc * d.R;
+        for (uint64_t base = 0; base < total; base += kBlockThreads) {
+            const uint64_t w = base + (uint64_t)tid;
+            if (w < total) {
+                const uint32_t kk = (uint32_t)(w / d.R);
+                const uint32_t p = (uint32_t)(w - (uint64_t)kk * d.R);
+                const uint32_t k = c.k0 + kk;
+                const Probe pr = make_probe(d.seed_lo, d.seed_hi, d.uid, k, G.dom.n);
+                const float U = walk_pair<kLayout>(G, pr, s0, t0, d.L, p, k, d.uid, d.seed_lo, d.seed_hi);
+                lds_add_i128(acc + 4 * kk, fix54(U));
+                lds_add_i128(acc + 4 * kk + 2, (i128)sqfix64(U));
+            }
         }
     }
     __syncthreads();
@@ -183,15 +208,16 @@ __device__ void run_chunk(const WalkArgs& A, const DevGraph& G, uint32_t ci,
     __syncthreads();
 }
 
-template <int kFat>
-__global__ __launch_bounds__(kBlockThreads) void walk_kernel(WalkArgs A)
+// kUniform: every chunk of the launch has R >= kUniformMinR (see run_chunk).
+template <int kLayout, int kUniform>
+__global__ __launch_bounds__(kBlockThreads, kUniform ? 8 : 1) void walk_kernel(WalkArgs A)
 {
     __shared__ unsigned long long acc[kMaxChunkProbes * 4];
     __shared__ double ys[kMaxG];
     __shared__ uint32_t next;
     const DevGraph G = make_graph(A.g);
     if (!A.persistent) {
-        if (blockIdx.x < A.nchunks) run_chunk<kFat>(A, G, blockIdx.x, acc, ys);
+        if (blockIdx.x < A.nchunks) run_chunk<kLayout, kUniform>(A, G, blockIdx.x, acc, ys);
         return;
     }
     for (;;) {
@@ -200,24 +226,40 @@ __global__ __launch_bounds__(kBlockThreads) void walk_kernel(WalkArgs A)
         const uint32_t ci = next;
         __syncthreads();
         if (ci >= A.nchunks) break;
-        run_chunk<kFat>(A, G, ci, acc, ys);
+        run_chunk<kLayout, kUniform>(A, G, ci, acc, ys);
     }
 }
 
-hipError_t launch_walk(const WalkArgs& a, int fat, uint32_t grid, hipStream_t st)
+static const void* walk_fn(int layout, int uniform)
+{
+    if (layout == kLayoutFat) return uniform ? (const void*)walk_kernel<1, 1> : (const void*)walk_kernel<1, 0>;
+    if (layout == kLayoutCompact) return uniform ? (const void*)walk_kernel<2, 1> : (const void*)walk_kernel<2, 0>;
+    return uniform ? (const void*)walk_kernel<0, 1> : (const void*)walk_kernel<0, 0>;
+}
+
+hipError_t launch_walk(const WalkArgs& a, int layout, int uniform, uint32_t grid, hipStream_t st)
 {
     if (grid == 0) return hipSuccess;
-    if (fat) hipLaunchKernelGGL(walk_kernel<1>, dim3(grid), dim3(kBlockThreads), 0, st, a);
-    else hipLaunchKernelGGL(walk_kernel<0>, dim3(grid), dim3(kBlockThreads), 0, st, a);
+#define PW_WALK(Lay, U) hipLaunchKernelGGL((walk_kernel<Lay, U>), dim3(grid), dim3(kBlockThreads), 0, st, a)
+    if (layout == kLayoutFat) {
+        if (uniform) PW_WALK(1, 1);
+        else PW_WALK(1, 0);
+    } else if (layout == kLayoutCompact) {
+        if (uniform) PW_WALK(2, 1);
+        else PW_WALK(2, 0);
+    } else {
+        if (uniform) PW_WALK(0, 1);
+        else PW_WALK(0, 0);
+    }
+#undef PW_WALK
     return hipGetLastError();
 }
 
-int walk_occupancy(int fat, int* wgs_per_cu)
+int walk_occupancy(int layout, int uniform, int* wgs_per_cu)
 {
     int nb = 0;
-    hipError_t e = fat ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, walk_kernel<1>, kBlockThreads, 0)
-                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, walk_kernel<0>, kBlockThreads, 0);
-    if (e != hipSuccess) return -1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, walk_fn(layout, uniform), kBlockThreads, 0) != hipSuccess)
+        return -1;
     *wgs_per_cu = nb;
     return 0;
 }
@@ -245,9 +287,8 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t st)
 __global__ void fat_kernel(const uint4* node, const uint32_t* col, uint4* adj, uint32_t nnz)
 {
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nnz; i += gridDim.x * blockDim.x) {
-        const uint32_t x = col[i];
-        const uint4 e = node[x];
-        adj[i] = make_uint4(x, e.x, e.y, e.z);
+        const uint4 e = node[col[i]];
+        adj[i] = make_uint4(e.w, e.x, e.y, e.z);
     }
 }
 
@@ -263,7 +304,7 @@ hipError_t build_fat_adjacency(const uint4* node, const uint32_t* col, uint4* ad
 
 // One walk per thread, recording X_0..X_L and the binary32 sum of z/d; the
 // transitions and the scoring are the production ones (advance / add_term).
-template <int kFat>
+template <int kLayout>
 __global__ void trace_kernel(GraphTables gt, uint32_t count, const int32_t* start,
                              const uint32_t* uid, const uint32_t* kk, const uint32_t* pp,
                              const uint32_t* side, int32_t L, uint32_t slo, uint32_t shi,
@@ -274,35 +315,34 @@ __global__ void trace_kernel(GraphTables gt, uint32_t count, const int32_t* star
     const DevGraph G = make_graph(gt);
     const uint32_t x0 = (uint32_t)start[i];
     const Probe pr = make_probe(slo, shi, uid[i], kk[i], G.dom.n);
-    WalkState w = start_state(x0, G.node[x0]);
+    WalkState w = start_at<kLayout>(G, x0);
     const uint32_t c3 = (uid[i] << 1) | side[i];
     int32_t* tr = trace ? trace + (size_t)i * (L + 1) : nullptr;
-    if (tr) tr[0] = (int32_t)x0;
+    if (tr) tr[0] = (int32_t)w.x;
     float a = 0.0f;
     U4 r = U4{0, 0, 0, 0};
     for (int s = 0; s < L; ++s) {
         if ((s & 3) == 0) r = philox10((uint32_t)(s >> 2), pp[i], kk[i], c3, slo, shi);
         const uint32_t u = (s & 3) == 0 ? r.x : (s & 3) == 1 ? r.y : (s & 3) == 2 ? r.z : r.w;
-        a = advance<kFat>(w, a, u, G, pr);
+        a = advance<kLayout>(w, a, u, G, pr);
         if (tr) tr[s + 1] = (int32_t)w.x;
     }
     a = add_term(a, w.x, w.inv, pr, G.dom);
     if (acc_out) acc_out[i] = a;
 }
 
-hipError_t launch_trace(const GraphTables& g, int fat, uint32_t count, const int32_t* start,
+hipError_t launch_trace(const GraphTables& g, int layout, uint32_t count, const int32_t* start,
                         const uint32_t* uid, const uint32_t* k, const uint32_t* p,
                         const uint32_t* side, int32_t L, uint32_t slo, uint32_t shi,
                         int32_t* trace, float* acc, hipStream_t st)
 {
     if (count == 0) return hipSuccess;
     const uint32_t blocks = (count + 127) / 128;
-    if (fat)
-        hipLaunchKernelGGL(trace_kernel<1>, dim3(blocks), dim3(128), 0, st, g, count, start, uid, k, p,
-                           side, L, slo, shi, trace, acc);
-    else
-        hipLaunchKernelGGL(trace_kernel<0>, dim3(blocks), dim3(128), 0, st, g, count, start, uid, k, p,
-                           side, L, slo, shi, trace, acc);
+#define PW_TRACE(Lay) hipLaunchKernelGGL(trace_kernel<Lay>, dim3(blocks), dim3(128), 0, st, g, count, start, uid, k, p, side, L, slo, shi, trace, acc)
+    if (layout == kLayoutFat) PW_TRACE(1);
+    else if (layout == kLayoutCompact) PW_TRACE(2);
+    else PW_TRACE(0);
+#undef PW_TRACE
     return hipGetLastError();
 }
 
@@ -326,6 +366,68 @@ hipError_t launch_probe_eval(const GraphTables& g, uint32_t slo, uint32_t shi, u
     if (count == 0) return hipSuccess;
     hipLaunchKernelGGL(probe_kernel, dim3((count + 255) / 256), dim3(256), 0, st, g, slo, shi, uid, k,
                        count, nodes, pi, z);
+    return hipGetLastError();
+}
+
+}  // namespace pw
+
+namespace pw {
+
+// Gather roofline: the walk's dependent loads over the loaded graph tables
+// with a cheap xorshift in place of Philox and no probe arithmetic. Each lane
+// runs kChains independent chains of `steps` transitions; the number of
+// transitions per second is the memory-side ceiling of the walk kernel on
+// this graph, layout and footprint.
+template <int kLayout, int kChains>
+__global__ __launch_bounds__(kBlockThreads) void gather_kernel(GraphTables gt, int32_t steps, uint32_t seed,
+                                                               uint32_t* sink)
+{
+    const DevGraph G = make_graph(gt);
+    const uint32_t gid = blockIdx.x * blockDim.x + threadIdx.x;
+    WalkState w[kChains];
+    uint32_t rng[kChains];
+#pragma unroll
+    for (int c = 0; c < kChains; ++c) {
+        uint32_t h = (gid * kChains + c) * 0x9E3779B1u ^ seed;
+        h ^= h >> 16;
+        h *= 0x85EBCA6Bu;
+        h ^= h >> 13;
+        rng[c] = h | 1u;
+        w[c] = start_at<kLayout>(G, __umulhi(h, G.dom.n));
+    }
+    uint32_t acc = 0;
+    for (int s = 0; s < steps; ++s) {
+#pragma unroll
+        for (int c = 0; c < kChains; ++c) {
+            uint32_t x = rng[c];
+            x ^= x << 13;
+            x ^= x >> 17;
+            x ^= x << 5;
+            rng[c] = x;
+            step<kLayout>(w[c], x, G);
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < kChains; ++c) acc ^= w[c].x ^ __float_as_uint(w[c].inv);
+    sink[gid] = acc;
+}
+
+hipError_t launch_gather(const GraphTables& g, int layout, int chains, uint32_t grid, int32_t steps, uint32_t seed,
+                         uint32_t* sink, hipStream_t st)
+{
+#define PW_GATHER(F, C) hipLaunchKernelGGL((gather_kernel<F, C>), dim3(grid), dim3(kBlockThreads), 0, st, g, steps, seed, sink)
+#define PW_GATHER_C(F)                  \
+    do {                                \
+        if (chains == 1) PW_GATHER(F, 1); \
+        else if (chains == 2) PW_GATHER(F, 2); \
+        else if (chains == 4) PW_GATHER(F, 4); \
+        else PW_GATHER(F, 8);           \
+    } while (0)
+    if (layout == kLayoutFat) PW_GATHER_C(1);
+    else if (layout == kLayoutCompact) PW_GATHER_C(2);
+    else PW_GATHER_C(0);
+#undef PW_GATHER_C
+#undef PW_GATHER
     return hipGetLastError();
 }
 

@@ -61,12 +61,13 @@ def test_device_info():
     assert "gfx950" in info
 
 
-@pytest.mark.parametrize("layout", [B.BD_LAYOUT_CSR, B.BD_LAYOUT_FAT])
-def test_graph_info(ba1k, layout):
+@pytest.mark.parametrize("layout,code", [(B.BD_LAYOUT_CSR, 0), (B.BD_LAYOUT_FAT, 1),
+                                         (B.BD_LAYOUT_FAT | B.BD_RELABEL_DEGREE, 1), (B.BD_LAYOUT_COMPACT, 2)])
+def test_graph_info(ba1k, layout, code):
     gi = load(ba1k, layout).info()
     assert gi["n"] == ba1k.n and gi["nnz"] == ba1k.nnz
     assert gi["d_min"] == ba1k.d_min and gi["d_max"] == ba1k.d_max
-    assert gi["layout"] == layout and gi["bipartite"] == 0
+    assert gi["layout"] == code and gi["bipartite"] == 0
 
 
 def test_bipartite_flag():
@@ -79,7 +80,7 @@ def test_bipartite_flag():
 @pytest.mark.parametrize("name", list(SMALL) + ["ba1k", "cl100k"])
 def test_probe_parity(name):
     g = SMALL[name]() if name in SMALL else graphs.workload_graph(name)
-    dg = load(g, B.BD_LAYOUT_CSR)
+    dg = load(g, B.BD_LAYOUT_CSR | B.BD_RELABEL_DEGREE)
     nodes = np.arange(g.n, dtype=np.uint32)
     for uid, k in [(0, 0), (3, 1), (7, 12345), (2 ** 31 - 1, 2 ** 32 - 2)]:
         pi, z = B.bd_probe_eval(dg, SEED, uid, k, nodes)
@@ -88,7 +89,11 @@ def test_probe_parity(name):
         assert np.array_equal(z, oz), (name, uid, k)
 
 
-@pytest.mark.parametrize("layout", [B.BD_LAYOUT_CSR, B.BD_LAYOUT_FAT])
+LAYOUTS = [B.BD_LAYOUT_CSR, B.BD_LAYOUT_FAT, B.BD_LAYOUT_CSR | B.BD_RELABEL_DEGREE,
+           B.BD_LAYOUT_FAT | B.BD_RELABEL_DEGREE, B.BD_LAYOUT_COMPACT]
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
 @pytest.mark.parametrize("name", ["ba1k", "cl100k", "K5", "P2", "G37"])
 @pytest.mark.parametrize("L", [0, 1, 2, 3, 4, 5, 37, 1000])
 def test_trace_parity(name, layout, L):
@@ -136,6 +141,12 @@ PROBE_CASES = [
     ("ba1k", 10, 900, 200, 3, 300, B.BD_LAYOUT_FAT, 2),
     ("cl100k", 5, 77, 1000, 1, 70, B.BD_LAYOUT_CSR, 0),
     ("cl100k", 5, 77, 1000, 1, 70, B.BD_LAYOUT_FAT, 0),
+    ("cl100k", 5, 77, 1000, 1, 70, B.BD_LAYOUT_CSR | B.BD_RELABEL_DEGREE, 0),
+    ("G37", 2, 30, 40, 3, 100, B.BD_LAYOUT_FAT | B.BD_RELABEL_DEGREE, 7),
+    ("G37", 2, 30, 40, 3, 100, B.BD_LAYOUT_COMPACT, 7),
+    ("ba1k", 10, 900, 200, 3, 300, B.BD_LAYOUT_COMPACT, 0),
+    ("cl100k", 5, 77, 1000, 1, 70, B.BD_LAYOUT_COMPACT, 0),
+    ("P2", 0, 1, 5, 2, 3, B.BD_LAYOUT_COMPACT, 0),
 ]
 
 
@@ -197,7 +208,7 @@ def _mixed_batch(g, n, seed):
     return s, t, eps, L
 
 
-@pytest.mark.parametrize("layout", [B.BD_LAYOUT_CSR, B.BD_LAYOUT_FAT])
+@pytest.mark.parametrize("layout", LAYOUTS)
 def test_batch_parity_all_modes(ba1k, layout):
     dg = load(ba1k, layout)
     s, t, eps, L = _mixed_batch(ba1k, 10, 3)
@@ -217,7 +228,7 @@ def test_batch_parity_all_modes(ba1k, layout):
 
 
 def test_alone_equals_in_batch(ba1k):
-    dg = load(ba1k, B.BD_LAYOUT_FAT)
+    dg = load(ba1k, B.BD_LAYOUT_FAT | B.BD_RELABEL_DEGREE)
     s, t, eps, L = _mixed_batch(ba1k, 16, 11)
     pol = B.policy("scaled", c_B=0.05, c_R=2e-4)
     full = B.bd_query_batch(dg, s, t, eps, L, SEED, pol)
@@ -229,11 +240,12 @@ def test_alone_equals_in_batch(ba1k):
     assert not np.array_equal(other["beta"], full["beta"])
 
 
-def test_full_size_sampled_parity(cl100k):
+@pytest.mark.parametrize("layout", [B.BD_LAYOUT_COMPACT, B.BD_LAYOUT_FAT])
+def test_full_size_sampled_parity(cl100k, layout):
     # Bench shape: Chung-Lu n=1e5, L = 1000, eps = 0.05; per-probe Q checked on
     # sampled probes (the oracle runs R walk pairs of 1000 steps per probe).
     from paper_2512_05460_amd.budgets import budget_policy
-    dg = load(cl100k, B.BD_LAYOUT_FAT)
+    dg = load(cl100k, layout)
     s, t = queries.uniform_pairs(cl100k.n, 4096, graphs.GRAPH_SEED + 1 + graphs.QUERY_SEED_OFFSET)
     pol = budget_policy("cl100k")
     for i in (0, 1):
