@@ -5,16 +5,18 @@ connected component (99,163 nodes, 997,038 adjacency entries); uniform (s,t)
 pairs; eps = 0.05, L = 1000; walk counts from the scaled policy of Algorithm 1
 (constants in paper_2512_05460_amd/budgets.py). One step = one batch of
 queries run in the plain mode (one query per launch, fixed tiling). The same
-batch is also run in the batched (persistent, work-stealing) mode.
+batch is also run in the batched (persistent, work-stealing) mode and through
+the server (continuous batching), reported beside the headline.
 
-Prints one JSON line. The graph and the query descriptors are resident on the
-device before the timed region; each query's descriptor travels host->device
-inside the call (48 bytes) and its result device->host.
+Prints one JSON line. The graph is resident on the device before the timed
+region; each query's 48-byte descriptor travels host->device inside the call
+and its result device->host.
 """
 
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -28,12 +30,43 @@ sys.path.insert(0, ROOT)
 WORKLOAD = "cl100k"
 EPS = 0.05
 L = 1000
-BYTES_PER_STEP = 12   # next node id + its row offset and degree (4 + 4 + 4 bytes)
+BYTES_PER_STEP = 12   # algorithmic: next node id + its row offset and degree (4 + 4 + 4 bytes)
 HBM_PEAK_GBS = 8000.0
+COUNTERS = os.path.join(ROOT, "profiles", "walk_kernel_cl100k_counters.txt")
+KERNEL_SOURCES = ["pw_kernels.hip", "pw_device.hpp", "pw_internal.hpp"]
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2512_05460_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def counter_traffic():
+    """HBM bytes per walk-kernel launch from the committed rocprofv3 summary, or
+    None when the kernel sources changed since the counters were taken."""
+    if not os.path.exists(COUNTERS):
+        return None, "no counter summary"
+    kv = {}
+    for ln in open(COUNTERS):
+        if "=" in ln and not ln.startswith("#"):
+            k, v = ln.split("=", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None, "kernel changed since the counters were taken"
+    try:
+        fetch = float(kv["fetch_kib_per_dispatch"]) * float(kv["fetch_scale"])
+        write = float(kv["write_kib_per_dispatch"]) * float(kv["write_scale"])
+        steps = float(kv["walk_steps_per_dispatch"])
+    except (KeyError, ValueError):
+        return None, "incomplete counter summary"
+    return (fetch + write) * 1024.0 / steps, "bytes per walk step, FETCH_SIZE and WRITE_SIZE scaled by a copy kernel"
 
 
 def cpu_baseline(g, s, t, plans, seed, target_s=20.0):
@@ -46,23 +79,21 @@ def cpu_baseline(g, s, t, plans, seed, target_s=20.0):
         cores = len(os.sched_getaffinity(0))
     except AttributeError:
         cores = os.cpu_count() or 1
-    threads = max(1, min(16, cores))
-    nq = threads
-    sub = [plans[i] for i in range(nq)]
-    per_probe = np.array([2 * p[3] * L for p in sub], dtype=np.float64)
-    # calibrate probe counts for ~target_s of work: oracle speed ~1.5e7 steps/s/thread
+    threads = max(1, min(16, cores, len(plans)))
+    sub = [plans[i] for i in range(threads)]
+    per_probe = np.array([2.0 * p[3] * L for p in sub])
     kend = np.maximum(1, np.minimum([p[2] for p in sub], (1.5e7 * target_s / per_probe).astype(np.int64)))
     t0 = time.perf_counter()
-    E.estimate(g, s[:nq], t[:nq], L, sub, seed, uid=np.arange(nq), threads=threads, k_end=kend)
+    E.estimate(g, s[:threads], t[:threads], L, sub, seed, uid=np.arange(threads), threads=threads, k_end=kend)
     dt = time.perf_counter() - t0
     steps = float((kend * per_probe).sum())
-    full = np.array([2.0 * p[2] * p[3] * L for p in plans], dtype=np.float64)
+    full = np.array([2.0 * p[2] * p[3] * L for p in plans])
     sps = steps / dt
     return {"value": sps / full.mean(), "unit": "queries/s", "cores": threads, "kind": "oracle",
             "walk_steps_per_s": sps,
-            "sample": (f"{nq} of the step's queries, first {int(kend.min())}-{int(kend.max())} probes each at "
-                       f"full R and L, one query per thread; {steps:.3e} walk steps in {dt:.1f} s; "
-                       "queries/s = steps/s / mean full-query steps")}
+            "sample": (f"{threads} of the step's queries, first {int(kend.min())}-{int(kend.max())} of their "
+                       f"probes each at full R and L, one query per thread; {steps:.3e} walk steps in "
+                       f"{dt:.1f} s; queries/s = steps/s / mean full-query steps of the batch")}
 
 
 def main():
@@ -70,16 +101,18 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--queries", type=int, default=64, help="queries per step")
-    ap.add_argument("--layout", choices=["csr", "fat"], default="csr")
+    ap.add_argument("--queries", type=int, default=32, help="queries per step")
+    ap.add_argument("--layout", choices=["compact", "csr", "fat"], default="compact")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--no-roofline", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calib", type=int, default=0,
-                    help="also run a torch copy of this many MiB (counter calibration)")
+                    help="also run a device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on one GPU only: the estimator's queries shard across GPUs "
-              "with no exchange but a few block sums, and this build measures one GPU's share.",
+        print("bench.py measures one GPU: queries shard across GPUs with nothing exchanged but "
+              "a few block sums per query, and this build runs and reports one GPU's share.",
               file=sys.stderr)
         sys.exit(2)
 
@@ -96,8 +129,9 @@ def main():
     s_all, t_all = queries.uniform_pairs(g.n, 4096, graphs.GRAPH_SEED + 1 + graphs.QUERY_SEED_OFFSET)
     nq = args.queries
     s, t = s_all[:nq], t_all[:nq]
-    layout = B.BD_LAYOUT_FAT if args.layout == "fat" else B.BD_LAYOUT_CSR
-    dg = B.graph_load_csr(g.n, g.row_ptr, g.col, layout)
+    flags = {"compact": B.BD_LAYOUT_COMPACT, "csr": B.BD_LAYOUT_CSR | B.BD_RELABEL_DEGREE,
+             "fat": B.BD_LAYOUT_FAT | B.BD_RELABEL_DEGREE}[args.layout]
+    dg = B.graph_load_csr(g.n, g.row_ptr, g.col, flags)
     pol = budget_policy(WORKLOAD)
     seed = graphs.PHILOX_SEED
     plan = B.bd_plan(dg, s, t, EPS, L, pol)
@@ -142,15 +176,36 @@ def main():
     extra = {}
     if not args.no_batched:
         log("batched mode, same batch")
-        B.bd_query_batch(dg, s, t, EPS, L, seed, pol, B.exec_cfg("batched"), stream=stream)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         r, st = B.bd_query_batch(dg, s, t, EPS, L, seed, pol, B.exec_cfg("batched"), stream=stream,
                                  with_stats=True)
         torch.cuda.synchronize()
         dtb = time.perf_counter() - t1
+        assert np.all(r["status"] == 0)
         extra["batched"] = {"queries_per_s": nq / dtb, "walk_steps_per_s": steps_per_batch / dtb,
                             "kernel_ms": st["walk_kernel_ms"], "vs_plain": (nq / dtb) / qps}
+    if not args.no_served:
+        log("served mode, same batch as 4 requests")
+        srv = B.Server(dg, pol)
+        t1 = time.perf_counter()
+        rids = [srv.submit(s[i::4], t[i::4], EPS, L, seed, uid=np.arange(nq)[i::4]) for i in range(4)]
+        lats = []
+        for rid in rids:
+            out, lat = srv.wait(rid)
+            assert np.all(out["status"] == 0)
+            lats.append(lat)
+        dts = time.perf_counter() - t1
+        srv.destroy()
+        extra["served"] = {"queries_per_s": nq / dts, "vs_plain": (nq / dts) / qps,
+                           "request_latency_ms": lats}
+    roof = None
+    if not args.no_roofline:
+        log("gather roofline")
+        best = max((B.bd_gather_roofline(dg, c, 1000) for c in (2, 4, 8)), key=lambda r: r["steps_per_s"])
+        roof = {"steps_per_s": best["steps_per_s"], "chains_per_lane": best["chains_per_lane"],
+                "frac": kernel_sps / best["steps_per_s"],
+                "what": "same dependent loads on the same tables, no Philox or probe arithmetic"}
     if args.copy_calib:
         n = args.copy_calib * (1 << 20) // 4
         x = torch.empty(n, dtype=torch.float32, device="cuda")
@@ -168,6 +223,8 @@ def main():
         log("cpu baseline (oracle, bounded sample)")
         cpu = cpu_baseline(g, s, t, plans, seed)
 
+    traffic_per_step, traffic_note = counter_traffic()
+    steps_per_launch = steps_per_batch * args.steps / max(1, launches_all)
     c_B, c_R, how = BUDGETS[WORKLOAD]
     out = {
         "metric": "queries/s at eps=0.05, L=1000",
@@ -199,11 +256,15 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved_gbs / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": None if traffic_per_step is None else traffic_per_step * steps_per_launch / 1e9,
+            "traffic_unit": "GB per launch",
+            "traffic_note": traffic_note,
             "kernel": "walk_kernel",
             "avg_launch_ms": kms_all / max(1, launches_all),
+            "walk_steps_per_launch": steps_per_launch,
             "kernel_walk_steps_per_s": kernel_sps,
             "bytes_per_step": BYTES_PER_STEP,
+            "gather_roofline": roof,
         },
         "cpu_baseline": cpu,
         "device": dev,
