@@ -440,25 +440,79 @@ int resident_wgs(const bd_graph* g, int uniform)
     return per_cu * prop.multiProcessorCount;
 }
 
-// Probes per chunk: enough (probe, replica) pairs to keep 256 lanes busy for
-// several rounds, capped by the LDS accumulator size.
-uint32_t chunk_probes(const bd_exec& ex, uint32_t K, uint32_t R)
+// How the probes of one query are cut into work-group chunks.
+//   plain:   one chunk holds whole probes (all R replicas), at least 256 pairs;
+//   batched / served: whole probes up to kSplitReplicas pairs per chunk, and a
+//   probe with R > kSplitReplicas is cut into replica parts (multiples of 64)
+//   so that no chunk runs much longer than the others.
+struct ChunkPlan {
+    uint32_t kc = 1;       // probes per chunk (whole-probe chunks)
+    uint32_t part = 0;     // replicas per part, 0 = probes are not split
+};
+
+ChunkPlan chunk_plan(const bd_exec& ex, uint32_t K, uint32_t R)
 {
+    ChunkPlan cp;
+    if (ex.mode != BD_MODE_PLAIN && R >= kUniformMinR && R > kSplitReplicas) {
+        const uint32_t parts = (R + kSplitReplicas - 1) / kSplitReplicas;
+        cp.part = ((R + parts - 1) / parts + 63u) & ~63u;
+        cp.kc = 1;
+        return cp;
+    }
     uint32_t kc;
     if (ex.chunk_probes > 0) {
         kc = (uint32_t)ex.chunk_probes;
     } else {
-        const uint64_t target = ex.mode == BD_MODE_PLAIN ? (uint64_t)kBlockThreads : 4u * kBlockThreads;
+        const uint64_t target = ex.mode == BD_MODE_PLAIN ? (uint64_t)kBlockThreads : (uint64_t)kSplitReplicas;
         kc = (uint32_t)std::max<uint64_t>(1, (target + R - 1) / R);
     }
     kc = std::min<uint32_t>(kc, (uint32_t)kMaxChunkProbes);
     kc = std::min<uint32_t>(kc, std::max<uint32_t>(K, 1));
-    return std::max<uint32_t>(kc, 1);
+    cp.kc = std::max<uint32_t>(kc, 1);
+    return cp;
 }
+
+// Emits the chunks of one query in order: (next_k, next_p) is the cursor.
+struct ChunkCursor {
+    uint32_t q = 0, K = 0, R = 0;
+    ChunkPlan plan;
+    uint32_t next_k = 0, next_p = 0;
+    bool done() const { return next_k >= K; }
+    Chunk next()
+    {
+        Chunk c{};
+        c.q = q;
+        c.k0 = next_k;
+        if (plan.part) {
+            c.kc = 1;
+            c.p0 = next_p;
+            c.pc = std::min<uint32_t>(plan.part, R - next_p);
+            next_p += c.pc;
+            if (next_p >= R) {
+                next_p = 0;
+                ++next_k;
+            }
+        } else {
+            c.kc = std::min<uint32_t>(plan.kc, K - next_k);
+            c.p0 = 0;
+            c.pc = R;
+            next_k += c.kc;
+        }
+        return c;
+    }
+    // walk steps of the next chunk (2 walks of L steps per replica)
+    uint64_t chunk_steps(uint32_t L) const
+    {
+        const uint64_t pairs = plan.part ? (uint64_t)std::min<uint32_t>(plan.part, R - next_p)
+                                         : (uint64_t)std::min<uint32_t>(plan.kc, K - next_k) * R;
+        return 2ull * pairs * ((uint64_t)L + 1);
+    }
+};
 
 struct Batch {
     std::vector<QueryDesc> qd;
     std::vector<Chunk> chunks;
+    uint32_t split_probes = 0;          // per-probe accumulators needed
     std::vector<uint32_t> chunk_begin;  // per valid query, first chunk (chunks grouped by query)
     std::vector<int64_t> index;         // valid query -> caller's index
     uint32_t G = 0;
@@ -472,8 +526,10 @@ int run_batch(bd_graph* g, const Batch& b, const bd_exec& ex, hipStream_t st,
     const size_t nv = b.qd.size();
     if (nv == 0) return BD_OK;
     const size_t gdim = b.G;
-    DevBuf d_qd, d_chunks, d_bs, d_done, d_beta, d_cursor, d_qdbg, d_ydbg;
+    DevBuf d_qd, d_chunks, d_bs, d_done, d_beta, d_cursor, d_qdbg, d_ydbg, d_psum, d_pcount;
     int rc = d_qd.alloc(nv * sizeof(QueryDesc));
+    if (rc == BD_OK) rc = d_psum.alloc((size_t)b.split_probes * 32);
+    if (rc == BD_OK) rc = d_pcount.alloc((size_t)b.split_probes * 4);
     if (rc == BD_OK) rc = d_chunks.alloc(b.chunks.size() * sizeof(Chunk));
     if (rc == BD_OK) rc = d_bs.alloc(nv * gdim * 16);
     if (rc == BD_OK) rc = d_done.alloc(nv * 4);
@@ -488,6 +544,8 @@ int run_batch(bd_graph* g, const Batch& b, const bd_exec& ex, hipStream_t st,
     HIP_TRY(launch_zero(d_bs.p, nv * gdim * 16, st));
     HIP_TRY(launch_zero(d_done.p, nv * 4, st));
     HIP_TRY(launch_zero(d_cursor.p, 16, st));
+    HIP_TRY(launch_zero(d_psum.p, (size_t)b.split_probes * 32, st));
+    HIP_TRY(launch_zero(d_pcount.p, (size_t)b.split_probes * 4, st));
 
     WalkArgs a{};
     a.g = tables(g);
@@ -496,6 +554,8 @@ int run_batch(bd_graph* g, const Batch& b, const bd_exec& ex, hipStream_t st,
     a.cursor = d_cursor.as<uint32_t>();
     a.blocksum = d_bs.as<unsigned long long>();
     a.done = d_done.as<uint32_t>();
+    a.psum = d_psum.as<unsigned long long>();
+    a.pcount = d_pcount.as<uint32_t>();
     a.beta = d_beta.as<double>();
     a.q_debug = q_dbg_host ? d_qdbg.as<double>() : nullptr;
     a.ybar_debug = y_dbg_host ? d_ydbg.as<double>() : nullptr;
@@ -604,17 +664,19 @@ void build_batch(const bd_graph* g, int64_t nq, const int32_t* s, const int32_t*
     b.chunk_begin.assign(b.qd.size(), 0);
     for (size_t oi = 0; oi < order.size(); ++oi) {
         const size_t q = order[oi];
-        const QueryDesc& d = b.qd[q];
-        const uint32_t kc = chunk_probes(ex, d.K, d.R);
-        b.chunk_begin[q] = (uint32_t)b.chunks.size();
-        if (ex.mode != BD_MODE_PLAIN && d.R >= kUniformMinR) b.n_uniform += (d.K + kc - 1) / kc;
-        for (uint32_t k0 = 0; k0 < d.K; k0 += kc) {
-            Chunk c{};
-            c.q = (uint32_t)q;
-            c.k0 = k0;
-            c.kc = std::min<uint32_t>(kc, d.K - k0);
-            b.chunks.push_back(c);
+        QueryDesc& d = b.qd[q];
+        ChunkCursor cur;
+        cur.q = (uint32_t)q;
+        cur.K = d.K;
+        cur.R = d.R;
+        cur.plan = chunk_plan(ex, d.K, d.R);
+        if (cur.plan.part) {
+            d.psum_base = b.split_probes;
+            b.split_probes += d.K;
         }
+        b.chunk_begin[q] = (uint32_t)b.chunks.size();
+        while (!cur.done()) b.chunks.push_back(cur.next());
+        if (ex.mode != BD_MODE_PLAIN && d.R >= kUniformMinR) b.n_uniform = (uint32_t)b.chunks.size();
     }
     (void)g;
 }
@@ -866,6 +928,7 @@ struct Request {
     std::vector<int64_t> index;   // valid query -> result index
     int64_t remaining = 0;
     uint64_t steps = 0;
+    uint64_t split_probes = 0;    // accumulators its split queries need
     double t_submit = 0, t_done = 0;
     bool done = false;
 };
@@ -873,10 +936,55 @@ struct Request {
 struct SlotState {
     uint64_t req = 0;
     int64_t ridx = 0;
-    uint32_t next_k = 0, K = 0, kc = 1;
-    uint64_t chunk_steps = 0;  // walk steps of one full chunk
+    ChunkCursor cur;           // next chunk of this query
+    uint32_t L = 0;
     uint64_t steps = 0;        // walk steps of the query
     bool uniform = false;      // R >= kUniformMinR
+    uint32_t psum_base = 0, psum_n = 0;  // accumulator range of a query with split probes
+};
+
+// First-fit allocator of per-probe accumulator ranges (units: probes).
+struct RangeAlloc {
+    std::map<uint32_t, uint32_t> free_;  // offset -> length
+    void init(uint32_t n)
+    {
+        free_.clear();
+        if (n) free_[0] = n;
+    }
+    bool alloc(uint32_t n, uint32_t* off)
+    {
+        if (n == 0) {
+            *off = 0;
+            return true;
+        }
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= n) {
+                *off = it->first;
+                const uint32_t rest = it->second - n, o = it->first + n;
+                free_.erase(it);
+                if (rest) free_[o] = rest;
+                return true;
+            }
+        }
+        return false;
+    }
+    void release(uint32_t off, uint32_t n)
+    {
+        if (n == 0) return;
+        auto it = free_.emplace(off, n).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
 };
 
 struct Slice {
@@ -902,8 +1010,10 @@ struct bd_server {
     hipStream_t st = nullptr;
     uint32_t slots = 0, gdim = 0;
     int resident[2] = {0, 0};  // resident work groups: [0] small-R kernel, [1] wave-uniform kernel
-    DevBuf d_qd, d_bs, d_done, d_beta, d_cursor, d_comp;
+    DevBuf d_qd, d_bs, d_done, d_beta, d_cursor, d_comp, d_psum, d_pcount;
     PinnedBuf h_qd;
+    uint32_t arena = 0;  // per-probe accumulators for split probes
+    RangeAlloc psum_alloc;
     Slice slice[2];
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
@@ -946,28 +1056,45 @@ int admit(bd_server* S)
         if (need > S->free_slots.size()) break;
         const uint64_t cap = S->cfg.max_steps_inflight;
         if (cap && S->inflight_steps > 0 && S->inflight_steps + r.steps > cap) break;
+        // memory admission: accumulators of split probes, all or nothing
+        bd_exec ex{};
+        ex.mode = BD_MODE_BATCHED;
+        ex.chunk_probes = S->cfg.chunk_probes;
+        std::vector<uint32_t> base(need, 0);
+        bool fits = true;
+        for (size_t i = 0; i < need && fits; ++i) {
+            const QueryDesc& d = r.desc[i];
+            if (chunk_plan(ex, d.K, d.R).part && !S->psum_alloc.alloc(d.K, &base[i])) {
+                for (size_t j = 0; j < i; ++j)
+                    if (chunk_plan(ex, r.desc[j].K, r.desc[j].R).part) S->psum_alloc.release(base[j], r.desc[j].K);
+                fits = false;
+            }
+        }
+        if (!fits) break;
         S->pending.pop_front();
         for (size_t i = 0; i < need; ++i) {
             const uint32_t sl = S->free_slots.back();
             S->free_slots.pop_back();
             QueryDesc d = r.desc[i];
             d.slot = sl;
+            d.psum_base = base[i];
             S->h_qd.as<QueryDesc>()[sl] = d;
             if (hipMemcpyAsync(S->d_qd.as<QueryDesc>() + sl, S->h_qd.as<QueryDesc>() + sl, sizeof(QueryDesc),
                                hipMemcpyHostToDevice, S->st) != hipSuccess)
                 return BD_E_HIP;
             SlotState& ss = S->slot[sl];
-            bd_exec ex{};
-            ex.mode = BD_MODE_BATCHED;
-            ex.chunk_probes = S->cfg.chunk_probes;
             ss.req = id;
             ss.ridx = r.index[i];
-            ss.next_k = 0;
-            ss.K = d.K;
-            ss.kc = chunk_probes(ex, d.K, d.R);
-            ss.chunk_steps = 2ull * ss.kc * d.R * (uint64_t)d.L + 2ull * ss.kc * d.R;
+            ss.cur = ChunkCursor();
+            ss.cur.q = sl;
+            ss.cur.K = d.K;
+            ss.cur.R = d.R;
+            ss.cur.plan = chunk_plan(ex, d.K, d.R);
+            ss.L = (uint32_t)d.L;
             ss.steps = (uint64_t)r.res[(size_t)ss.ridx].walk_steps;
             ss.uniform = d.R >= kUniformMinR;
+            ss.psum_base = base[i];
+            ss.psum_n = ss.cur.plan.part ? d.K : 0;
             S->inflight_steps += ss.steps;
             S->rr.push_back(sl);
         }
@@ -990,6 +1117,8 @@ void process_completions(bd_server* S, const Slice& sl)
             if (--r.remaining == 0) finish_request(S, ss.req, r);
         }
         S->inflight_steps -= std::min(S->inflight_steps, ss.steps);
+        S->psum_alloc.release(ss.psum_base, ss.psum_n);
+        ss.psum_n = 0;
         S->free_slots.push_back(c.slot);
     }
     S->comp_seen = count;
@@ -1009,15 +1138,11 @@ void fill_slice(bd_server* S, Slice& sl)
         const uint32_t q = S->rr.front();
         S->rr.pop_front();
         SlotState& ss = S->slot[q];
-        Chunk c{};
-        c.q = q;
-        c.k0 = ss.next_k;
-        c.kc = std::min<uint32_t>(ss.kc, ss.K - ss.next_k);
-        ss.next_k += c.kc;
+        sl.steps += ss.cur.chunk_steps(ss.L);
+        const Chunk c = ss.cur.next();
         if (ss.uniform) out[sl.n++] = c;
         else small.push_back(c);
-        sl.steps += ss.chunk_steps;
-        if (ss.next_k < ss.K) S->rr.push_back(q);
+        if (!ss.cur.done()) S->rr.push_back(q);
     }
     sl.n_uniform = sl.n;
     for (const Chunk& c : small) out[sl.n++] = c;
@@ -1040,6 +1165,8 @@ int launch_slice(bd_server* S, Slice& sl)
     a.cursor = S->d_cursor.as<uint32_t>();
     a.blocksum = S->d_bs.as<unsigned long long>();
     a.done = S->d_done.as<uint32_t>();
+    a.psum = S->d_psum.as<unsigned long long>();
+    a.pcount = S->d_pcount.as<uint32_t>();
     a.beta = S->d_beta.as<double>();
     a.comp_count = S->d_comp.as<uint32_t>();
     a.comp_ring = reinterpret_cast<Completion*>(S->d_comp.as<char>() + 16);
@@ -1153,6 +1280,10 @@ extern "C" int bd_server_create(bd_graph* g, const bd_server_cfg* cfg, bd_server
     if (rc == BD_OK) rc = S->d_beta.alloc((size_t)S->slots * 8);
     if (rc == BD_OK) rc = S->d_cursor.alloc(16);
     if (rc == BD_OK) rc = S->d_comp.alloc(comp_bytes(S));
+    S->arena = 1u << 22;
+    if (rc == BD_OK) rc = S->d_psum.alloc((size_t)S->arena * 32);
+    if (rc == BD_OK) rc = S->d_pcount.alloc((size_t)S->arena * 4);
+    S->psum_alloc.init(S->arena);
     if (rc == BD_OK) rc = S->h_qd.alloc((size_t)S->slots * sizeof(QueryDesc));
     for (int i = 0; i < 2 && rc == BD_OK; ++i) {
         rc = S->slice[i].chunks_h.alloc((size_t)kSliceMaxChunks * sizeof(Chunk));
@@ -1165,6 +1296,8 @@ extern "C" int bd_server_create(bd_graph* g, const bd_server_cfg* cfg, bd_server
     if (rc == BD_OK && launch_zero(S->d_bs.p, (size_t)S->slots * S->gdim * 16, S->st) != hipSuccess) rc = BD_E_HIP;
     if (rc == BD_OK && launch_zero(S->d_done.p, (size_t)S->slots * 4, S->st) != hipSuccess) rc = BD_E_HIP;
     if (rc == BD_OK && launch_zero(S->d_comp.p, comp_bytes(S), S->st) != hipSuccess) rc = BD_E_HIP;
+    if (rc == BD_OK && launch_zero(S->d_psum.p, (size_t)S->arena * 32, S->st) != hipSuccess) rc = BD_E_HIP;
+    if (rc == BD_OK && launch_zero(S->d_pcount.p, (size_t)S->arena * 4, S->st) != hipSuccess) rc = BD_E_HIP;
     if (rc == BD_OK && hipStreamSynchronize(S->st) != hipSuccess) rc = BD_E_HIP;
     if (rc != BD_OK) {
         for (int i = 0; i < 2; ++i)
@@ -1207,9 +1340,13 @@ extern "C" int bd_server_submit(bd_server* S, int64_t nq, const int32_t* s, cons
         r.desc.push_back(d);
         r.index.push_back(i);
         r.steps += (uint64_t)pr.walk_steps;
+        bd_exec ex{};
+        ex.mode = BD_MODE_BATCHED;
+        ex.chunk_probes = S->cfg.chunk_probes;
+        if (chunk_plan(ex, d.K, d.R).part) r.split_probes += d.K;
     }
     r.remaining = (int64_t)r.desc.size();
-    if (r.desc.size() > S->slots) return BD_E_FULL;
+    if (r.desc.size() > S->slots || r.split_probes > S->arena) return BD_E_FULL;
     if (S->cfg.max_steps_inflight && r.steps > S->cfg.max_steps_inflight) return BD_E_FULL;
     std::lock_guard<std::mutex> lk(S->mu);
     if (S->broken != BD_OK) return S->broken;

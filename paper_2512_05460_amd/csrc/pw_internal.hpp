@@ -14,15 +14,19 @@ struct QueryDesc {
     uint32_t K, R, B, G;
     uint32_t slot;      // row of the block-sum / done / result tables
     uint32_t seed_lo, seed_hi;  // 64-bit Philox key of this query
-    uint32_t pad;
+    uint32_t psum_base; // first per-probe accumulator of a query whose probes are split
 };
 
-// A work-group chunk: probes [k0, k0 + kc) of query q, all R replicas.
+// A work-group chunk: replicas [p0, p0 + pc) of probes [k0, k0 + kc) of query q.
+// Either pc == R (whole probes), or kc == 1 and the probe's replicas are split
+// over several chunks whose partial sums meet in a per-probe accumulator.
 struct Chunk {
     uint32_t q;
     uint32_t k0;
     uint32_t kc;
-    uint32_t pad;
+    uint32_t p0;
+    uint32_t pc;
+    uint32_t pad[3];
 };
 
 struct DomainParams {
@@ -55,6 +59,8 @@ struct WalkArgs {
     uint32_t* cursor;               // work-stealing cursor (persistent launches)
     unsigned long long* blocksum;   // [slot][G][2] int128 block sums of trunc(Q 2^64)
     uint32_t* done;                 // [slot] probes finished
+    unsigned long long* psum;       // [probe][4] exact S1, S2 of split probes
+    uint32_t* pcount;               // [probe] replicas finished of split probes
     double* beta;                   // [slot] results
     double* q_debug;                // optional: [K] per-probe Q of the (single) query
     double* ybar_debug;             // optional: [G] block means
@@ -71,6 +77,9 @@ constexpr int kMaxG = 128;
 // Probes with at least this many replicas are run one probe per wave block
 // (wave-uniform probe keys); fewer replicas use the per-lane mapping.
 constexpr uint32_t kUniformMinR = 48;
+// Batched and served launches split a probe whose R exceeds this many replicas
+// into chunks of at most this size (a multiple of 64).
+constexpr uint32_t kSplitReplicas = 4096;
 
 // Launchers (defined in pw_kernels.hip). All return hipError_t of the launch.
 // uniform: every chunk of the launch has R >= kUniformMinR.

@@ -155,13 +155,14 @@ __device__ void run_chunk(const WalkArgs& A, const DevGraph& G, uint32_t ci,
         // registers); only the last block of a probe runs partially masked.
         const uint32_t wave = __builtin_amdgcn_readfirstlane((uint32_t)tid >> 6);
         const uint32_t lane = (uint32_t)tid & 63u;
-        const uint32_t nb = (d.R + 63u) >> 6;
+        const uint32_t nb = (c.pc + 63u) >> 6;
         const uint32_t units = c.kc * nb;
+        const uint32_t pend = c.p0 + c.pc;
         for (uint32_t u = wave; u < units; u += kBlockThreads / 64) {
             const uint32_t kk = u / nb;
-            const uint32_t p = (u - kk * nb) * 64u + lane;
+            const uint32_t p = c.p0 + (u - kk * nb) * 64u + lane;
             const uint32_t k = c.k0 + kk;
-            if (p < d.R) {
+            if (p < pend) {
                 const Probe pr = make_probe(d.seed_lo, d.seed_hi, d.uid, k, G.dom.n);
                 const float U = walk_pair<kLayout>(G, pr, s0, t0, d.L, p, k, d.uid, d.seed_lo, d.seed_hi);
                 lds_add_i128(acc + 4 * kk, fix54(U));
@@ -186,6 +187,39 @@ __device__ void run_chunk(const WalkArgs& A, const DevGraph& G, uint32_t ci,
         }
     }
     __syncthreads();
+
+    if (kUniform && c.pc < d.R) {
+        // Part of a split probe: add the partial sums to the probe's accumulator;
+        // the chunk that brings its replica count to R forms Q_R.
+        if (tid == 0) {
+            const size_t pi = (size_t)d.psum_base + c.k0;
+            unsigned long long* ps = A.psum + pi * 4;
+            atomic_add_i128(ps, (i128)(((u128)acc[1] << 64) | (u128)acc[0]));
+            atomic_add_i128(ps + 2, (i128)(((u128)acc[3] << 64) | (u128)acc[2]));
+            __threadfence();
+            const uint32_t prev = atomicAdd(A.pcount + pi, c.pc);
+            if (prev + c.pc == d.R) {
+                __threadfence();
+                const i128 S1 = load_i128(ps);
+                const u128 S2 = (u128)load_i128(ps + 2);
+                const double Q = probe_q(S1, S2, d.R);
+                if (A.q_debug) A.q_debug[c.k0] = Q;
+                atomic_add_i128(A.blocksum + ((size_t)d.slot * A.gdim + c.k0 / d.B) * 2,
+                                f64_to_i128_trunc(Q * 0x1p64));
+                // every part of this probe has been added: clear it for reuse
+                ps[0] = ps[1] = ps[2] = ps[3] = 0ull;
+                A.pcount[pi] = 0u;
+                __threadfence();
+                const uint32_t old = atomicAdd(A.done + d.slot, 1u);
+                if (old + 1u == d.K) {
+                    __threadfence();
+                    finalize_query(A, d, ys);
+                }
+            }
+        }
+        __syncthreads();
+        return;
+    }
 
     for (uint32_t j = tid; j < c.kc; j += kBlockThreads) {
         const i128 S1 = (i128)(((u128)acc[4 * j + 1] << 64) | (u128)acc[4 * j]);

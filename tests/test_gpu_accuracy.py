@@ -56,7 +56,7 @@ def test_accuracy_cl100k():
     t = ref[:, 2].astype(np.int32)
     beta = ref[:, 5]
     assert np.all(np.abs(ref[:, 6] - beta) <= 1e-10 * beta)  # the two CG solves agree
-    dg = B.graph_load_csr(g.n, g.row_ptr, g.col, B.BD_LAYOUT_CSR | B.BD_RELABEL_DEGREE)
+    dg = B.graph_load_csr(g.n, g.row_ptr, g.col, B.BD_LAYOUT_COMPACT)
     res, st = B.bd_query_batch(dg, s, t, 0.05, 1000, SEED, budget_policy("cl100k"),
                                B.exec_cfg("batched"), with_stats=True)
     assert np.all(res["status"] == 0)

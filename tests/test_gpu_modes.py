@@ -1,0 +1,144 @@
+"""Execution modes on the GPU: split probes, batched work stealing and the
+served mode (continuous batching), each checked bit for bit against the
+oracle or against another mode (all sums are exact, so every mode must agree
+exactly).
+"""
+
+import sys
+import time
+
+import numpy as np
+import pytest
+
+from oracle import estimator as E
+from oracle import planner as OP
+from paper_2512_05460_amd import binding as B
+from synth import graphs, queries
+
+pytestmark = pytest.mark.gpu
+
+SEED = 0x5E12ED
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+_cache = {}
+
+
+def _graph(key, flags):
+    if (key, flags) not in _cache:
+        g = graphs.workload_graph(key)
+        _cache[(key, flags)] = (g, B.graph_load_csr(g.n, g.row_ptr, g.col, flags))
+    return _cache[(key, flags)]
+
+
+@pytest.mark.parametrize("flags", [B.BD_LAYOUT_COMPACT, B.BD_LAYOUT_CSR | B.BD_RELABEL_DEGREE])
+def test_split_probe_parity(flags):
+    # R = 5000 > 4096: batched and served launches cut each probe's replicas
+    # into parts (2560 + 2440); plain launches keep whole probes.
+    g, dg = _graph("ba1k", flags)
+    s, t, L = 10, 900, 5
+    pol = B.policy("fixed", B=1, R=5000)
+    plan = OP.plan(0.1, L, 1, 1, 1, OP.Policy("fixed", B_fixed=1, R_fixed=5000))
+    ob, oq, oy = E.estimate(g, [s], [t], L, [plan], SEED, uid=[3], want_q=True, threads=1)
+    for mode in ("batched", "plain"):
+        res, q, y = B.bd_query_probes(dg, s, t, 0.1, L, 3, SEED, pol, B.exec_cfg(mode))
+        assert np.array_equal(q, oq), mode
+        assert np.array_equal(y, oy) and res["beta"] == ob[0]
+
+
+def _mixed(g, n, seed, Ls=(0, 3, 20, 100)):
+    s, t = queries.uniform_pairs(g.n, n, seed)
+    eps, L = queries.mixed_eps_L(n, [0.3, 0.5], list(Ls), seed + 1)
+    return s, t, eps, L
+
+
+def test_batched_equals_plain_with_splits():
+    g, dg = _graph("ba1k", B.BD_LAYOUT_COMPACT)
+    s, t, eps, L = _mixed(g, 12, 5)
+    hubs = np.argsort(g.deg)[::-1][:4].astype(np.int32)
+    s = np.concatenate([s, hubs[:2]])
+    t = np.concatenate([t, hubs[2:]])
+    eps = np.concatenate([eps, [0.5, 0.5]])
+    L = np.concatenate([L, [100, 100]]).astype(np.int32)
+    pol = B.policy("scaled", c_B=0.02, c_R=0.2)  # R from 2 to > 4096: small-R, whole and split probes
+    plan = B.bd_plan(dg, s, t, eps, L, pol)
+    _say("R range", plan["R"].min(), plan["R"].max())
+    assert plan["R"].max() > 4096 and plan["R"].min() < 48
+    a = B.bd_query_batch(dg, s, t, eps, L, SEED, pol, B.exec_cfg("plain"))
+    b = B.bd_query_batch(dg, s, t, eps, L, SEED, pol, B.exec_cfg("batched"))
+    c = B.bd_query_batch(dg, s, t, eps, L, SEED, pol, B.exec_cfg("batched", grid_wgs=7))
+    assert np.array_equal(a["beta"], b["beta"]) and np.array_equal(a["beta"], c["beta"])
+
+
+def test_served_alone_equals_mix():
+    g, dg = _graph("ba1k", B.BD_LAYOUT_COMPACT)
+    pol = B.policy("scaled", c_B=0.05, c_R=0.005)
+    srv = B.Server(dg, pol, max_queries=4096)
+    try:
+        s, t, eps, L = _mixed(g, 6, 21)
+        uid = np.arange(6) + 1000
+        rid = srv.submit(s, t, eps, L, SEED, uid=uid)
+        alone, lat = srv.wait(rid)
+        assert np.all(alone["status"] == 0)
+        # the same request again, now among many others submitted around it
+        others = []
+        for j in range(8):
+            so, to, eo, lo = _mixed(g, 1 + 5 * j, 100 + j)
+            others.append(srv.submit(so, to, eo, lo, SEED + j, uid=np.arange(so.size) + 50 * j))
+            if j == 3:
+                rid2 = srv.submit(s, t, eps, L, SEED, uid=uid)
+        mixed, lat2 = srv.wait(rid2)
+        for r in others:
+            out, _ = srv.wait(r)
+            assert np.all(out["status"] == 0)
+        assert np.array_equal(alone["beta"], mixed["beta"])
+        _say(f"[served] latency alone {lat:.1f} ms, in the mix {lat2:.1f} ms")
+        # and equal to the batched call with the same uids
+        ref = B.bd_query_batch(dg, s, t, eps, L, SEED, pol, uid=uid)
+        assert np.array_equal(ref["beta"], alone["beta"])
+    finally:
+        srv.destroy()
+
+
+def test_served_admission_caps_and_split():
+    g, dg = _graph("ba1k", B.BD_LAYOUT_COMPACT)
+    pol = B.policy("fixed", B=1, R=4500)  # every probe split into two parts
+    srv = B.Server(dg, pol, max_queries=4)
+    try:
+        with pytest.raises(B.ProbeWalkError) as ei:
+            srv.submit(np.arange(5), np.arange(5) + 10, 0.1, 3, SEED)
+        assert ei.value.code == B.BD_E_FULL
+        rids, inputs = [], []
+        for j in range(5):
+            s, t = queries.uniform_pairs(g.n, 3, 300 + j)
+            L = np.array([2, 3, 4], dtype=np.int32)
+            inputs.append((s, t, L))
+            rids.append(srv.submit(s, t, 0.1, L, SEED, uid=np.arange(3) + 10 * j))
+        done = set()
+        t0 = time.time()
+        while len(done) < len(rids) and time.time() - t0 < 60:
+            for i, r in enumerate(rids):
+                if i in done:
+                    continue
+                ok, out, lat = srv.poll(r)
+                if ok:
+                    s, t, L = inputs[i]
+                    ref = B.bd_query_batch(dg, s, t, 0.1, L, SEED, pol, uid=np.arange(3) + 10 * i)
+                    assert np.array_equal(out["beta"], ref["beta"])
+                    done.add(i)
+            time.sleep(0.01)
+        assert len(done) == len(rids)
+    finally:
+        srv.destroy()
+
+
+def test_served_destroy_with_pending_work():
+    g, dg = _graph("ba1k", B.BD_LAYOUT_COMPACT)
+    srv = B.Server(dg, B.policy("fixed", B=4, R=256), max_queries=2)
+    for j in range(6):
+        s, t = queries.uniform_pairs(g.n, 2, 700 + j)
+        srv.submit(s, t, 0.1, 50, SEED)
+    srv.destroy()  # must return: in-flight slices drain, pending requests are cancelled
