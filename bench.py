@@ -96,6 +96,44 @@ def cpu_baseline(g, s, t, plans, seed, target_s=20.0):
                        f"{dt:.1f} s; queries/s = steps/s / mean full-query steps of the batch")}
 
 
+def small_queries(B, torch, stream):
+    """The regime where one query cannot fill the GPU: BA n=1,000, 256 uniform
+    pairs, eps=0.1, L=200 (a few 10^8 walk steps per query), plain vs batched
+    vs batched replayed from a captured hipGraph."""
+    from paper_2512_05460_amd.budgets import budget_policy
+    from synth import graphs, queries
+
+    g = graphs.workload_graph("ba1k")
+    s, t = queries.uniform_pairs(g.n, 256, graphs.GRAPH_SEED + 0 + graphs.QUERY_SEED_OFFSET)
+    dg = B.graph_load_csr(g.n, g.row_ptr, g.col, B.BD_LAYOUT_COMPACT)
+    pol = budget_policy("ba1k")
+    seed = graphs.PHILOX_SEED
+    out = {"workload": "Barabasi-Albert n=1,000 m=3; 256 uniform pairs; eps=0.1, L=200"}
+
+    def timed(fn, reps=3):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps
+
+    plain = B.exec_cfg("plain")
+    dt_plain = timed(lambda: [B.bd_query_batch(dg, s[i:i + 1], t[i:i + 1], 0.1, 200, seed, pol, plain,
+                                               uid=[i], stream=stream) for i in range(256)], reps=1)
+    dt_batched = timed(lambda: B.bd_query_batch(dg, s, t, 0.1, 200, seed, pol, B.exec_cfg("batched"),
+                                                stream=stream))
+    dt_graph = timed(lambda: B.bd_query_batch(dg, s, t, 0.1, 200, seed, pol,
+                                              B.exec_cfg("batched", use_graph=True), stream=stream))
+    steps = float(B.bd_plan(dg, s, t, 0.1, 200, pol)["walk_steps"].sum())
+    out.update({"walk_steps": steps, "plain_qps": 256 / dt_plain, "batched_qps": 256 / dt_batched,
+                "graph_qps": 256 / dt_graph, "batched_vs_plain": dt_plain / dt_batched,
+                "graph_vs_plain": dt_plain / dt_graph})
+    dg.free()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -106,6 +144,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--no-roofline", action="store_true")
+    ap.add_argument("--no-small", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calib", type=int, default=0,
                     help="also run a device copy of this many MiB (counter calibration)")
@@ -199,6 +238,8 @@ def main():
         srv.destroy()
         extra["served"] = {"queries_per_s": nq / dts, "vs_plain": (nq / dts) / qps,
                            "request_latency_ms": lats}
+    if not args.no_small:
+        extra["small_queries"] = small_queries(B, torch, stream)
     roof = None
     if not args.no_roofline:
         log("gather roofline")

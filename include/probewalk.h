@@ -130,9 +130,12 @@ int bd_plan(const bd_graph* g, int64_t nq, const int32_t* s, const int32_t* t,
 
 typedef struct {
     uint32_t mode;
-    int32_t  chunk_probes;   /* probes per work-group chunk; 0 = automatic */
+    int32_t  chunk_probes;   /* probes per work-group chunk; 0 = from chunk_pairs */
     int32_t  grid_wgs;       /* persistent grid size (BATCHED); 0 = resident capacity */
-    int32_t  use_graph;      /* BATCHED: replay a captured hipGraph of the launch */
+    int32_t  use_graph;      /* BATCHED: replay a captured hipGraph of the launch (work buffers
+                                are reused; the graph is rebuilt when the batch shape changes) */
+    int32_t  chunk_pairs;    /* (probe, replica) pairs per chunk, also the replica-part size of
+                                a split probe (BATCHED); 0 = 256 (PLAIN) / 4096 (BATCHED) */
 } bd_exec;
 
 typedef struct {
@@ -161,6 +164,17 @@ int bd_query_batch(bd_graph* g, int64_t nq, const int32_t* s, const int32_t* t,
                    const double* eps, const int32_t* L, const uint32_t* uid,
                    uint64_t seed, const bd_policy* pol, const bd_exec* exec,
                    void* stream, bd_result* out, bd_stats* stats);
+
+/*
+ * Autotuner: runs the (small, representative) sample batch once per candidate
+ * execution configuration -- chunk_pairs in {1024, 2048, 4096, 8192, 16384} and
+ * mode -- and returns the fastest by walk-kernel time in *best. times_ms (host,
+ * may be NULL) receives the kernel time of each of the n_candidates (<= 16)
+ * candidates in the order listed; *n_candidates is set to the count.
+ */
+int bd_autotune(bd_graph* g, int64_t nq, const int32_t* s, const int32_t* t, const double* eps,
+                const int32_t* L, uint64_t seed, const bd_policy* pol, uint32_t mode, void* stream,
+                bd_exec* best, double* times_ms, int32_t* n_candidates);
 
 /* ---- validation entry points (expose intermediate values for parity tests) -- */
 

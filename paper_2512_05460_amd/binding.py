@@ -54,7 +54,7 @@ BD_MODE_BATCHED = 1
 EXPORTS = ("graph_load_csr", "graph_free", "bd_graph_get_info", "bd_plan", "bd_query_batch",
            "bd_walk_trace", "bd_probe_eval", "bd_query_probes", "bd_server_create",
            "bd_server_submit", "bd_server_poll", "bd_server_wait", "bd_server_destroy",
-           "bd_strerror", "bd_device_info", "bd_gather_roofline")
+           "bd_strerror", "bd_device_info", "bd_gather_roofline", "bd_autotune")
 
 
 class BdPolicy(ctypes.Structure):
@@ -65,7 +65,11 @@ class BdPolicy(ctypes.Structure):
 
 class BdExec(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_uint32), ("chunk_probes", ctypes.c_int32),
-                ("grid_wgs", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
+                ("grid_wgs", ctypes.c_int32), ("use_graph", ctypes.c_int32),
+                ("chunk_pairs", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 class BdStats(ctypes.Structure):
@@ -141,6 +145,8 @@ def lib():
             "bd_strerror": (ctypes.c_char_p, [ctypes.c_int]),
             "bd_device_info": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_size_t]),
             "bd_gather_roofline": (ctypes.c_int, [_P, i32, i32, i32, _P, ctypes.POINTER(BdRoofline)]),
+            "bd_autotune": (ctypes.c_int, [_P, i64, _P, _P, _P, _P, u64, ctypes.POINTER(BdPolicy), u32, _P,
+                                           ctypes.POINTER(BdExec), _P, ctypes.POINTER(i32)]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -184,9 +190,9 @@ def policy(kind="paper", c_B=448.0, c_R=128.0, delta=0.01, B=0, R=0, max_steps=0
     return BdPolicy(k, c_B, c_R, delta, B, R, max_steps)
 
 
-def exec_cfg(mode="batched", chunk_probes=0, grid_wgs=0, use_graph=False) -> BdExec:
+def exec_cfg(mode="batched", chunk_probes=0, grid_wgs=0, use_graph=False, chunk_pairs=0) -> BdExec:
     m = {"plain": BD_MODE_PLAIN, "batched": BD_MODE_BATCHED}[mode]
-    return BdExec(m, chunk_probes, grid_wgs, 1 if use_graph else 0)
+    return BdExec(m, chunk_probes, grid_wgs, 1 if use_graph else 0, chunk_pairs)
 
 
 class Graph:
@@ -374,3 +380,19 @@ def bd_gather_roofline(g: Graph, chains_per_lane: int = 4, steps: int = 2000, wo
     _check(lib().bd_gather_roofline(g.handle, chains_per_lane, steps, work_groups, _stream(stream),
                                     ctypes.byref(r)), "bd_gather_roofline")
     return {f: getattr(r, f) for f, _ in r._fields_}
+
+
+def bd_autotune(g: Graph, s, t, eps, L, seed: int, pol: BdPolicy | None = None, mode: str = "batched",
+                stream=None):
+    """Returns (best BdExec, kernel ms per candidate)."""
+    s, t = _arr(s, np.int32), _arr(t, np.int32)
+    eps = _arr(np.broadcast_to(eps, s.shape), np.float64)
+    L = _arr(np.broadcast_to(L, s.shape), np.int32)
+    best = BdExec()
+    times = np.zeros(16, dtype=np.float64)
+    n = ctypes.c_int32()
+    m = {"plain": BD_MODE_PLAIN, "batched": BD_MODE_BATCHED}[mode]
+    _check(lib().bd_autotune(g.handle, s.size, _ptr(s), _ptr(t), _ptr(eps), _ptr(L), seed & (2 ** 64 - 1),
+                             None if pol is None else ctypes.byref(pol), m, _stream(stream), ctypes.byref(best),
+                             _ptr(times), ctypes.byref(n)), "bd_autotune")
+    return best, times[:n.value]

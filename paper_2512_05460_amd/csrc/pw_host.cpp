@@ -17,7 +17,7 @@
 #include <thread>
 #include <vector>
 
-#include "../../include/probewalk.h"
+#include "probewalk.h"
 #include "pw_internal.hpp"
 
 using namespace pw;
@@ -73,6 +73,26 @@ double now_ms()
 
 }  // namespace
 
+// Work buffers of bd_query_batch, kept with the graph and grown on demand, and
+// the captured hipGraph of the last batched launch shape.
+struct Workspace {
+    DevBuf qd, chunks, bs, done, beta, cursor, psum, pcount, qdbg, ydbg;
+    hipStream_t gstream = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    std::vector<uint64_t> gkey;
+    int64_t graph_builds = 0, graph_replays = 0;
+    int ensure(DevBuf& b, size_t bytes)
+    {
+        if (b.p && b.bytes >= bytes) return BD_OK;
+        return b.alloc(std::max(bytes, 2 * b.bytes));
+    }
+    ~Workspace()
+    {
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+        if (gstream) (void)hipStreamDestroy(gstream);
+    }
+};
+
 struct bd_graph {
     int64_t n = 0, nnz = 0;
     int32_t d_min = 0, d_max = 0;
@@ -85,6 +105,7 @@ struct bd_graph {
     DomainParams dom{};
     int64_t device_bytes = 0;
     std::mutex mu;  // serialises calls that use the per-graph work buffers
+    Workspace ws;
 };
 
 // ---------------------------------------------------------------------------
@@ -453,8 +474,10 @@ struct ChunkPlan {
 ChunkPlan chunk_plan(const bd_exec& ex, uint32_t K, uint32_t R)
 {
     ChunkPlan cp;
-    if (ex.mode != BD_MODE_PLAIN && R >= kUniformMinR && R > kSplitReplicas) {
-        const uint32_t parts = (R + kSplitReplicas - 1) / kSplitReplicas;
+    const uint32_t pairs = ex.chunk_pairs > 0 ? std::max<uint32_t>((uint32_t)ex.chunk_pairs, 64u)
+                           : ex.mode == BD_MODE_PLAIN ? (uint32_t)kBlockThreads : kSplitReplicas;
+    if (ex.mode != BD_MODE_PLAIN && R >= kUniformMinR && R > pairs) {
+        const uint32_t parts = (R + pairs - 1) / pairs;
         cp.part = ((R + parts - 1) / parts + 63u) & ~63u;
         cp.kc = 1;
         return cp;
@@ -463,8 +486,7 @@ ChunkPlan chunk_plan(const bd_exec& ex, uint32_t K, uint32_t R)
     if (ex.chunk_probes > 0) {
         kc = (uint32_t)ex.chunk_probes;
     } else {
-        const uint64_t target = ex.mode == BD_MODE_PLAIN ? (uint64_t)kBlockThreads : (uint64_t)kSplitReplicas;
-        kc = (uint32_t)std::max<uint64_t>(1, (target + R - 1) / R);
+        kc = (uint32_t)std::max<uint64_t>(1, ((uint64_t)pairs + R - 1) / R);
     }
     kc = std::min<uint32_t>(kc, (uint32_t)kMaxChunkProbes);
     kc = std::min<uint32_t>(kc, std::max<uint32_t>(K, 1));
@@ -520,46 +542,79 @@ struct Batch {
 };
 
 // Run one set of valid queries: zero the tables, launch, read the results.
-int run_batch(bd_graph* g, const Batch& b, const bd_exec& ex, hipStream_t st,
+// Work buffers live in the graph's workspace and are reused across calls. With
+// ex.use_graph (batched mode) the zeroing and the persistent launches are
+// captured once per launch shape into a hipGraph on a library-owned stream and
+// replayed; descriptors and chunk tables are copied in before each replay.
+int run_batch(bd_graph* g, const Batch& b, const bd_exec& ex, hipStream_t user_st,
               std::vector<double>& beta, bd_stats* stats, double* q_dbg_host, double* y_dbg_host)
 {
     const size_t nv = b.qd.size();
     if (nv == 0) return BD_OK;
     const size_t gdim = b.G;
-    DevBuf d_qd, d_chunks, d_bs, d_done, d_beta, d_cursor, d_qdbg, d_ydbg, d_psum, d_pcount;
-    int rc = d_qd.alloc(nv * sizeof(QueryDesc));
-    if (rc == BD_OK) rc = d_psum.alloc((size_t)b.split_probes * 32);
-    if (rc == BD_OK) rc = d_pcount.alloc((size_t)b.split_probes * 4);
-    if (rc == BD_OK) rc = d_chunks.alloc(b.chunks.size() * sizeof(Chunk));
-    if (rc == BD_OK) rc = d_bs.alloc(nv * gdim * 16);
-    if (rc == BD_OK) rc = d_done.alloc(nv * 4);
-    if (rc == BD_OK) rc = d_beta.alloc(nv * 8);
-    if (rc == BD_OK) rc = d_cursor.alloc(16);
-    if (rc == BD_OK && q_dbg_host) rc = d_qdbg.alloc((size_t)b.qd[0].K * 8);
-    if (rc == BD_OK && y_dbg_host) rc = d_ydbg.alloc(gdim * 8);
+    Workspace& w = g->ws;
+    const bool graph_mode = ex.use_graph && ex.mode != BD_MODE_PLAIN && !q_dbg_host && !y_dbg_host;
+    if (graph_mode && !w.gstream && hipStreamCreateWithFlags(&w.gstream, hipStreamNonBlocking) != hipSuccess)
+        return BD_E_HIP;
+    hipStream_t st = graph_mode ? w.gstream : user_st;
+    int rc = w.ensure(w.qd, nv * sizeof(QueryDesc));
+    if (rc == BD_OK) rc = w.ensure(w.chunks, b.chunks.size() * sizeof(Chunk));
+    if (rc == BD_OK) rc = w.ensure(w.bs, nv * gdim * 16);
+    if (rc == BD_OK) rc = w.ensure(w.done, nv * 4);
+    if (rc == BD_OK) rc = w.ensure(w.beta, nv * 8);
+    if (rc == BD_OK) rc = w.ensure(w.cursor, 16);
+    if (rc == BD_OK) rc = w.ensure(w.psum, (size_t)b.split_probes * 32);
+    if (rc == BD_OK) rc = w.ensure(w.pcount, (size_t)b.split_probes * 4);
+    if (rc == BD_OK && q_dbg_host) rc = w.ensure(w.qdbg, (size_t)b.qd[0].K * 8);
+    if (rc == BD_OK && y_dbg_host) rc = w.ensure(w.ydbg, gdim * 8);
     if (rc != BD_OK) return rc;
-    HIP_TRY(hipMemcpyAsync(d_qd.p, b.qd.data(), nv * sizeof(QueryDesc), hipMemcpyHostToDevice, st));
-    HIP_TRY(hipMemcpyAsync(d_chunks.p, b.chunks.data(), b.chunks.size() * sizeof(Chunk),
-                           hipMemcpyHostToDevice, st));
-    HIP_TRY(launch_zero(d_bs.p, nv * gdim * 16, st));
-    HIP_TRY(launch_zero(d_done.p, nv * 4, st));
-    HIP_TRY(launch_zero(d_cursor.p, 16, st));
-    HIP_TRY(launch_zero(d_psum.p, (size_t)b.split_probes * 32, st));
-    HIP_TRY(launch_zero(d_pcount.p, (size_t)b.split_probes * 4, st));
+    HIP_TRY(hipMemcpyAsync(w.qd.p, b.qd.data(), nv * sizeof(QueryDesc), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(w.chunks.p, b.chunks.data(), b.chunks.size() * sizeof(Chunk), hipMemcpyHostToDevice,
+                           st));
 
     WalkArgs a{};
     a.g = tables(g);
-    a.qd = d_qd.as<const QueryDesc>();
+    a.qd = w.qd.as<const QueryDesc>();
     a.gdim = (uint32_t)gdim;
-    a.cursor = d_cursor.as<uint32_t>();
-    a.blocksum = d_bs.as<unsigned long long>();
-    a.done = d_done.as<uint32_t>();
-    a.psum = d_psum.as<unsigned long long>();
-    a.pcount = d_pcount.as<uint32_t>();
-    a.beta = d_beta.as<double>();
-    a.q_debug = q_dbg_host ? d_qdbg.as<double>() : nullptr;
-    a.ybar_debug = y_dbg_host ? d_ydbg.as<double>() : nullptr;
+    a.cursor = w.cursor.as<uint32_t>();
+    a.blocksum = w.bs.as<unsigned long long>();
+    a.done = w.done.as<uint32_t>();
+    a.psum = w.psum.as<unsigned long long>();
+    a.pcount = w.pcount.as<uint32_t>();
+    a.beta = w.beta.as<double>();
+    a.q_debug = q_dbg_host ? w.qdbg.as<double>() : nullptr;
+    a.ybar_debug = y_dbg_host ? w.ydbg.as<double>() : nullptr;
     const int layout = g->layout;
+
+    // the zeroing every launch needs
+    auto zero_all = [&](hipStream_t s2) -> int {
+        if (launch_zero(w.bs.p, nv * gdim * 16, s2) != hipSuccess) return BD_E_HIP;
+        if (launch_zero(w.done.p, nv * 4, s2) != hipSuccess) return BD_E_HIP;
+        if (launch_zero(w.cursor.p, 16, s2) != hipSuccess) return BD_E_HIP;
+        if (launch_zero(w.psum.p, (size_t)b.split_probes * 32, s2) != hipSuccess) return BD_E_HIP;
+        if (launch_zero(w.pcount.p, (size_t)b.split_probes * 4, s2) != hipSuccess) return BD_E_HIP;
+        return BD_OK;
+    };
+    // the persistent launches of the batched mode: wave-uniform chunks, then the rest
+    uint32_t grids[2] = {0, 0};
+    const uint32_t parts[3] = {0u, b.n_uniform, (uint32_t)b.chunks.size()};
+    for (int part = 0; part < 2; ++part) {
+        const uint32_t nch = parts[part + 1] - parts[part];
+        uint32_t grid = ex.grid_wgs > 0 ? (uint32_t)ex.grid_wgs : (uint32_t)resident_wgs(g, part == 0);
+        grids[part] = std::min<uint32_t>(grid, nch);
+    }
+    auto launch_persistent = [&](hipStream_t s2) -> int {
+        for (int part = 0; part < 2; ++part) {
+            if (grids[part] == 0) continue;
+            WalkArgs ab = a;
+            ab.chunks = w.chunks.as<const Chunk>() + parts[part];
+            ab.nchunks = parts[part + 1] - parts[part];
+            ab.cursor = w.cursor.as<uint32_t>() + part;
+            ab.persistent = 1;
+            if (launch_walk(ab, layout, part == 0, grids[part], s2) != hipSuccess) return BD_E_HIP;
+        }
+        return BD_OK;
+    };
 
     hipEvent_t e0 = nullptr, e1 = nullptr;
     HIP_TRY(hipEventCreate(&e0));
@@ -570,10 +625,10 @@ int run_batch(bd_graph* g, const Batch& b, const bd_exec& ex, hipStream_t st,
     double kernel_ms = 0.0;
     int64_t launches = 0;
     int status = BD_OK;
-    auto timed_launch = [&](const WalkArgs& args, int uniform, uint32_t grid) -> int {
-        if (grid == 0) return BD_OK;
+    auto timed = [&](auto&& body) -> int {
         if (hipEventRecord(e0, st) != hipSuccess) return BD_E_HIP;
-        if (launch_walk(args, layout, uniform, grid, st) != hipSuccess) return BD_E_HIP;
+        const int r = body();
+        if (r != BD_OK) return r;
         if (hipEventRecord(e1, st) != hipSuccess) return BD_E_HIP;
         if (hipEventSynchronize(e1) != hipSuccess) return BD_E_HIP;
         float ms = 0.f;
@@ -583,40 +638,63 @@ int run_batch(bd_graph* g, const Batch& b, const bd_exec& ex, hipStream_t st,
         return BD_OK;
     };
     if (ex.mode == BD_MODE_PLAIN) {
+        status = zero_all(st);
         // one query per launch, one work group per chunk
         for (size_t q = 0; q < nv && status == BD_OK; ++q) {
             const uint32_t c0 = b.chunk_begin[q];
             const uint32_t c1 = q + 1 < nv ? b.chunk_begin[q + 1] : (uint32_t)b.chunks.size();
             WalkArgs aq = a;
-            aq.chunks = d_chunks.as<const Chunk>() + c0;
+            aq.chunks = w.chunks.as<const Chunk>() + c0;
             aq.nchunks = c1 - c0;
             aq.persistent = 0;
-            status = timed_launch(aq, b.qd[q].R >= kUniformMinR, c1 - c0);
+            const int uniform = b.qd[q].R >= kUniformMinR;
+            status = timed([&] {
+                return launch_walk(aq, layout, uniform, c1 - c0, st) == hipSuccess ? BD_OK : BD_E_HIP;
+            });
         }
+    } else if (!graph_mode) {
+        status = zero_all(st);
+        if (status == BD_OK) status = timed([&] { return launch_persistent(st); });
     } else {
-        // chunks of queries with R >= kUniformMinR come first (wave-uniform
-        // kernel), then the rest; one persistent launch each, own cursor
-        const uint32_t parts[3] = {0u, b.n_uniform, (uint32_t)b.chunks.size()};
-        for (int part = 0; part < 2 && status == BD_OK; ++part) {
-            WalkArgs ab = a;
-            ab.chunks = d_chunks.as<const Chunk>() + parts[part];
-            ab.nchunks = parts[part + 1] - parts[part];
-            ab.cursor = d_cursor.as<uint32_t>() + part;
-            ab.persistent = 1;
-            const int uniform = part == 0;
-            uint32_t grid = ex.grid_wgs > 0 ? (uint32_t)ex.grid_wgs : (uint32_t)resident_wgs(g, uniform);
-            grid = std::min<uint32_t>(grid, ab.nchunks);
-            status = timed_launch(ab, uniform, grid);
+        // key: everything the captured launches depend on
+        const std::vector<uint64_t> key = {nv, b.chunks.size(), b.n_uniform, b.split_probes, gdim, grids[0],
+                                           grids[1], (uint64_t)layout, (uint64_t)(uintptr_t)w.qd.p,
+                                           (uint64_t)(uintptr_t)w.chunks.p, (uint64_t)(uintptr_t)w.bs.p,
+                                           (uint64_t)(uintptr_t)w.psum.p};
+        if (!w.gexec || w.gkey != key) {
+            if (w.gexec) {
+                (void)hipGraphExecDestroy(w.gexec);
+                w.gexec = nullptr;
+            }
+            hipGraph_t graph = nullptr;
+            HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+            int cr = zero_all(st);
+            if (cr == BD_OK) cr = launch_persistent(st);
+            const hipError_t ce = hipStreamEndCapture(st, &graph);
+            if (cr != BD_OK || ce != hipSuccess) {
+                if (graph) (void)hipGraphDestroy(graph);
+                return BD_E_HIP;
+            }
+            const hipError_t ie = hipGraphInstantiate(&w.gexec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (ie != hipSuccess) {
+                w.gexec = nullptr;
+                return BD_E_HIP;
+            }
+            w.gkey = key;
+            ++w.graph_builds;
         }
+        status = timed([&] { return hipGraphLaunch(w.gexec, st) == hipSuccess ? BD_OK : BD_E_HIP; });
+        ++w.graph_replays;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (status != BD_OK) return status;
     beta.resize(nv);
-    HIP_TRY(hipMemcpyAsync(beta.data(), d_beta.p, nv * 8, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(beta.data(), w.beta.p, nv * 8, hipMemcpyDeviceToHost, st));
     if (q_dbg_host)
-        HIP_TRY(hipMemcpyAsync(q_dbg_host, d_qdbg.p, (size_t)b.qd[0].K * 8, hipMemcpyDeviceToHost, st));
-    if (y_dbg_host) HIP_TRY(hipMemcpyAsync(y_dbg_host, d_ydbg.p, gdim * 8, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(q_dbg_host, w.qdbg.p, (size_t)b.qd[0].K * 8, hipMemcpyDeviceToHost, st));
+    if (y_dbg_host) HIP_TRY(hipMemcpyAsync(y_dbg_host, w.ydbg.p, gdim * 8, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     if (stats) {
         stats->walk_kernel_ms += kernel_ms;
@@ -736,6 +814,33 @@ extern "C" int bd_query_probes(bd_graph* g, int32_t s, int32_t t, double eps, in
     const int rc = run_batch(g, b, ex, (hipStream_t)stream, beta, nullptr, q_out, ybar_out);
     if (rc != BD_OK) return rc;
     out->beta = beta[0];
+    return BD_OK;
+}
+
+extern "C" int bd_autotune(bd_graph* g, int64_t nq, const int32_t* s, const int32_t* t, const double* eps,
+                           const int32_t* L, uint64_t seed, const bd_policy* pol, uint32_t mode, void* stream,
+                           bd_exec* best, double* times_ms, int32_t* n_candidates)
+{
+    if (!g || !best || nq < 1 || !s || !t || !eps || !L) return BD_E_INVALID;
+    const int32_t cands[5] = {1024, 2048, 4096, 8192, 16384};
+    std::vector<bd_result> res((size_t)nq);
+    double best_ms = 1e300;
+    int n = 0;
+    for (int i = 0; i < 5; ++i) {
+        bd_exec ex{};
+        ex.mode = mode;
+        ex.chunk_pairs = mode == BD_MODE_PLAIN ? cands[i] / 16 : cands[i];
+        bd_stats st{};
+        const int rc = bd_query_batch(g, nq, s, t, eps, L, nullptr, seed, pol, &ex, stream, res.data(), &st);
+        if (rc != BD_OK) return rc;
+        if (times_ms) times_ms[n] = st.walk_kernel_ms;
+        ++n;
+        if (st.walk_kernel_ms < best_ms) {
+            best_ms = st.walk_kernel_ms;
+            *best = ex;
+        }
+    }
+    if (n_candidates) *n_candidates = n;
     return BD_OK;
 }
 

@@ -77,7 +77,7 @@ def test_graph_checks_reject_bad_input():
 def test_result_layout_matches_header():
     assert binding.RESULT_DTYPE.itemsize == 48
     assert ctypes.sizeof(binding.BdPolicy) == 56
-    assert ctypes.sizeof(binding.BdExec) == 16
+    assert ctypes.sizeof(binding.BdExec) == 20
     assert ctypes.sizeof(binding.BdStats) == 48
     assert ctypes.sizeof(binding.BdServerCfg) == 88
 

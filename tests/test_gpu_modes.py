@@ -142,3 +142,38 @@ def test_served_destroy_with_pending_work():
         s, t = queries.uniform_pairs(g.n, 2, 700 + j)
         srv.submit(s, t, 0.1, 50, SEED)
     srv.destroy()  # must return: in-flight slices drain, pending requests are cancelled
+
+
+def test_graph_replay_matches_eager():
+    g, dg = _graph("ba1k", B.BD_LAYOUT_COMPACT)
+    pol = B.policy("scaled", c_B=0.05, c_R=0.05)
+    ex_graph = B.exec_cfg("batched", use_graph=True)
+    ex_eager = B.exec_cfg("batched")
+    # fixed endpoints, eps and L keep the launch shape; seeds and uids vary per replay
+    s = np.full(16, 7, dtype=np.int32)
+    t = np.full(16, 900, dtype=np.int32)
+    eps = np.full(16, 0.3)
+    L = np.full(16, 100, dtype=np.int32)
+    for rep in range(4):
+        seed = SEED + 17 * rep
+        uid = np.arange(16) + 100 * rep
+        got = B.bd_query_batch(dg, s, t, eps, L, seed, pol, ex_graph, uid=uid)
+        # eager work in between replays
+        other = B.bd_query_batch(dg, s[:3], t[:3] + 1, eps[:3], L[:3], seed + 1, pol, ex_eager)
+        assert np.all(other["status"] == 0)
+        ref = B.bd_query_batch(dg, s, t, eps, L, seed, pol, ex_eager, uid=uid)
+        assert np.array_equal(got["beta"], ref["beta"]), rep
+        again = B.bd_query_batch(dg, s, t, eps, L, seed, pol, ex_graph, uid=uid)
+        assert np.array_equal(again["beta"], ref["beta"]), rep
+
+
+def test_autotune():
+    g, dg = _graph("ba1k", B.BD_LAYOUT_COMPACT)
+    s, t = queries.uniform_pairs(g.n, 8, 77)
+    pol = B.policy("scaled", c_B=0.05, c_R=0.05)
+    best, times = B.bd_autotune(dg, s, t, 0.3, 100, SEED, pol, "batched")
+    _say(f"[autotune] best chunk_pairs={best.chunk_pairs} times={np.round(times, 2)}")
+    assert len(times) == 5 and best.chunk_pairs in (1024, 2048, 4096, 8192, 16384)
+    a = B.bd_query_batch(dg, s, t, 0.3, 100, SEED, pol, best)
+    b = B.bd_query_batch(dg, s, t, 0.3, 100, SEED, pol)
+    assert np.array_equal(a["beta"], b["beta"])
