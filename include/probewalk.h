@@ -166,6 +166,49 @@ int bd_query_batch(bd_graph* g, int64_t nq, const int32_t* s, const int32_t* t,
                    void* stream, bd_result* out, bd_stats* stats);
 
 /*
+ * The truncated distance beta^(L)(s,t) = ||h||^2 - (1^T h)^2 / n with
+ * h = sum_{i=0..L} P^i D^{-1} b_st (Lemma 2.3), in binary64 on the device by
+ * L sparse products (the paper's PUSH series; a deterministic reference for
+ * the estimator, which is unbiased for beta^(L) by Lemma 3.3).
+ *   beta_L  host, nq doubles.  Up to 64 queries share one pass.
+ */
+int bd_truncated_beta(bd_graph* g, int64_t nq, const int32_t* s, const int32_t* t, int32_t L,
+                      void* stream, double* beta_L);
+
+/*
+ * The mixing factor lambda = max(|lambda_2|, |lambda_n|) of P = D^{-1} A
+ * (section 2.1), estimated by `iters` power iterations on D^{-1/2} A D^{-1/2}
+ * (same spectrum) with the stationary direction projected out; the estimate
+ * is ||N x|| for the unit iterate x, which converges to lambda from below.
+ */
+int bd_graph_lambda(bd_graph* g, int32_t iters, uint64_t seed, void* stream, double* lambda);
+
+/*
+ * Truncation length of Theorem 3.8 (Algorithm 1, first line):
+ * L = ceil(log(96 n / (eps (1-lambda)^2 (1/d_s + 1/d_t)^2)) / log(1/lambda)).
+ * Host-only. BD_E_RANGE unless 0 < lambda < 1 (a bipartite graph has lambda = 1);
+ * values above 16383 are reported as 16384.
+ */
+int bd_theorem_L(const bd_graph* g, int64_t nq, const int32_t* s, const int32_t* t, const double* eps,
+                 double lambda, int32_t* L);
+
+/*
+ * Truncation length by the stabilization rule (section 4.3): starting at
+ * L = L0 = 1, estimate at L and 2L; accept L_stop = 2L and beta-hat^(2L) when
+ * |beta-hat^(2L) - beta-hat^(L)| <= (eps/2) |beta-hat^(2L)|, else double L.
+ * Doubling stops at L_max (out[i] is then the estimate at L_max and
+ * L_stop[i] = L_max). Each round runs every still-unstopped query in one
+ * batched launch; estimates at a given L are the same as bd_query_batch's.
+ *   L_max   cap on L (1 <= L_max <= 16383).
+ *   L_stop  host, nq int32 (the accepted truncation length per query).
+ * Other arguments as bd_query_batch (eps[] is the relative-error target).
+ */
+int bd_query_stabilized(bd_graph* g, int64_t nq, const int32_t* s, const int32_t* t,
+                        const double* eps, int32_t L_max, const uint32_t* uid, uint64_t seed,
+                        const bd_policy* pol, const bd_exec* exec, void* stream,
+                        bd_result* out, int32_t* L_stop);
+
+/*
  * Autotuner: runs the (small, representative) sample batch once per candidate
  * execution configuration -- chunk_pairs in {1024, 2048, 4096, 8192, 16384} and
  * mode -- and returns the fastest by walk-kernel time in *best. times_ms (host,

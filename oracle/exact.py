@@ -11,6 +11,8 @@ TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).
     beta = b^T y with (L + 11^T/n) y = x from a second solve.
   * ``h_truncated`` / ``beta_truncated``: the truncated series of Lemma 2.3,
     h^(L) = sum_{i=0..L} P^i D^{-1} b, beta^(L) = ||h||^2 - (1^T h)^2 / n.
+  * ``mixing_factor``: lambda = max(|lambda_2|, |lambda_n|) of P (section 2.1)
+    from the dense spectrum of D^{-1/2} A D^{-1/2}, which P is similar to.
 """
 
 from __future__ import annotations
@@ -113,3 +115,11 @@ def beta_truncated(g, s: int, t: int, L: int) -> float:
 def phi(g, s: int, t: int, L: int, z: np.ndarray) -> float:
     """phi(z) = z^T h^(L) (Lemma 3.3)."""
     return float(np.asarray(z, dtype=np.float64) @ h_truncated(g, s, t, L))
+
+
+def mixing_factor(g) -> float:
+    """max(|lambda_2|, |lambda_n|) over the eigenvalues of P (dense; small graphs)."""
+    A = g.scipy().toarray()
+    r = 1.0 / np.sqrt(g.deg.astype(np.float64))
+    ev = np.sort(np.linalg.eigvalsh(A * r[:, None] * r[None, :]))
+    return float(max(abs(ev[-2]), abs(ev[0])))

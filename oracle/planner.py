@@ -56,3 +56,9 @@ def plan(eps: float, L: int, d_s: int, d_t: int, d_min: int, policy: Policy = PA
     B = max(B, 1)
     R = max(R, 2)
     return B, G, B * G, R
+
+
+def theorem_L(n: int, eps: float, lam: float, d_s: int, d_t: int) -> int:
+    """Truncation length of Theorem 3.8 (Algorithm 1, first line)."""
+    arg = 96.0 * n / (eps * (1.0 - lam) ** 2 * (1.0 / d_s + 1.0 / d_t) ** 2)
+    return ceil_guarded(math.log(arg) / math.log(1.0 / lam))

@@ -54,7 +54,8 @@ BD_MODE_BATCHED = 1
 EXPORTS = ("graph_load_csr", "graph_free", "bd_graph_get_info", "bd_plan", "bd_query_batch",
            "bd_walk_trace", "bd_probe_eval", "bd_query_probes", "bd_server_create",
            "bd_server_submit", "bd_server_poll", "bd_server_wait", "bd_server_destroy",
-           "bd_strerror", "bd_device_info", "bd_gather_roofline", "bd_autotune")
+           "bd_strerror", "bd_device_info", "bd_gather_roofline", "bd_autotune",
+           "bd_query_stabilized", "bd_truncated_beta", "bd_graph_lambda", "bd_theorem_L")
 
 
 class BdPolicy(ctypes.Structure):
@@ -145,6 +146,11 @@ def lib():
             "bd_strerror": (ctypes.c_char_p, [ctypes.c_int]),
             "bd_device_info": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_size_t]),
             "bd_gather_roofline": (ctypes.c_int, [_P, i32, i32, i32, _P, ctypes.POINTER(BdRoofline)]),
+            "bd_truncated_beta": (ctypes.c_int, [_P, i64, _P, _P, i32, _P, _P]),
+            "bd_graph_lambda": (ctypes.c_int, [_P, i32, u64, _P, ctypes.POINTER(ctypes.c_double)]),
+            "bd_theorem_L": (ctypes.c_int, [_P, i64, _P, _P, _P, ctypes.c_double, _P]),
+            "bd_query_stabilized": (ctypes.c_int, [_P, i64, _P, _P, _P, i32, _P, u64, ctypes.POINTER(BdPolicy),
+                                                   ctypes.POINTER(BdExec), _P, _P, _P]),
             "bd_autotune": (ctypes.c_int, [_P, i64, _P, _P, _P, _P, u64, ctypes.POINTER(BdPolicy), u32, _P,
                                            ctypes.POINTER(BdExec), _P, ctypes.POINTER(i32)]),
         }
@@ -396,3 +402,40 @@ def bd_autotune(g: Graph, s, t, eps, L, seed: int, pol: BdPolicy | None = None, 
                              None if pol is None else ctypes.byref(pol), m, _stream(stream), ctypes.byref(best),
                              _ptr(times), ctypes.byref(n)), "bd_autotune")
     return best, times[:n.value]
+
+
+def bd_query_stabilized(g: Graph, s, t, eps, L_max: int, seed: int, pol: BdPolicy | None = None,
+                        ex: BdExec | None = None, uid=None, stream=None):
+    """Returns (results, L_stop) -- the stabilization rule of section 4.3."""
+    s, t = _arr(s, np.int32), _arr(t, np.int32)
+    eps = _arr(np.broadcast_to(eps, s.shape), np.float64)
+    u = None if uid is None else _arr(uid, np.uint32)
+    out = np.zeros(s.size, dtype=RESULT_DTYPE)
+    Ls = np.zeros(s.size, dtype=np.int32)
+    _check(lib().bd_query_stabilized(g.handle, s.size, _ptr(s), _ptr(t), _ptr(eps), L_max, _ptr(u),
+                                     seed & (2 ** 64 - 1), None if pol is None else ctypes.byref(pol),
+                                     None if ex is None else ctypes.byref(ex), _stream(stream), _ptr(out),
+                                     _ptr(Ls)), "bd_query_stabilized")
+    return out, Ls
+
+
+def bd_truncated_beta(g: Graph, s, t, L: int, stream=None) -> np.ndarray:
+    s, t = _arr(s, np.int32), _arr(t, np.int32)
+    out = np.zeros(s.size, dtype=np.float64)
+    _check(lib().bd_truncated_beta(g.handle, s.size, _ptr(s), _ptr(t), L, _stream(stream), _ptr(out)),
+           "bd_truncated_beta")
+    return out
+
+
+def bd_graph_lambda(g: Graph, iters: int = 500, seed: int = 1, stream=None) -> float:
+    lam = ctypes.c_double()
+    _check(lib().bd_graph_lambda(g.handle, iters, seed, _stream(stream), ctypes.byref(lam)), "bd_graph_lambda")
+    return lam.value
+
+
+def bd_theorem_L(g: Graph, s, t, eps, lam: float) -> np.ndarray:
+    s, t = _arr(s, np.int32), _arr(t, np.int32)
+    eps = _arr(np.broadcast_to(eps, s.shape), np.float64)
+    out = np.zeros(s.size, dtype=np.int32)
+    _check(lib().bd_theorem_L(g.handle, s.size, _ptr(s), _ptr(t), _ptr(eps), lam, _ptr(out)), "bd_theorem_L")
+    return out

@@ -295,7 +295,11 @@ extern "C" int graph_load_csr(int64_t n, const int64_t* row_ptr, const int32_t* 
             return BD_E_HIP;
         }
     } else {
-        rc = g->node.alloc((size_t)n * 16);
+        rp32.resize((size_t)n + 1);
+        for (int64_t i = 0; i < n; ++i) rp32[(size_t)i] = nodetab[(size_t)i * 4];
+        rp32[(size_t)n] = (uint32_t)nnz;
+        rc = g->rp32.alloc(rp32.size() * 4);
+        if (rc == BD_OK) rc = g->node.alloc((size_t)n * 16);
         if (rc == BD_OK) rc = g->col.alloc((size_t)std::max<int64_t>(nnz, 1) * 4);
         if (rc == BD_OK && g->layout == 1) rc = g->adj.alloc((size_t)std::max<int64_t>(nnz, 1) * 16);
         if (rc != BD_OK) {
@@ -303,6 +307,7 @@ extern "C" int graph_load_csr(int64_t n, const int64_t* row_ptr, const int32_t* 
             return rc;
         }
         if (hipMemcpyAsync(g->node.p, nodetab.data(), (size_t)n * 16, hipMemcpyHostToDevice, st) != hipSuccess ||
+            hipMemcpyAsync(g->rp32.p, rp32.data(), rp32.size() * 4, hipMemcpyHostToDevice, st) != hipSuccess ||
             hipMemcpyAsync(g->col.p, col_store, (size_t)nnz * 4, hipMemcpyHostToDevice, st) != hipSuccess) {
             delete g;
             return BD_E_HIP;
@@ -814,6 +819,210 @@ extern "C" int bd_query_probes(bd_graph* g, int32_t s, int32_t t, double eps, in
     const int rc = run_batch(g, b, ex, (hipStream_t)stream, beta, nullptr, q_out, ybar_out);
     if (rc != BD_OK) return rc;
     out->beta = beta[0];
+    return BD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Truncated series in binary64 and the spectral quantities of Lemma 2.3 /
+// Theorem 3.8
+// ---------------------------------------------------------------------------
+extern "C" int bd_truncated_beta(bd_graph* g, int64_t nq, const int32_t* s, const int32_t* t, int32_t L,
+                                 void* stream, double* beta_L)
+{
+    if (!g || nq < 0 || L < 0 || (nq > 0 && (!s || !t || !beta_L))) return BD_E_INVALID;
+    for (int64_t i = 0; i < nq; ++i)
+        if (s[i] < 0 || t[i] < 0 || s[i] >= g->n || t[i] >= g->n || s[i] == t[i]) return BD_E_INVALID;
+    std::lock_guard<std::mutex> lock(g->mu);
+    hipStream_t st = (hipStream_t)stream;
+    const uint32_t n = (uint32_t)g->n;
+    const uint32_t* rp = g->rp32.as<const uint32_t>();
+    const uint32_t* col = g->layout == 2 ? nullptr : g->col.as<const uint32_t>();
+    const uint32_t* col24 = g->layout == 2 ? g->col24.as<const uint32_t>() : nullptr;
+    for (int64_t q0 = 0; q0 < nq; q0 += 64) {
+        const uint32_t Q = (uint32_t)std::min<int64_t>(64, nq - q0);
+        const size_t bytes = (size_t)n * Q * 8;
+        DevBuf dv, dy, dh, dsq, dlin;
+        int rc = dv.alloc(bytes);
+        if (rc == BD_OK) rc = dy.alloc(bytes);
+        if (rc == BD_OK) rc = dh.alloc(bytes);
+        if (rc == BD_OK) rc = dsq.alloc(Q * 8);
+        if (rc == BD_OK) rc = dlin.alloc(Q * 8);
+        if (rc != BD_OK) return rc;
+        // v_0 = D^{-1} b_st in storage ids
+        std::vector<double> v0((size_t)n * Q, 0.0);
+        for (uint32_t q = 0; q < Q; ++q) {
+            const int32_t a = s[q0 + q], b = t[q0 + q];
+            v0[(size_t)storage_id(g, a) * Q + q] = 1.0 / (double)g->deg[(size_t)a];
+            v0[(size_t)storage_id(g, b) * Q + q] = -1.0 / (double)g->deg[(size_t)b];
+        }
+        HIP_TRY(hipMemcpyAsync(dv.p, v0.data(), bytes, hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(dh.p, v0.data(), bytes, hipMemcpyHostToDevice, st));
+        for (int32_t i = 0; i < L; ++i) {
+            HIP_TRY(launch_spmv_step(rp, col, col24, n, Q, dv.as<double>(), dy.as<double>(), dh.as<double>(), st));
+            std::swap(dv.p, dy.p);
+        }
+        HIP_TRY(launch_colsum(dh.as<double>(), n, Q, dsq.as<double>(), dlin.as<double>(), st));
+        std::vector<double> sq(Q), lin(Q);
+        HIP_TRY(hipMemcpyAsync(sq.data(), dsq.p, Q * 8, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(lin.data(), dlin.p, Q * 8, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        for (uint32_t q = 0; q < Q; ++q) beta_L[q0 + q] = sq[q] - lin[q] * lin[q] / (double)n;
+    }
+    return BD_OK;
+}
+
+extern "C" int bd_graph_lambda(bd_graph* g, int32_t iters, uint64_t seed, void* stream, double* lambda)
+{
+    if (!g || iters < 1 || !lambda) return BD_E_INVALID;
+    std::lock_guard<std::mutex> lock(g->mu);
+    hipStream_t st = (hipStream_t)stream;
+    const uint32_t n = (uint32_t)g->n;
+    const uint32_t* rp = g->rp32.as<const uint32_t>();
+    const uint32_t* col = g->layout == 2 ? nullptr : g->col.as<const uint32_t>();
+    const uint32_t* col24 = g->layout == 2 ? g->col24.as<const uint32_t>() : nullptr;
+    // phi = sqrt(d) / ||sqrt(d)|| in storage order; x0 from a seeded LCG, made orthogonal to phi
+    std::vector<double> phi(n), x(n), y(n);
+    double nrm = 0.0;
+    for (uint32_t i = 0; i < n; ++i) {
+        phi[i] = std::sqrt((double)g->deg[(size_t)i]);
+        nrm += phi[i] * phi[i];
+    }
+    if (!g->internal.empty()) {
+        for (uint32_t v = 0; v < n; ++v) y[g->internal[v]] = phi[v];
+        phi.swap(y);
+    }
+    nrm = std::sqrt(nrm);
+    for (auto& p : phi) p /= nrm;
+    uint64_t r = seed | 1u;
+    auto project = [&](std::vector<double>& v) {
+        double dot = 0.0, nn = 0.0;
+        for (uint32_t i = 0; i < n; ++i) dot += phi[i] * v[i];
+        for (uint32_t i = 0; i < n; ++i) {
+            v[i] -= dot * phi[i];
+            nn += v[i] * v[i];
+        }
+        return std::sqrt(nn);
+    };
+    for (uint32_t i = 0; i < n; ++i) {
+        r = r * 6364136223846793005ull + 1442695040888963407ull;
+        x[i] = (double)(r >> 11) * 0x1p-53 - 0.5;
+    }
+    double nx = project(x);
+    for (auto& v : x) v /= nx;
+    DevBuf dx, dy;
+    int rc = dx.alloc((size_t)n * 8);
+    if (rc == BD_OK) rc = dy.alloc((size_t)n * 8);
+    if (rc != BD_OK) return rc;
+    double est = 0.0;
+    for (int32_t it = 0; it < iters; ++it) {
+        HIP_TRY(hipMemcpyAsync(dx.p, x.data(), (size_t)n * 8, hipMemcpyHostToDevice, st));
+        HIP_TRY(launch_nmul(rp, col, col24, n, dx.as<double>(), dy.as<double>(), st));
+        HIP_TRY(hipMemcpyAsync(y.data(), dy.p, (size_t)n * 8, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        const double ny = project(y);  // ||N x|| off the stationary direction, with ||x|| = 1
+        est = ny;
+        if (ny == 0.0) break;
+        for (uint32_t i = 0; i < n; ++i) x[i] = y[i] / ny;
+    }
+    *lambda = est;
+    return BD_OK;
+}
+
+extern "C" int bd_theorem_L(const bd_graph* g, int64_t nq, const int32_t* s, const int32_t* t, const double* eps,
+                            double lambda, int32_t* L)
+{
+    if (!g || nq < 0 || (nq > 0 && (!s || !t || !eps || !L))) return BD_E_INVALID;
+    if (!(lambda > 0.0 && lambda < 1.0)) return BD_E_RANGE;
+    for (int64_t i = 0; i < nq; ++i) {
+        if (s[i] < 0 || t[i] < 0 || s[i] >= g->n || t[i] >= g->n || s[i] == t[i] || !(eps[i] > 0 && eps[i] < 1))
+            return BD_E_INVALID;
+        const double inv = 1.0 / g->deg[(size_t)s[i]] + 1.0 / g->deg[(size_t)t[i]];
+        const double arg = 96.0 * (double)g->n / (eps[i] * (1.0 - lambda) * (1.0 - lambda) * inv * inv);
+        const double v = std::ceil(std::log(arg) / std::log(1.0 / lambda) * kCeilGuard);
+        L[i] = v > (double)kMaxL ? kMaxL + 1 : (int32_t)std::max(0.0, v);
+    }
+    return BD_OK;
+}
+
+extern "C" int bd_query_stabilized(bd_graph* g, int64_t nq, const int32_t* s, const int32_t* t,
+                                   const double* eps, int32_t L_max, const uint32_t* uid, uint64_t seed,
+                                   const bd_policy* pol, const bd_exec* exec, void* stream, bd_result* out,
+                                   int32_t* L_stop)
+{
+    if (!g || nq < 0 || (nq > 0 && (!s || !t || !eps || !out || !L_stop)) || L_max < 1 || L_max > kMaxL)
+        return BD_E_INVALID;
+    bd_exec ex{};
+    ex.mode = BD_MODE_BATCHED;
+    if (exec) ex = *exec;
+    std::vector<uint32_t> ids((size_t)nq);
+    for (int64_t i = 0; i < nq; ++i) ids[(size_t)i] = uid ? uid[i] : (uint32_t)i;
+    // estimate at L for the listed queries (their own uids, so each estimate
+    // equals the one bd_query_batch gives for that query and L)
+    auto run = [&](const std::vector<int64_t>& idx, const std::vector<int32_t>& Ls, std::vector<bd_result>& res) {
+        const size_t m = idx.size();
+        std::vector<int32_t> ss(m), tt(m);
+        std::vector<double> ee(m);
+        std::vector<uint32_t> uu(m);
+        for (size_t j = 0; j < m; ++j) {
+            ss[j] = s[idx[j]];
+            tt[j] = t[idx[j]];
+            ee[j] = eps[idx[j]];
+            uu[j] = ids[(size_t)idx[j]];
+        }
+        res.assign(m, bd_result{});
+        return bd_query_batch(g, (int64_t)m, ss.data(), tt.data(), ee.data(), Ls.data(), uu.data(), seed, pol,
+                              &ex, stream, res.data(), nullptr);
+    };
+    std::vector<int64_t> live;
+    std::vector<bd_result> prev((size_t)nq);  // estimate at the current L
+    std::vector<int32_t> curL((size_t)nq, 1);
+    for (int64_t i = 0; i < nq; ++i) {
+        live.push_back(i);
+        L_stop[i] = 0;
+    }
+    {  // L0 = 1
+        std::vector<int32_t> Ls(live.size(), 1);
+        std::vector<bd_result> res;
+        const int rc = run(live, Ls, res);
+        if (rc != BD_OK) return rc;
+        for (size_t j = 0; j < live.size(); ++j) prev[(size_t)live[j]] = res[j];
+    }
+    std::vector<int64_t> next;
+    for (int64_t i : live) {
+        if (prev[(size_t)i].status != BD_OK) {
+            out[i] = prev[(size_t)i];
+            L_stop[i] = 1;
+        } else if (L_max == 1) {
+            out[i] = prev[(size_t)i];
+            L_stop[i] = 1;
+        } else {
+            next.push_back(i);
+        }
+    }
+    live.swap(next);
+    while (!live.empty()) {
+        std::vector<int32_t> Ls(live.size());
+        for (size_t j = 0; j < live.size(); ++j) Ls[j] = std::min<int32_t>(2 * curL[(size_t)live[j]], L_max);
+        std::vector<bd_result> res;
+        const int rc = run(live, Ls, res);
+        if (rc != BD_OK) return rc;
+        next.clear();
+        for (size_t j = 0; j < live.size(); ++j) {
+            const int64_t i = live[j];
+            const bd_result& r2 = res[j];
+            const bd_result& r1 = prev[(size_t)i];
+            const bool stable = r2.status == BD_OK && std::fabs(r2.beta - r1.beta) <= 0.5 * eps[i] * std::fabs(r2.beta);
+            if (r2.status != BD_OK || stable || Ls[j] >= L_max) {
+                out[i] = r2;
+                L_stop[i] = Ls[j];
+            } else {
+                prev[(size_t)i] = r2;
+                curL[(size_t)i] = Ls[j];
+                next.push_back(i);
+            }
+        }
+        live.swap(next);
+    }
     return BD_OK;
 }
 

@@ -98,6 +98,13 @@ hipError_t build_fat_adjacency(const uint4* node, const uint32_t* col, uint4* ad
 // Gather-roofline microbenchmark: `chains` in {1, 2, 4, 8} chains per lane.
 hipError_t launch_gather(const GraphTables& g, int layout, int chains, uint32_t grid, int32_t steps, uint32_t seed,
                          uint32_t* sink, hipStream_t st);
+// Binary64 truncated series and spectral helpers (row offsets rp[0..n], and
+// either col (32-bit ids) or col24 (packed 3-byte ids)).
+hipError_t launch_spmv_step(const uint32_t* rp, const uint32_t* col, const uint32_t* col24, uint32_t n, uint32_t Q,
+                            const double* V, double* Y, double* H, hipStream_t st);
+hipError_t launch_colsum(const double* H, uint32_t n, uint32_t Q, double* sq, double* lin, hipStream_t st);
+hipError_t launch_nmul(const uint32_t* rp, const uint32_t* col, const uint32_t* col24, uint32_t n, const double* x,
+                       double* y, hipStream_t st);
 // Work groups of the walk kernel that fit on the device at once.
 int walk_occupancy(int layout, int uniform, int* wgs_per_cu);
 

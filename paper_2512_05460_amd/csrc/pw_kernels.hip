@@ -466,3 +466,118 @@ hipError_t launch_gather(const GraphTables& g, int layout, int chains, uint32_t 
 }
 
 }  // namespace pw
+
+namespace pw {
+
+// ---------------------------------------------------------------------------
+// Truncated series in binary64 (Lemma 2.3): h^(L) = sum_{i<=L} P^i D^{-1} b for
+// Q queries at once. V and Y are n x Q row-major; one wave per row, lanes over
+// queries, so the neighbour gathers of a row read Q consecutive values.
+//   y[x][q] = (1/d_x) * sum_{u in N(x)} v[u][q]     (in neighbour order)
+//   h[x][q] += y[x][q]
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void spmv_step_kernel(const uint32_t* rp, const uint32_t* col,
+                                                        const uint32_t* col24, uint32_t n, uint32_t Q,
+                                                        const double* V, double* Y, double* H)
+{
+    const uint32_t row = blockIdx.x * 4u + (threadIdx.x >> 6);
+    const uint32_t lane = threadIdx.x & 63u;
+    if (row >= n) return;
+    const uint32_t b = rp[row], e = rp[row + 1];
+    for (uint32_t q0 = 0; q0 < Q; q0 += 64u) {
+        const uint32_t q = q0 + lane;
+        if (q < Q) {
+            double acc = 0.0;
+            for (uint32_t i = b; i < e; ++i) {
+                uint32_t u;
+                if (col24) {
+                    const uint32_t o = i * 3u;
+                    u = __builtin_amdgcn_alignbit(col24[(o >> 2) + 1], col24[o >> 2], (o & 3u) * 8u) & 0xFFFFFFu;
+                } else {
+                    u = col[i];
+                }
+                acc = __dadd_rn(acc, V[(size_t)u * Q + q]);
+            }
+            const double y = __dmul_rn(acc, __ddiv_rn(1.0, (double)(e - b)));
+            Y[(size_t)row * Q + q] = y;
+            H[(size_t)row * Q + q] = __dadd_rn(H[(size_t)row * Q + q], y);
+        }
+    }
+}
+
+// Per-query sums ||h||^2 and 1^T h in a fixed order: one work group per query,
+// a strided partial per thread, then a fixed tree in LDS.
+__global__ __launch_bounds__(256) void colsum_kernel(const double* H, uint32_t n, uint32_t Q, double* sq,
+                                                     double* lin)
+{
+    __shared__ double a[256], c[256];
+    const uint32_t q = blockIdx.x;
+    double s2 = 0.0, s1 = 0.0;
+    for (uint32_t x = threadIdx.x; x < n; x += 256u) {
+        const double h = H[(size_t)x * Q + q];
+        s2 = __dadd_rn(s2, __dmul_rn(h, h));
+        s1 = __dadd_rn(s1, h);
+    }
+    a[threadIdx.x] = s2;
+    c[threadIdx.x] = s1;
+    __syncthreads();
+    for (uint32_t w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+            a[threadIdx.x] = __dadd_rn(a[threadIdx.x], a[threadIdx.x + w]);
+            c[threadIdx.x] = __dadd_rn(c[threadIdx.x], c[threadIdx.x + w]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        sq[q] = a[0];
+        lin[q] = c[0];
+    }
+}
+
+hipError_t launch_spmv_step(const uint32_t* rp, const uint32_t* col, const uint32_t* col24, uint32_t n, uint32_t Q,
+                            const double* V, double* Y, double* H, hipStream_t st)
+{
+    hipLaunchKernelGGL(spmv_step_kernel, dim3((n + 3) / 4), dim3(256), 0, st, rp, col, col24, n, Q, V, Y, H);
+    return hipGetLastError();
+}
+
+hipError_t launch_colsum(const double* H, uint32_t n, uint32_t Q, double* sq, double* lin, hipStream_t st)
+{
+    hipLaunchKernelGGL(colsum_kernel, dim3(Q), dim3(256), 0, st, H, n, Q, sq, lin);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Spectral radius of P off the stationary direction: power iteration on the
+// symmetric N = D^{-1/2} A D^{-1/2} (same spectrum as P) with the top
+// eigenvector sqrt(d)/||sqrt(d)|| projected out each step.
+//   y = N x; then y -= (phi . y) phi
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void nmul_kernel(const uint32_t* rp, const uint32_t* col, const uint32_t* col24,
+                                                   uint32_t n, const double* x, double* y)
+{
+    const uint32_t row = blockIdx.x * blockDim.x + threadIdx.x;
+    if (row >= n) return;
+    const uint32_t b = rp[row], e = rp[row + 1];
+    double acc = 0.0;
+    for (uint32_t i = b; i < e; ++i) {
+        uint32_t u;
+        if (col24) {
+            const uint32_t o = i * 3u;
+            u = __builtin_amdgcn_alignbit(col24[(o >> 2) + 1], col24[o >> 2], (o & 3u) * 8u) & 0xFFFFFFu;
+        } else {
+            u = col[i];
+        }
+        acc = __dadd_rn(acc, __ddiv_rn(x[u], sqrt((double)(rp[u + 1] - rp[u]))));
+    }
+    y[row] = __ddiv_rn(acc, sqrt((double)(e - b)));
+}
+
+hipError_t launch_nmul(const uint32_t* rp, const uint32_t* col, const uint32_t* col24, uint32_t n, const double* x,
+                       double* y, hipStream_t st)
+{
+    hipLaunchKernelGGL(nmul_kernel, dim3((n + 255) / 256), dim3(256), 0, st, rp, col, col24, n, x, y);
+    return hipGetLastError();
+}
+
+}  // namespace pw

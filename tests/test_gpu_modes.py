@@ -177,3 +177,54 @@ def test_autotune():
     a = B.bd_query_batch(dg, s, t, 0.3, 100, SEED, pol, best)
     b = B.bd_query_batch(dg, s, t, 0.3, 100, SEED, pol)
     assert np.array_equal(a["beta"], b["beta"])
+
+
+# ---------------------------------------------------------------------------
+# Truncated series, mixing factor, Theorem 3.8's L, stabilization rule
+# ---------------------------------------------------------------------------
+from oracle import exact as X  # noqa: E402
+from oracle import stabilize as OS  # noqa: E402
+
+
+@pytest.mark.parametrize("key,flags", [("ba1k", B.BD_LAYOUT_COMPACT), ("ba1k", B.BD_LAYOUT_CSR | B.BD_RELABEL_DEGREE),
+                                       ("cl100k", B.BD_LAYOUT_COMPACT)])
+def test_truncated_beta_vs_oracle(key, flags):
+    g, dg = _graph(key, flags)
+    s, t = queries.uniform_pairs(g.n, 70, 11)
+    for L in ((0, 1, 7, 200) if key == "ba1k" else (50,)):
+        got = B.bd_truncated_beta(dg, s, t, L)
+        idx = range(70) if key == "ba1k" else range(0, 70, 10)
+        for i in idx:
+            ref = X.beta_truncated(g, int(s[i]), int(t[i]), L)
+            assert got[i] == pytest.approx(ref, rel=1e-11), (L, i)
+
+
+@pytest.mark.parametrize("maker,lam", [(lambda: graphs.complete_graph(7), 1 / 6),
+                                       (lambda: graphs.cycle_graph(9), float(np.cos(np.pi / 9)))])
+def test_lambda_closed_forms(maker, lam):
+    g = maker()
+    dg = B.graph_load_csr(g.n, g.row_ptr, g.col, B.BD_LAYOUT_CSR)
+    assert B.bd_graph_lambda(dg, 300, 7) == pytest.approx(lam, rel=1e-8)
+
+
+def test_lambda_ba1k_and_theorem_L():
+    g, dg = _graph("ba1k", B.BD_LAYOUT_COMPACT)
+    ref = X.mixing_factor(g)
+    lam = B.bd_graph_lambda(dg, 3000, 3)
+    _say(f"[lambda] ba1k dense {ref:.8f} power {lam:.8f}")
+    assert lam == pytest.approx(ref, rel=1e-4)
+    s, t = queries.uniform_pairs(g.n, 20, 4)
+    Ls = B.bd_theorem_L(dg, s, t, 0.1, ref)
+    for i in range(20):
+        assert Ls[i] == OP.theorem_L(g.n, 0.1, ref, int(g.deg[s[i]]), int(g.deg[t[i]]))
+
+
+def test_stabilized_matches_oracle():
+    g, dg = _graph("ba1k", B.BD_LAYOUT_COMPACT)
+    s, t = queries.uniform_pairs(g.n, 6, 9)
+    pol = B.policy("scaled", c_B=0.05, c_R=0.05)
+    opol = OP.Policy("scaled", c_B=0.05, c_R=0.05)
+    res, Ls = B.bd_query_stabilized(dg, s, t, 0.3, 64, SEED, pol, uid=np.arange(6))
+    for i in range(6):
+        ob, oL = OS.stabilized(g, int(s[i]), int(t[i]), 0.3, 64, SEED, i, opol)
+        assert Ls[i] == oL and res["beta"][i] == ob, (i, Ls[i], oL)
