@@ -134,6 +134,74 @@ def small_queries(B, torch, stream):
     return out
 
 
+def grid_batched(B, torch, stream, plain_sample=512):
+    """Mixed eps and L in one persistent launch: the 1,414 x 1,414 grid (5% of
+    edges removed), 65,536 queries, eps over {0.02, 0.05, 0.1}, L over {500,
+    2000, 5000}, throughput walk counts; chunking from the autotuner, the
+    launches captured into a hipGraph and run from it. The plain mode (one
+    query per launch) runs the first `plain_sample` queries of the same set."""
+    from paper_2512_05460_amd.budgets import BUDGETS, budget_policy
+    from synth import graphs, queries
+
+    g = graphs.workload_graph("grid1414")
+    s, t, eps, Ls = queries.workload_batch("grid1414", g.n)
+    nq = s.size
+    dg = B.graph_load_csr(g.n, g.row_ptr, g.col, B.BD_LAYOUT_COMPACT)
+    pol = budget_policy("grid1414")
+    seed = graphs.PHILOX_SEED
+    plan = B.bd_plan(dg, s, t, eps, Ls, pol)
+    steps = float(plan["walk_steps"].sum())
+    na = min(nq, 2048)
+    log(f"grid: {nq} queries, {steps:.3e} walk steps; autotune on the first {na}")
+    best, times = B.bd_autotune(dg, s[:na], t[:na], eps[:na], Ls[:na], seed, pol, stream=stream)
+    ex = B.exec_cfg("batched", chunk_pairs=best.chunk_pairs, use_graph=True, queues=best.queues)
+    log(f"grid: chunk_pairs={best.chunk_pairs} queues={best.queues}; capture and launch the whole set")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r, st = B.bd_query_batch(dg, s, t, eps, Ls, seed, pol, ex, stream=stream, with_stats=True)
+    torch.cuda.synchronize()
+    dt_graph = time.perf_counter() - t0
+    assert np.all(r["status"] == 0)
+    roof = max((B.bd_gather_roofline(dg, c, 2000) for c in (2, 4, 8)), key=lambda x: x["steps_per_s"])
+    m = plain_sample
+    plain = B.exec_cfg("plain")
+    log(f"grid: plain mode on the first {m} queries")
+    t0 = time.perf_counter()
+    for i in range(m):
+        B.bd_query_batch(dg, s[i:i + 1], t[i:i + 1], eps[i:i + 1], Ls[i:i + 1], seed, pol, plain,
+                         uid=[i], stream=stream)
+    torch.cuda.synchronize()
+    dt_plain = time.perf_counter() - t0
+    steps_m = float(plan["walk_steps"][:m].sum())
+    t0 = time.perf_counter()
+    B.bd_query_batch(dg, s[:m], t[:m], eps[:m], Ls[:m], seed, pol, B.exec_cfg("batched", chunk_pairs=best.chunk_pairs),
+                     stream=stream)
+    torch.cuda.synchronize()
+    dt_batched_m = time.perf_counter() - t0
+    dg.free()
+    c_B, c_R, how = BUDGETS["grid1414"]
+    return {
+        "workload": ("1,414 x 1,414 grid, 5% of edges removed, connected (bipartite); 65,536 uniform pairs, "
+                     "eps over {0.02, 0.05, 0.1}, L over {500, 2000, 5000}"),
+        "policy": {"kind": "scaled", "c_B": c_B, "c_R": c_R, "calibration": how},
+        "R_range": [int(plan["R"].min()), int(plan["R"].max())],
+        "walk_steps": steps,
+        "autotune": {"chunk_pairs": best.chunk_pairs, "queues": best.queues,
+                     "sample_queries": na, "kernel_ms": [float(x) for x in times]},
+        "graph_qps": nq / dt_graph,
+        "graph_walk_steps_per_s": steps / dt_graph,
+        "kernel_ms": st["walk_kernel_ms"],
+        "kernel_walk_steps_per_s": steps / (st["walk_kernel_ms"] / 1e3),
+        "gather_roofline_steps_per_s": roof["steps_per_s"],
+        "gather_roofline_frac": steps / (st["walk_kernel_ms"] / 1e3) / roof["steps_per_s"],
+        "plain_sample": m,
+        "plain_qps": m / dt_plain,
+        "plain_walk_steps_per_s": steps_m / dt_plain,
+        "batched_same_sample_qps": m / dt_batched_m,
+        "graph_vs_plain_walk_steps_per_s": (steps / dt_graph) / (steps_m / dt_plain),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -145,6 +213,7 @@ def main():
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--no-roofline", action="store_true")
     ap.add_argument("--no-small", action="store_true")
+    ap.add_argument("--no-grid", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calib", type=int, default=0,
                     help="also run a device copy of this many MiB (counter calibration)")
@@ -240,6 +309,8 @@ def main():
                            "request_latency_ms": lats}
     if not args.no_small:
         extra["small_queries"] = small_queries(B, torch, stream)
+    if not args.no_grid:
+        extra["grid_batched"] = grid_batched(B, torch, stream)
     roof = None
     if not args.no_roofline:
         log("gather roofline")

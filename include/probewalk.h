@@ -136,6 +136,10 @@ typedef struct {
                                 are reused; the graph is rebuilt when the batch shape changes) */
     int32_t  chunk_pairs;    /* (probe, replica) pairs per chunk, also the replica-part size of
                                 a split probe (BATCHED); 0 = 256 (PLAIN) / 4096 (BATCHED) */
+    int32_t  queues;         /* BATCHED: chunk queues of the persistent launch, 1..8. A query's
+                                chunks stay in one queue and a work group takes chunks from the
+                                queue of the XCD it runs on before the others, so they share
+                                that XCD's L2. 0 = 8. Results do not depend on it. */
 } bd_exec;
 
 typedef struct {
@@ -210,10 +214,11 @@ int bd_query_stabilized(bd_graph* g, int64_t nq, const int32_t* s, const int32_t
 
 /*
  * Autotuner: runs the (small, representative) sample batch once per candidate
- * execution configuration -- chunk_pairs in {1024, 2048, 4096, 8192, 16384} and
- * mode -- and returns the fastest by walk-kernel time in *best. times_ms (host,
- * may be NULL) receives the kernel time of each of the n_candidates (<= 16)
- * candidates in the order listed; *n_candidates is set to the count.
+ * execution configuration and returns the fastest by walk-kernel time in *best:
+ * chunk_pairs in {1024, 2048, 4096, 8192, 16384} with 8 chunk queues, then (BATCHED)
+ * the best of those with 1 queue. times_ms (host, may be NULL) receives the
+ * kernel time of each of the n_candidates (<= 16) candidates in that order;
+ * *n_candidates is set to the count.
  */
 int bd_autotune(bd_graph* g, int64_t nq, const int32_t* s, const int32_t* t, const double* eps,
                 const int32_t* L, uint64_t seed, const bd_policy* pol, uint32_t mode, void* stream,

@@ -112,6 +112,38 @@ def beta_truncated(g, s: int, t: int, L: int) -> float:
     return float(h @ h - h.sum() ** 2 / g.n)
 
 
+def beta_truncated_multi(g, s, t, Ls) -> np.ndarray:
+    """beta^(L)(s_j, t_j) for every pair j and every L in ``Ls``: out[i, j] for Ls[i].
+
+    The same series as ``h_truncated``, run once for all pairs as columns of one
+    matrix; h^(L) for a smaller L is a partial sum of the series for a larger L.
+    """
+    s = np.asarray(s, dtype=np.int64)
+    t = np.asarray(t, dtype=np.int64)
+    Ls = [int(x) for x in Ls]
+    A = g.scipy().astype(np.float64)
+    dinv = 1.0 / g.deg.astype(np.float64)
+    m = s.size
+    cols = np.arange(m)
+    V = np.zeros((g.n, m))
+    V[s, cols] += dinv[s]
+    V[t, cols] -= dinv[t]
+    H = V.copy()
+    out = np.zeros((len(Ls), m))
+
+    def record(step):
+        for i, L in enumerate(Ls):
+            if L == step:
+                out[i] = (H * H).sum(axis=0) - H.sum(axis=0) ** 2 / g.n
+
+    record(0)
+    for step in range(1, max(Ls) + 1):
+        V = dinv[:, None] * (A @ V)
+        H += V
+        record(step)
+    return out
+
+
 def phi(g, s: int, t: int, L: int, z: np.ndarray) -> float:
     """phi(z) = z^T h^(L) (Lemma 3.3)."""
     return float(np.asarray(z, dtype=np.float64) @ h_truncated(g, s, t, L))

@@ -471,6 +471,12 @@ int resident_wgs(const bd_graph* g, int uniform)
 //   batched / served: whole probes up to kSplitReplicas pairs per chunk, and a
 //   probe with R > kSplitReplicas is cut into replica parts (multiples of 64)
 //   so that no chunk runs much longer than the others.
+uint32_t exec_queues(const bd_exec& ex)
+{
+    if (ex.queues <= 0) return kMaxQueues;
+    return std::min<uint32_t>((uint32_t)ex.queues, kMaxQueues);
+}
+
 struct ChunkPlan {
     uint32_t kc = 1;       // probes per chunk (whole-probe chunks)
     uint32_t part = 0;     // replicas per part, 0 = probes are not split
@@ -544,6 +550,10 @@ struct Batch {
     std::vector<int64_t> index;         // valid query -> caller's index
     uint32_t G = 0;
     uint32_t n_uniform = 0;             // chunks [0, n_uniform) belong to queries with R >= kUniformMinR
+    // chunk queues of the persistent launches: part 0 = [0, n_uniform), part 1 =
+    // the rest; qoff[part][i] is the first chunk of queue i relative to the part
+    uint32_t nqueues = 1;
+    uint32_t qoff[2][kMaxQueues + 1] = {};
 };
 
 // Run one set of valid queries: zero the tables, launch, read the results.
@@ -567,7 +577,7 @@ int run_batch(bd_graph* g, const Batch& b, const bd_exec& ex, hipStream_t user_s
     if (rc == BD_OK) rc = w.ensure(w.bs, nv * gdim * 16);
     if (rc == BD_OK) rc = w.ensure(w.done, nv * 4);
     if (rc == BD_OK) rc = w.ensure(w.beta, nv * 8);
-    if (rc == BD_OK) rc = w.ensure(w.cursor, 16);
+    if (rc == BD_OK) rc = w.ensure(w.cursor, 2 * kMaxQueues * 4);
     if (rc == BD_OK) rc = w.ensure(w.psum, (size_t)b.split_probes * 32);
     if (rc == BD_OK) rc = w.ensure(w.pcount, (size_t)b.split_probes * 4);
     if (rc == BD_OK && q_dbg_host) rc = w.ensure(w.qdbg, (size_t)b.qd[0].K * 8);
@@ -595,7 +605,7 @@ int run_batch(bd_graph* g, const Batch& b, const bd_exec& ex, hipStream_t user_s
     auto zero_all = [&](hipStream_t s2) -> int {
         if (launch_zero(w.bs.p, nv * gdim * 16, s2) != hipSuccess) return BD_E_HIP;
         if (launch_zero(w.done.p, nv * 4, s2) != hipSuccess) return BD_E_HIP;
-        if (launch_zero(w.cursor.p, 16, s2) != hipSuccess) return BD_E_HIP;
+        if (launch_zero(w.cursor.p, 2 * kMaxQueues * 4, s2) != hipSuccess) return BD_E_HIP;
         if (launch_zero(w.psum.p, (size_t)b.split_probes * 32, s2) != hipSuccess) return BD_E_HIP;
         if (launch_zero(w.pcount.p, (size_t)b.split_probes * 4, s2) != hipSuccess) return BD_E_HIP;
         return BD_OK;
@@ -614,8 +624,10 @@ int run_batch(bd_graph* g, const Batch& b, const bd_exec& ex, hipStream_t user_s
             WalkArgs ab = a;
             ab.chunks = w.chunks.as<const Chunk>() + parts[part];
             ab.nchunks = parts[part + 1] - parts[part];
-            ab.cursor = w.cursor.as<uint32_t>() + part;
+            ab.cursor = w.cursor.as<uint32_t>() + part * kMaxQueues;
             ab.persistent = 1;
+            ab.nqueues = b.nqueues;
+            for (uint32_t i = 0; i <= b.nqueues; ++i) ab.qoff[i] = b.qoff[part][i];
             if (launch_walk(ab, layout, part == 0, grids[part], s2) != hipSuccess) return BD_E_HIP;
         }
         return BD_OK;
@@ -662,10 +674,12 @@ int run_batch(bd_graph* g, const Batch& b, const bd_exec& ex, hipStream_t user_s
         if (status == BD_OK) status = timed([&] { return launch_persistent(st); });
     } else {
         // key: everything the captured launches depend on
-        const std::vector<uint64_t> key = {nv, b.chunks.size(), b.n_uniform, b.split_probes, gdim, grids[0],
+        std::vector<uint64_t> key = {nv, b.chunks.size(), b.n_uniform, b.split_probes, gdim, grids[0],
                                            grids[1], (uint64_t)layout, (uint64_t)(uintptr_t)w.qd.p,
                                            (uint64_t)(uintptr_t)w.chunks.p, (uint64_t)(uintptr_t)w.bs.p,
-                                           (uint64_t)(uintptr_t)w.psum.p};
+                                           (uint64_t)(uintptr_t)w.psum.p, b.nqueues};
+        for (int part = 0; part < 2; ++part)
+            for (uint32_t i = 0; i <= b.nqueues; ++i) key.push_back(b.qoff[part][i]);
         if (!w.gexec || w.gkey != key) {
             if (w.gexec) {
                 (void)hipGraphExecDestroy(w.gexec);
@@ -734,19 +748,19 @@ void build_batch(const bd_graph* g, int64_t nq, const int32_t* s, const int32_t*
     }
     // chunk table: grouped by query; batched launches order queries by
     // descending cost so the longest work starts first
+    auto cost = [&](size_t q) { return (double)b.qd[q].K * b.qd[q].R * (double)b.qd[q].L; };
+    auto uniform = [&](size_t q) { return ex.mode != BD_MODE_PLAIN && b.qd[q].R >= kUniformMinR; };
     std::vector<size_t> order(b.qd.size());
     for (size_t i = 0; i < order.size(); ++i) order[i] = i;
     if (ex.mode != BD_MODE_PLAIN) {
         std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) {
-            const bool ux = b.qd[x].R >= kUniformMinR, uy = b.qd[y].R >= kUniformMinR;
-            if (ux != uy) return ux;
-            const double cx = (double)b.qd[x].L * b.qd[x].R, cy = (double)b.qd[y].L * b.qd[y].R;
-            return cx > cy;
+            if (uniform(x) != uniform(y)) return uniform(x);
+            return cost(x) > cost(y);
         });
     }
+    b.nqueues = ex.mode == BD_MODE_PLAIN ? 1u : exec_queues(ex);
     b.chunk_begin.assign(b.qd.size(), 0);
-    for (size_t oi = 0; oi < order.size(); ++oi) {
-        const size_t q = order[oi];
+    auto emit = [&](size_t q) {
         QueryDesc& d = b.qd[q];
         ChunkCursor cur;
         cur.q = (uint32_t)q;
@@ -759,7 +773,29 @@ void build_batch(const bd_graph* g, int64_t nq, const int32_t* s, const int32_t*
         }
         b.chunk_begin[q] = (uint32_t)b.chunks.size();
         while (!cur.done()) b.chunks.push_back(cur.next());
-        if (ex.mode != BD_MODE_PLAIN && d.R >= kUniformMinR) b.n_uniform = (uint32_t)b.chunks.size();
+    };
+    // each part (wave-uniform queries, then the rest) is dealt into nqueues
+    // queues by longest-processing-time-first on the walk steps, so the queues
+    // carry about equal work; a query's chunks stay together in one queue
+    const size_t split = (size_t)(std::find_if(order.begin(), order.end(), [&](size_t q) { return !uniform(q); }) -
+                                  order.begin());
+    for (int part = 0; part < 2; ++part) {
+        const size_t o0 = part == 0 ? 0 : split, o1 = part == 0 ? split : order.size();
+        const uint32_t base = (uint32_t)b.chunks.size();
+        std::vector<std::vector<size_t>> bins(b.nqueues);
+        std::vector<double> load(b.nqueues, 0.0);
+        for (size_t oi = o0; oi < o1; ++oi) {
+            const size_t q = order[oi];
+            const size_t i = (size_t)(std::min_element(load.begin(), load.end()) - load.begin());
+            bins[i].push_back(q);
+            load[i] += cost(q);
+        }
+        for (uint32_t i = 0; i < b.nqueues; ++i) {
+            b.qoff[part][i] = (uint32_t)b.chunks.size() - base;
+            for (size_t q : bins[i]) emit(q);
+        }
+        b.qoff[part][b.nqueues] = (uint32_t)b.chunks.size() - base;
+        if (part == 0) b.n_uniform = (uint32_t)b.chunks.size();
     }
     (void)g;
 }
@@ -1035,10 +1071,7 @@ extern "C" int bd_autotune(bd_graph* g, int64_t nq, const int32_t* s, const int3
     std::vector<bd_result> res((size_t)nq);
     double best_ms = 1e300;
     int n = 0;
-    for (int i = 0; i < 5; ++i) {
-        bd_exec ex{};
-        ex.mode = mode;
-        ex.chunk_pairs = mode == BD_MODE_PLAIN ? cands[i] / 16 : cands[i];
+    auto trial = [&](const bd_exec& ex) -> int {
         bd_stats st{};
         const int rc = bd_query_batch(g, nq, s, t, eps, L, nullptr, seed, pol, &ex, stream, res.data(), &st);
         if (rc != BD_OK) return rc;
@@ -1048,6 +1081,21 @@ extern "C" int bd_autotune(bd_graph* g, int64_t nq, const int32_t* s, const int3
             best_ms = st.walk_kernel_ms;
             *best = ex;
         }
+        return BD_OK;
+    };
+    for (int i = 0; i < 5; ++i) {
+        bd_exec ex{};
+        ex.mode = mode;
+        ex.chunk_pairs = mode == BD_MODE_PLAIN ? cands[i] / 16 : cands[i];
+        ex.queues = (int32_t)kMaxQueues;
+        const int rc = trial(ex);
+        if (rc != BD_OK) return rc;
+    }
+    if (mode != BD_MODE_PLAIN) {
+        bd_exec ex = *best;
+        ex.queues = 1;
+        const int rc = trial(ex);
+        if (rc != BD_OK) return rc;
     }
     if (n_candidates) *n_candidates = n;
     return BD_OK;
@@ -1493,6 +1541,9 @@ int launch_slice(bd_server* S, Slice& sl)
         ap.chunks = sl.chunks_d.as<const Chunk>() + parts[part];
         ap.nchunks = parts[part + 1] - parts[part];
         ap.cursor = S->d_cursor.as<uint32_t>() + part;
+        ap.nqueues = 1;
+        ap.qoff[0] = 0;
+        ap.qoff[1] = ap.nchunks;
         const uint32_t grid = std::min<uint32_t>((uint32_t)S->resident[part == 0], ap.nchunks);
         if (grid && launch_walk(ap, S->g->layout, part == 0, grid, st) != hipSuccess)
             return BD_E_HIP;

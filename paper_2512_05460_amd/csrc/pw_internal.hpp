@@ -69,9 +69,16 @@ struct WalkArgs {
     uint32_t comp_cap;
     uint32_t recycle;               // clear a finished query's block sums and counter
     uint32_t persistent;
+    // Persistent launches: the chunk table is cut into nqueues segments
+    // [qoff[i], qoff[i+1]), each with its own cursor cursor[i]. A work group
+    // starts on the queue of the XCD it runs on and moves to the next queue
+    // when that one is empty, so chunks of one query share an XCD's L2.
+    uint32_t nqueues;
+    uint32_t qoff[9];
 };
 
 constexpr int kBlockThreads = 256;
+constexpr uint32_t kMaxQueues = 8;      // one chunk queue per XCD
 constexpr int kMaxChunkProbes = 256;
 constexpr int kMaxG = 128;
 // Probes with at least this many replicas are run one probe per wave block

@@ -243,8 +243,10 @@ __device__ void run_chunk(const WalkArgs& A, const DevGraph& G, uint32_t ci,
 }
 
 // kUniform: every chunk of the launch has R >= kUniformMinR (see run_chunk).
+// Eight waves per SIMD where the kernel fits 64 VGPRs without spilling.
 template <int kLayout, int kUniform>
-__global__ __launch_bounds__(kBlockThreads, kUniform ? 8 : 1) void walk_kernel(WalkArgs A)
+__global__ __launch_bounds__(kBlockThreads, (kUniform || kLayout == kLayoutCompact) ? 8 : 1) void walk_kernel(
+    WalkArgs A)
 {
     __shared__ unsigned long long acc[kMaxChunkProbes * 4];
     __shared__ double ys[kMaxG];
@@ -254,8 +256,36 @@ __global__ __launch_bounds__(kBlockThreads, kUniform ? 8 : 1) void walk_kernel(W
         if (blockIdx.x < A.nchunks) run_chunk<kLayout, kUniform>(A, G, blockIdx.x, acc, ys);
         return;
     }
+    // Claim chunks from the queue of this XCD first, then from the others in
+    // turn. A queue seen empty stays empty (its cursor only grows), so each
+    // work group makes at most nqueues failed claims and every wave exits.
+    // (thread 0 keeps the queue state in LDS, so it holds no registers while
+    // the chunk runs)
+    __shared__ uint32_t qstate[2];   // current queue, queues found empty
+    if (threadIdx.x == 0) {
+        uint32_t xcc = 0;
+        if (A.nqueues > 1) asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(xcc));
+        qstate[0] = (xcc & 15u) % A.nqueues;
+        qstate[1] = 0;
+    }
     for (;;) {
-        if (threadIdx.x == 0) next = atomicAdd(A.cursor, 1u);
+        if (threadIdx.x == 0) {
+            uint32_t ci = 0xFFFFFFFFu;
+            uint32_t qi = qstate[0], tried = qstate[1];
+            while (tried < A.nqueues) {
+                const uint32_t beg = A.qoff[qi];
+                const uint32_t c = atomicAdd(A.cursor + qi, 1u);
+                if (c < A.qoff[qi + 1] - beg) {
+                    ci = beg + c;
+                    break;
+                }
+                qi = qi + 1 == A.nqueues ? 0u : qi + 1;
+                ++tried;
+            }
+            qstate[0] = qi;
+            qstate[1] = tried;
+            next = ci;
+        }
         __syncthreads();
         const uint32_t ci = next;
         __syncthreads();

@@ -20,3 +20,26 @@ def mixed_eps_L(count: int, eps_choices, L_choices, seed: int) -> tuple[np.ndarr
     eps = np.asarray(eps_choices, dtype=np.float64)[rng.integers(0, len(eps_choices), size=count)]
     L = np.asarray(L_choices, dtype=np.int32)[rng.integers(0, len(L_choices), size=count)]
     return eps, L
+
+
+# Query sets of the workloads: (pairs, eps choices, L choices); eps and L are
+# drawn per query when more than one value is listed.
+WORKLOAD_QUERIES = {
+    "ba1k": (256, (0.1,), (200,)),
+    "cl100k": (4096, (0.05,), (1000,)),
+    "grid1414": (65536, (0.02, 0.05, 0.1), (500, 2000, 5000)),
+    "cl10m": (4096, (0.02, 0.05, 0.1), (1000,)),
+    "cl40m": (262144, (0.05,), (1000, 10000)),
+}
+
+
+def workload_batch(key: str, n: int, count: int | None = None):
+    """(s, t, eps, L) of a workload's query set (first ``count`` queries)."""
+    from synth.graphs import GRAPH_SEED, QUERY_SEED_OFFSET, WORKLOAD_INDEX
+
+    total, eps_choices, L_choices = WORKLOAD_QUERIES[key]
+    seed = GRAPH_SEED + WORKLOAD_INDEX[key] + QUERY_SEED_OFFSET
+    s, t = uniform_pairs(n, total, seed)
+    eps, L = mixed_eps_L(total, eps_choices, L_choices, seed + 1)
+    m = total if count is None else count
+    return s[:m], t[:m], eps[:m], L[:m]

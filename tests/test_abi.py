@@ -4,6 +4,7 @@ host-side graph checks reject bad input before any device work (CPU only)."""
 import ctypes
 import os
 import re
+import subprocess
 
 import numpy as np
 import pytest
@@ -11,8 +12,8 @@ import pytest
 from paper_2512_05460_amd import binding
 from synth import graphs
 
-HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include",
-                      "probewalk.h")
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "probewalk.h")
 
 
 def _declared():
@@ -74,12 +75,23 @@ def test_graph_checks_reject_bad_input():
         assert rc == binding.BD_E_INVALID
 
 
-def test_result_layout_matches_header():
-    assert binding.RESULT_DTYPE.itemsize == 48
-    assert ctypes.sizeof(binding.BdPolicy) == 56
-    assert ctypes.sizeof(binding.BdExec) == 20
-    assert ctypes.sizeof(binding.BdStats) == 48
-    assert ctypes.sizeof(binding.BdServerCfg) == 88
+def test_result_layout_matches_header(tmp_path):
+    # the ctypes mirrors against the C header as a C compiler lays it out
+    src = tmp_path / "sizes.c"
+    src.write_text('#include <stdio.h>\n#include "probewalk.h"\n'
+                   'int main(void) { printf("%zu %zu %zu %zu %zu %zu %zu\\n", sizeof(bd_result), '
+                   'sizeof(bd_policy), sizeof(bd_exec), sizeof(bd_stats), sizeof(bd_server_cfg), '
+                   'sizeof(bd_graph_info), sizeof(bd_roofline)); return 0; }\n')
+    exe = tmp_path / "sizes"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    sizes = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True,
+                                            check=True).stdout.split()]
+    assert sizes == [binding.RESULT_DTYPE.itemsize, ctypes.sizeof(binding.BdPolicy),
+                     ctypes.sizeof(binding.BdExec), ctypes.sizeof(binding.BdStats),
+                     ctypes.sizeof(binding.BdServerCfg), ctypes.sizeof(binding.BdGraphInfo),
+                     ctypes.sizeof(binding.BdRoofline)]
+    assert ctypes.sizeof(binding.BdExec) == 24
 
 
 def test_binding_has_no_fallback(monkeypatch, tmp_path):

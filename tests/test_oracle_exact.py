@@ -95,6 +95,28 @@ def test_truncated_complete_graph(n, L):
     assert exact.beta_truncated(g, 0, 3, L) == pytest.approx(ref, rel=1e-12)
 
 
+def test_truncated_multi_complete_graph_and_L0():
+    # all pairs of K_n share the closed form; several L from one pass
+    n = 7
+    g = graphs.complete_graph(n)
+    q = -1.0 / (n - 1)
+    Ls = [0, 1, 3, 12]
+    out = exact.beta_truncated_multi(g, [0, 2, 6], [3, 5, 1], Ls)
+    for i, L in enumerate(Ls):
+        ref = 2.0 / n ** 2 * (1.0 - q ** (L + 1)) ** 2
+        assert out[i] == pytest.approx([ref] * 3, rel=1e-12)
+    # L = 0 and large L on a non-complete graph: the L = 0 formula and beta
+    g = graphs.random_connected(30, 0.15, 9)
+    d = g.deg
+    s, t = np.array([0, 4, 29]), np.array([1, 17, 3])
+    out = exact.beta_truncated_multi(g, s, t, [0, 2000])
+    ref0 = (1 / d[s] ** 2 + 1 / d[t] ** 2) - (1 / d[s] - 1 / d[t]) ** 2 / g.n
+    assert out[0] == pytest.approx(ref0, rel=1e-13)
+    Lp = exact.pinv_dense(g)
+    ref = [exact.beta_dense(g, int(a), int(b), Lp)[0] for a, b in zip(s, t)]
+    assert out[1] == pytest.approx(ref, rel=1e-9)
+
+
 def test_truncated_L0_formula():
     g = graphs.random_connected(30, 0.15, 9)
     d = g.deg
