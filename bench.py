@@ -202,6 +202,84 @@ def grid_batched(B, torch, stream, plain_sample=512):
     }
 
 
+def served_cl10m(B, torch, seconds_per_load=10.0):
+    """Continuous batching under Poisson arrivals: Chung-Lu n=10^7 (mean degree
+    10, exponent 2.3, largest component, compact layout resident on the
+    device); request batches of 2^U uniform pairs (U uniform on 0..12, 1 to
+    4,096 pairs), eps per query from {0.02, 0.05, 0.1}, L=1000, throughput walk
+    counts. Capacity comes from a burst of requests submitted at once; then
+    Poisson arrivals at 50%, 80% and 95% of it, each for `seconds_per_load`
+    seconds of arrivals. Latency is per request, from submission to completion
+    as the server records it."""
+    from paper_2512_05460_amd.budgets import BUDGETS, budget_policy
+    from synth import graphs, queries
+
+    log("served: building Chung-Lu n=10^7")
+    g = graphs.workload_graph("cl10m")
+    dg = B.graph_load_csr(g.n, g.row_ptr, g.col, B.BD_LAYOUT_COMPACT)
+    pol = budget_policy("cl10m")
+    seed = graphs.PHILOX_SEED
+    base = graphs.GRAPH_SEED + 3 + graphs.QUERY_SEED_OFFSET + 0x10
+    Lq = 1000
+    mean_size = (2 ** 13 - 1) / 13.0
+    srv = B.Server(dg, pol)
+    warm = queries.served_requests(g.n, 2, base - 7, max_log2=4)
+    for i, (s, t, e) in enumerate(warm):
+        srv.wait(srv.submit(s, t, e, Lq, seed + 999 + i))
+    burst = queries.served_requests(g.n, 24, base)
+    nq_burst = sum(x[0].size for x in burst)
+    log(f"served: capacity burst of {len(burst)} requests, {nq_burst} queries")
+    t0 = time.perf_counter()
+    rids = [srv.submit(s, t, e, Lq, seed + i) for i, (s, t, e) in enumerate(burst)]
+    for rid in rids:
+        out, _ = srv.wait(rid)
+        assert np.all(out["status"] == 0)
+    dt = time.perf_counter() - t0
+    cap_qps = nq_burst / dt
+    out = {"workload": ("Chung-Lu n=10,000,000 mean degree 10 exponent 2.3 LCC; Poisson arrivals of request "
+                        "batches of 2^U uniform pairs, U uniform on 0..12; eps per query from {0.02, 0.05, 0.1}; "
+                        "L=1000"),
+           "graph": {"n": g.n, "nnz": g.nnz, "layout": "compact", "device_bytes": dg.info()["device_bytes"]},
+           "policy": {"kind": "scaled", "c_B": BUDGETS["cl10m"][0], "c_R": BUDGETS["cl10m"][1],
+                      "calibration": BUDGETS["cl10m"][2]},
+           "admission": "slots 65,536 queries; per-probe accumulator arena; no walk-step cap",
+           "capacity_queries_per_s": cap_qps, "capacity_burst": {"requests": len(burst), "queries": nq_burst,
+                                                                 "seconds": dt},
+           "loads": []}
+    for li, f in enumerate((0.5, 0.8, 0.95)):
+        rate = f * cap_qps / mean_size
+        count = max(8, int(round(rate * seconds_per_load)))
+        reqs = queries.served_requests(g.n, count, base + 1000 * (li + 1))
+        arr = queries.poisson_arrivals(count, rate, base + 1000 * (li + 1) + 1)
+        log(f"served: offered load {f:.0%} of capacity, {count} requests at {rate:.2f}/s")
+        start = time.perf_counter()
+        sub, rids = [], []
+        for i, (s, t, e) in enumerate(reqs):
+            d = start + arr[i] - time.perf_counter()
+            if d > 0:
+                time.sleep(d)
+            sub.append(time.perf_counter() - start)
+            rids.append(srv.submit(s, t, e, Lq, seed + 100000 * (li + 1) + i))
+        lat = []
+        for rid in rids:
+            o, l_ms = srv.wait(rid)
+            assert np.all(o["status"] == 0)
+            lat.append(l_ms)
+        lat = np.array(lat)
+        end = max(sub[i] + lat[i] / 1e3 for i in range(count))
+        nq = sum(x[0].size for x in reqs)
+        sizes = np.array([x[0].size for x in reqs])
+        out["loads"].append({"offered_fraction": f, "offered_requests_per_s": rate, "requests": count,
+                             "queries": int(nq), "queries_per_s": nq / end,
+                             "latency_ms": {"p50": float(np.percentile(lat, 50)),
+                                            "p99": float(np.percentile(lat, 99)), "max": float(lat.max())},
+                             "latency_ms_requests_le_64": float(np.percentile(lat[sizes <= 64], 50))
+                             if np.any(sizes <= 64) else None})
+    srv.destroy()
+    dg.free()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -214,6 +292,7 @@ def main():
     ap.add_argument("--no-roofline", action="store_true")
     ap.add_argument("--no-small", action="store_true")
     ap.add_argument("--no-grid", action="store_true")
+    ap.add_argument("--no-served-cl10m", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calib", type=int, default=0,
                     help="also run a device copy of this many MiB (counter calibration)")
@@ -311,6 +390,8 @@ def main():
         extra["small_queries"] = small_queries(B, torch, stream)
     if not args.no_grid:
         extra["grid_batched"] = grid_batched(B, torch, stream)
+    if not args.no_served_cl10m:
+        extra["served_cl10m"] = served_cl10m(B, torch)
     roof = None
     if not args.no_roofline:
         log("gather roofline")

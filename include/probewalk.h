@@ -140,6 +140,13 @@ typedef struct {
                                 chunks stay in one queue and a work group takes chunks from the
                                 queue of the XCD it runs on before the others, so they share
                                 that XCD's L2. 0 = 8. Results do not depend on it. */
+    int32_t  uniform_min_r;  /* BATCHED: queries with at least this many replicas run on the
+                                wave-uniform kernel (one probe per wave, probe keys in scalar
+                                registers), the others on the general kernel (lanes over
+                                (probe, replica) pairs). 0 = automatic: 48, and the general
+                                kernel for all when the wave-uniform chunks could not fill
+                                the device; < 0 = general kernel only. Results do not
+                                depend on it. */
 } bd_exec;
 
 typedef struct {

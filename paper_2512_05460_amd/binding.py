@@ -67,7 +67,8 @@ class BdPolicy(ctypes.Structure):
 class BdExec(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_uint32), ("chunk_probes", ctypes.c_int32),
                 ("grid_wgs", ctypes.c_int32), ("use_graph", ctypes.c_int32),
-                ("chunk_pairs", ctypes.c_int32), ("queues", ctypes.c_int32)]
+                ("chunk_pairs", ctypes.c_int32), ("queues", ctypes.c_int32),
+                ("uniform_min_r", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -196,9 +197,10 @@ def policy(kind="paper", c_B=448.0, c_R=128.0, delta=0.01, B=0, R=0, max_steps=0
     return BdPolicy(k, c_B, c_R, delta, B, R, max_steps)
 
 
-def exec_cfg(mode="batched", chunk_probes=0, grid_wgs=0, use_graph=False, chunk_pairs=0, queues=0) -> BdExec:
+def exec_cfg(mode="batched", chunk_probes=0, grid_wgs=0, use_graph=False, chunk_pairs=0, queues=0,
+             uniform_min_r=0) -> BdExec:
     m = {"plain": BD_MODE_PLAIN, "batched": BD_MODE_BATCHED}[mode]
-    return BdExec(m, chunk_probes, grid_wgs, 1 if use_graph else 0, chunk_pairs, queues)
+    return BdExec(m, chunk_probes, grid_wgs, 1 if use_graph else 0, chunk_pairs, queues, uniform_min_r)
 
 
 class Graph:

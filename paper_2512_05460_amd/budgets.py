@@ -25,7 +25,10 @@ BUDGETS = {
     # L in {500, 2000, 5000}: no exact reference was computed at this size, so
     # these are throughput settings (B = 16/3/1, R = 2..49), not calibrated.
     "grid1414": (0.0064, 128.0 / 2 ** 28, "throughput setting, not calibrated"),
-    "cl10m": (448.0 / 1024, 128.0 / 2 ** 18, "provisional"),
+    # Chung-Lu n=1e7 (served requests of 1-4,096 pairs), eps in {.02,.05,.1},
+    # L=1000: B = 100/16/4 and R median 3 (up to ~1,800 for hub pairs), a
+    # throughput setting for the serving measurement, not calibrated.
+    "cl10m": (0.04, 128.0 / 2 ** 28, "throughput setting, not calibrated"),
     "cl40m": (448.0 / 1024, 128.0 / 2 ** 18, "provisional"),
 }
 

@@ -749,7 +749,21 @@ void build_batch(const bd_graph* g, int64_t nq, const int32_t* s, const int32_t*
     // chunk table: grouped by query; batched launches order queries by
     // descending cost so the longest work starts first
     auto cost = [&](size_t q) { return (double)b.qd[q].K * b.qd[q].R * (double)b.qd[q].L; };
-    auto uniform = [&](size_t q) { return ex.mode != BD_MODE_PLAIN && b.qd[q].R >= kUniformMinR; };
+    int64_t umin = ex.uniform_min_r == 0 ? (int64_t)kUniformMinR
+                   : ex.uniform_min_r < 0 ? INT64_MAX : (int64_t)ex.uniform_min_r;
+    if (ex.mode != BD_MODE_PLAIN && ex.uniform_min_r == 0) {
+        // automatic: the wave-uniform kernel gets a launch of its own only when
+        // its chunks can fill the device; otherwise the general kernel runs every
+        // chunk
+        uint64_t nu = 0;
+        for (const QueryDesc& d : b.qd) {
+            if ((int64_t)d.R < umin) continue;
+            const ChunkPlan cp = chunk_plan(ex, d.K, d.R);
+            nu += cp.part ? (uint64_t)d.K * ((d.R + cp.part - 1) / cp.part) : (d.K + cp.kc - 1) / cp.kc;
+        }
+        if (nu < (uint64_t)resident_wgs(g, 1)) umin = INT64_MAX;
+    }
+    auto uniform = [&](size_t q) { return ex.mode != BD_MODE_PLAIN && (int64_t)b.qd[q].R >= umin; };
     std::vector<size_t> order(b.qd.size());
     for (size_t i = 0; i < order.size(); ++i) order[i] = i;
     if (ex.mode != BD_MODE_PLAIN) {
@@ -797,7 +811,6 @@ void build_batch(const bd_graph* g, int64_t nq, const int32_t* s, const int32_t*
         b.qoff[part][b.nqueues] = (uint32_t)b.chunks.size() - base;
         if (part == 0) b.n_uniform = (uint32_t)b.chunks.size();
     }
-    (void)g;
 }
 
 }  // namespace
@@ -1250,13 +1263,16 @@ extern "C" int bd_device_info(char* buf, size_t len)
 //
 // A scheduler thread keeps a table of resident queries ("slots") on the
 // device. Each scheduling slice is one persistent walk launch over chunks
-// taken round-robin from every admitted query that still has probes left, so
-// a request that arrives while others run joins the very next slice and its
-// work shares the device with theirs. Two slices are kept in flight. The work
-// group that finishes a query posts (slot, beta) to a completion ring and
-// clears the slot's tables; the host frees the slot when it reads the ring.
-// Admission is FIFO under two caps: resident queries (device memory) and
-// outstanding walk steps.
+// taken round-robin over the admitted requests (and within a request over its
+// queries), so a request that arrives while others run joins the very next
+// slice, its work shares the device with theirs, and a small request is not
+// held back by the size of a large one. Two slices are in flight on two
+// streams, so the next slice's work groups take over compute units as the
+// current slice's finish. The work group that finishes a query posts (slot,
+// beta) to its slice's completion ring and clears the slot's tables; the host
+// frees the slot when it reads the ring. Admission is FIFO under caps on
+// resident queries and accumulator memory and, optionally, outstanding walk
+// steps.
 // ---------------------------------------------------------------------------
 namespace {
 
@@ -1293,6 +1309,8 @@ struct Request {
     uint64_t split_probes = 0;    // accumulators its split queries need
     double t_submit = 0, t_done = 0;
     bool done = false;
+    std::deque<uint32_t> rr_slots;  // admitted queries with chunks left to hand out
+    bool in_rr = false;             // the request is in the server's round-robin
 };
 
 struct SlotState {
@@ -1352,7 +1370,10 @@ struct RangeAlloc {
 struct Slice {
     PinnedBuf chunks_h;
     DevBuf chunks_d;
-    PinnedBuf comp_h;  // [u32 count, pad to 16 B][Completion x cap]
+    DevBuf d_cursor;   // chunk cursors of the slice's launches
+    DevBuf d_comp;     // completion ring: [u32 count, pad to 16 B][Completion x cap]
+    PinnedBuf comp_h;  // host copy of d_comp after the slice
+    hipStream_t st = nullptr;
     hipEvent_t ev = nullptr;
     uint32_t n = 0;
     uint32_t n_uniform = 0;  // chunks [0, n_uniform) have R >= kUniformMinR
@@ -1369,10 +1390,12 @@ struct bd_server {
     bd_graph* g = nullptr;
     bd_server_cfg cfg{};
     bd_policy pol{};
-    hipStream_t st = nullptr;
+    hipStream_t st = nullptr;    // descriptor copies at admission
+    hipEvent_t ev_admit = nullptr;
+    bool admit_recorded = false;
     uint32_t slots = 0, gdim = 0;
     int resident[2] = {0, 0};  // resident work groups: [0] small-R kernel, [1] wave-uniform kernel
-    DevBuf d_qd, d_bs, d_done, d_beta, d_cursor, d_comp, d_psum, d_pcount;
+    DevBuf d_qd, d_bs, d_done, d_beta, d_psum, d_pcount;
     PinnedBuf h_qd;
     uint32_t arena = 0;  // per-probe accumulators for split probes
     RangeAlloc psum_alloc;
@@ -1387,10 +1410,10 @@ struct bd_server {
     uint64_t next_id = 1;
     std::vector<uint32_t> free_slots;
     std::vector<SlotState> slot;
-    std::deque<uint32_t> rr;
+    std::deque<uint64_t> rr;  // requests with chunks left, round-robin
     uint64_t inflight_steps = 0;
-    uint32_t comp_seen = 0;
     double steps_per_ms = 5e7;
+    double t_last_done = 0;
 };
 
 namespace {
@@ -1434,6 +1457,10 @@ int admit(bd_server* S)
         }
         if (!fits) break;
         S->pending.pop_front();
+        if (need > 0 && !r.in_rr) {
+            S->rr.push_back(id);
+            r.in_rr = true;
+        }
         for (size_t i = 0; i < need; ++i) {
             const uint32_t sl = S->free_slots.back();
             S->free_slots.pop_back();
@@ -1458,7 +1485,12 @@ int admit(bd_server* S)
             ss.psum_base = base[i];
             ss.psum_n = ss.cur.plan.part ? d.K : 0;
             S->inflight_steps += ss.steps;
-            S->rr.push_back(sl);
+            r.rr_slots.push_back(sl);
+        }
+        if (need > 0) {
+            // slices launched from now on wait for these descriptor copies
+            if (hipEventRecord(S->ev_admit, S->st) != hipSuccess) return BD_E_HIP;
+            S->admit_recorded = true;
         }
     }
     return BD_OK;
@@ -1467,10 +1499,10 @@ int admit(bd_server* S)
 // Read the completion ring snapshot of a finished slice. Caller holds mu.
 void process_completions(bd_server* S, const Slice& sl)
 {
-    const uint32_t count = *sl.comp_h.as<const uint32_t>();
+    const uint32_t count = std::min(*sl.comp_h.as<const uint32_t>(), S->slots);
     const Completion* ring = reinterpret_cast<const Completion*>(sl.comp_h.as<const char>() + 16);
-    for (uint32_t i = S->comp_seen; i != count; ++i) {
-        const Completion c = ring[i % S->slots];
+    for (uint32_t i = 0; i < count; ++i) {
+        const Completion c = ring[i];
         SlotState& ss = S->slot[c.slot];
         auto it = S->reqs.find(ss.req);
         if (it != S->reqs.end()) {
@@ -1483,7 +1515,6 @@ void process_completions(bd_server* S, const Slice& sl)
         ss.psum_n = 0;
         S->free_slots.push_back(c.slot);
     }
-    S->comp_seen = count;
 }
 
 // Take chunks round-robin for one slice. Caller holds mu.
@@ -1497,26 +1528,37 @@ void fill_slice(bd_server* S, Slice& sl)
     std::vector<Chunk> small;  // chunks of queries with R < kUniformMinR go after the others
     while (!S->rr.empty() && sl.n + small.size() < kSliceMaxChunks &&
            ((double)sl.steps < target || sl.n + small.size() < (size_t)S->resident[1])) {
-        const uint32_t q = S->rr.front();
+        const uint64_t id = S->rr.front();
         S->rr.pop_front();
+        Request& r = S->reqs[id];
+        const uint32_t q = r.rr_slots.front();
+        r.rr_slots.pop_front();
         SlotState& ss = S->slot[q];
         sl.steps += ss.cur.chunk_steps(ss.L);
         const Chunk c = ss.cur.next();
         if (ss.uniform) out[sl.n++] = c;
         else small.push_back(c);
-        if (!ss.cur.done()) S->rr.push_back(q);
+        if (!ss.cur.done()) r.rr_slots.push_back(q);
+        if (!r.rr_slots.empty()) S->rr.push_back(id);
+        else r.in_rr = false;
     }
-    sl.n_uniform = sl.n;
+    // The wave-uniform chunks get a launch of their own only when they can fill
+    // the device; otherwise the general kernel (which runs any chunk) takes them
+    // at the head of its table, so the slice is one launch and no part of it
+    // waits for a nearly empty one.
+    sl.n_uniform = sl.n >= (uint32_t)S->resident[1] ? sl.n : 0u;
     for (const Chunk& c : small) out[sl.n++] = c;
 }
 
 int launch_slice(bd_server* S, Slice& sl)
 {
-    hipStream_t st = S->st;
+    hipStream_t st = sl.st;
+    if (S->admit_recorded && hipStreamWaitEvent(st, S->ev_admit, 0) != hipSuccess) return BD_E_HIP;
     if (hipMemcpyAsync(sl.chunks_d.p, sl.chunks_h.p, (size_t)sl.n * sizeof(Chunk), hipMemcpyHostToDevice, st) !=
         hipSuccess)
         return BD_E_HIP;
-    if (launch_zero(S->d_cursor.p, 16, st) != hipSuccess) return BD_E_HIP;
+    if (launch_zero(sl.d_cursor.p, 16, st) != hipSuccess) return BD_E_HIP;
+    if (launch_zero(sl.d_comp.p, 16, st) != hipSuccess) return BD_E_HIP;
     // the slice's chunk table holds the wave-uniform chunks first
     WalkArgs a{};
     a.g = tables(S->g);
@@ -1524,14 +1566,14 @@ int launch_slice(bd_server* S, Slice& sl)
     a.chunks = sl.chunks_d.as<const Chunk>();
     a.nchunks = sl.n;
     a.gdim = S->gdim;
-    a.cursor = S->d_cursor.as<uint32_t>();
+    a.cursor = sl.d_cursor.as<uint32_t>();
     a.blocksum = S->d_bs.as<unsigned long long>();
     a.done = S->d_done.as<uint32_t>();
     a.psum = S->d_psum.as<unsigned long long>();
     a.pcount = S->d_pcount.as<uint32_t>();
     a.beta = S->d_beta.as<double>();
-    a.comp_count = S->d_comp.as<uint32_t>();
-    a.comp_ring = reinterpret_cast<Completion*>(S->d_comp.as<char>() + 16);
+    a.comp_count = sl.d_comp.as<uint32_t>();
+    a.comp_ring = reinterpret_cast<Completion*>(sl.d_comp.as<char>() + 16);
     a.comp_cap = S->slots;
     a.recycle = 1;
     a.persistent = 1;
@@ -1540,7 +1582,7 @@ int launch_slice(bd_server* S, Slice& sl)
         WalkArgs ap = a;
         ap.chunks = sl.chunks_d.as<const Chunk>() + parts[part];
         ap.nchunks = parts[part + 1] - parts[part];
-        ap.cursor = S->d_cursor.as<uint32_t>() + part;
+        ap.cursor = sl.d_cursor.as<uint32_t>() + part;
         ap.nqueues = 1;
         ap.qoff[0] = 0;
         ap.qoff[1] = ap.nchunks;
@@ -1548,7 +1590,7 @@ int launch_slice(bd_server* S, Slice& sl)
         if (grid && launch_walk(ap, S->g->layout, part == 0, grid, st) != hipSuccess)
             return BD_E_HIP;
     }
-    if (hipMemcpyAsync(sl.comp_h.p, S->d_comp.p, comp_bytes(S), hipMemcpyDeviceToHost, st) != hipSuccess)
+    if (hipMemcpyAsync(sl.comp_h.p, sl.d_comp.p, comp_bytes(S), hipMemcpyDeviceToHost, st) != hipSuccess)
         return BD_E_HIP;
     if (hipEventRecord(sl.ev, st) != hipSuccess) return BD_E_HIP;
     sl.inflight = true;
@@ -1590,7 +1632,10 @@ void server_loop(bd_server* S)
             if (e != hipSuccess) {
                 rc = BD_E_HIP;
             } else {
-                const double dt = now_ms() - sl.t_launch;
+                // device rate from the time between slice completions (slices overlap)
+                const double tn = now_ms();
+                const double dt = tn - std::max(sl.t_launch, S->t_last_done);
+                S->t_last_done = tn;
                 if (dt > 0.5 && sl.steps > 0) S->steps_per_ms = 0.7 * S->steps_per_ms + 0.3 * (sl.steps / dt);
                 process_completions(S, sl);
             }
@@ -1608,6 +1653,8 @@ void server_loop(bd_server* S)
             fail_all(S, rc);
             // drain whatever is still on the device before leaving
             lk.unlock();
+            (void)hipStreamSynchronize(S->slice[0].st);
+            (void)hipStreamSynchronize(S->slice[1].st);
             (void)hipStreamSynchronize(S->st);
             lk.lock();
             S->slice[0].inflight = S->slice[1].inflight = false;
@@ -1643,8 +1690,6 @@ extern "C" int bd_server_create(bd_graph* g, const bd_server_cfg* cfg, bd_server
     if (rc == BD_OK) rc = S->d_bs.alloc((size_t)S->slots * S->gdim * 16);
     if (rc == BD_OK) rc = S->d_done.alloc((size_t)S->slots * 4);
     if (rc == BD_OK) rc = S->d_beta.alloc((size_t)S->slots * 8);
-    if (rc == BD_OK) rc = S->d_cursor.alloc(16);
-    if (rc == BD_OK) rc = S->d_comp.alloc(comp_bytes(S));
     S->arena = 1u << 22;
     if (rc == BD_OK) rc = S->d_psum.alloc((size_t)S->arena * 32);
     if (rc == BD_OK) rc = S->d_pcount.alloc((size_t)S->arena * 4);
@@ -1654,19 +1699,26 @@ extern "C" int bd_server_create(bd_graph* g, const bd_server_cfg* cfg, bd_server
         rc = S->slice[i].chunks_h.alloc((size_t)kSliceMaxChunks * sizeof(Chunk));
         if (rc == BD_OK) rc = S->slice[i].chunks_d.alloc((size_t)kSliceMaxChunks * sizeof(Chunk));
         if (rc == BD_OK) rc = S->slice[i].comp_h.alloc(comp_bytes(S));
+        if (rc == BD_OK) rc = S->slice[i].d_comp.alloc(comp_bytes(S));
+        if (rc == BD_OK) rc = S->slice[i].d_cursor.alloc(16);
         if (rc == BD_OK && hipEventCreateWithFlags(&S->slice[i].ev, hipEventDisableTiming) != hipSuccess)
+            rc = BD_E_HIP;
+        if (rc == BD_OK && hipStreamCreateWithFlags(&S->slice[i].st, hipStreamNonBlocking) != hipSuccess)
             rc = BD_E_HIP;
     }
     if (rc == BD_OK && hipStreamCreateWithFlags(&S->st, hipStreamNonBlocking) != hipSuccess) rc = BD_E_HIP;
+    if (rc == BD_OK && hipEventCreateWithFlags(&S->ev_admit, hipEventDisableTiming) != hipSuccess) rc = BD_E_HIP;
     if (rc == BD_OK && launch_zero(S->d_bs.p, (size_t)S->slots * S->gdim * 16, S->st) != hipSuccess) rc = BD_E_HIP;
     if (rc == BD_OK && launch_zero(S->d_done.p, (size_t)S->slots * 4, S->st) != hipSuccess) rc = BD_E_HIP;
-    if (rc == BD_OK && launch_zero(S->d_comp.p, comp_bytes(S), S->st) != hipSuccess) rc = BD_E_HIP;
     if (rc == BD_OK && launch_zero(S->d_psum.p, (size_t)S->arena * 32, S->st) != hipSuccess) rc = BD_E_HIP;
     if (rc == BD_OK && launch_zero(S->d_pcount.p, (size_t)S->arena * 4, S->st) != hipSuccess) rc = BD_E_HIP;
     if (rc == BD_OK && hipStreamSynchronize(S->st) != hipSuccess) rc = BD_E_HIP;
     if (rc != BD_OK) {
-        for (int i = 0; i < 2; ++i)
+        for (int i = 0; i < 2; ++i) {
             if (S->slice[i].ev) (void)hipEventDestroy(S->slice[i].ev);
+            if (S->slice[i].st) (void)hipStreamDestroy(S->slice[i].st);
+        }
+        if (S->ev_admit) (void)hipEventDestroy(S->ev_admit);
         if (S->st) (void)hipStreamDestroy(S->st);
         delete S;
         return rc;
@@ -1773,9 +1825,13 @@ extern "C" void bd_server_destroy(bd_server* S)
     }
     S->cv_work.notify_all();
     if (S->th.joinable()) S->th.join();
+    for (int i = 0; i < 2; ++i) (void)hipStreamSynchronize(S->slice[i].st);
     (void)hipStreamSynchronize(S->st);
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < 2; ++i) {
         if (S->slice[i].ev) (void)hipEventDestroy(S->slice[i].ev);
+        (void)hipStreamDestroy(S->slice[i].st);
+    }
+    (void)hipEventDestroy(S->ev_admit);
     (void)hipStreamDestroy(S->st);
     delete S;
 }

@@ -170,14 +170,14 @@ __device__ void run_chunk(const WalkArgs& A, const DevGraph& G, uint32_t ci,
             }
         }
     } else {
-        // Few replicas per probe: lanes stride over (probe, replica) pairs so
-        // that one wave covers several probes.
-        const uint64_t total = (uint64_t)c.kc * d.R;
+        // Any replica count: lanes stride over the chunk's (probe, replica)
+        // pairs, so one wave can cover several probes.
+        const uint64_t total = (uint64_t)c.kc * c.pc;
         for (uint64_t base = 0; base < total; base += kBlockThreads) {
             const uint64_t w = base + (uint64_t)tid;
             if (w < total) {
-                const uint32_t kk = (uint32_t)(w / d.R);
-                const uint32_t p = (uint32_t)(w - (uint64_t)kk * d.R);
+                const uint32_t kk = (uint32_t)(w / c.pc);
+                const uint32_t p = c.p0 + (uint32_t)(w - (uint64_t)kk * c.pc);
                 const uint32_t k = c.k0 + kk;
                 const Probe pr = make_probe(d.seed_lo, d.seed_hi, d.uid, k, G.dom.n);
                 const float U = walk_pair<kLayout>(G, pr, s0, t0, d.L, p, k, d.uid, d.seed_lo, d.seed_hi);
@@ -188,7 +188,7 @@ __device__ void run_chunk(const WalkArgs& A, const DevGraph& G, uint32_t ci,
     }
     __syncthreads();
 
-    if (kUniform && c.pc < d.R) {
+    if (c.pc < d.R) {
         // Part of a split probe: add the partial sums to the probe's accumulator;
         // the chunk that brings its replica count to R forms Q_R.
         if (tid == 0) {

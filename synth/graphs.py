@@ -78,14 +78,17 @@ def largest_component(g: Csr, name: str | None = None) -> Csr:
     sizes = np.bincount(labels)
     big = int(np.argmax(sizes))
     keep = labels == big
-    new_id = np.full(g.n, -1, dtype=np.int64)
-    new_id[keep] = np.arange(int(keep.sum()), dtype=np.int64)
-    rows = np.repeat(np.arange(g.n, dtype=np.int64), g.deg)
-    mask = keep[rows]
-    u = new_id[rows[mask]]
-    v = new_id[g.col[mask].astype(np.int64)]
     m = int(keep.sum())
-    return csr_from_edges(m, u, v, name=name if name is not None else g.name)
+    new_id = np.full(g.n, -1, dtype=np.int64)
+    new_id[keep] = np.arange(m, dtype=np.int64)
+    # A component is closed under adjacency, so a kept node keeps its whole
+    # neighbour list; the renaming is increasing, so rows stay in order and
+    # neighbour lists stay sorted: the result is already canonical.
+    deg = g.deg
+    row_ptr = np.zeros(m + 1, dtype=np.int64)
+    np.cumsum(deg[keep], out=row_ptr[1:])
+    col = new_id[g.col[np.repeat(keep, deg)]].astype(np.int32)
+    return Csr(n=m, row_ptr=row_ptr, col=col, name=name if name is not None else g.name)
 
 
 def relabel(g: Csr, perm: np.ndarray, name: str | None = None) -> Csr:
@@ -161,6 +164,25 @@ def barabasi_albert(n: int, m: int, seed: int) -> Csr:
     return csr_from_edges(n, np.array(us), np.array(vs), name=f"BA(n={n},m={m})")
 
 
+def _inverse_cdf(cdf: np.ndarray, r: np.ndarray, first: np.ndarray, buckets: int) -> np.ndarray:
+    """np.searchsorted(cdf, r, side="right") for nondecreasing ``cdf``, by a
+    bucket table: ``first[j]`` counts the entries <= j / buckets, so the answer
+    for r is at least ``first[j]`` with j / buckets <= r, and is reached by
+    stepping forward while cdf[idx] <= r (a few steps per draw)."""
+    j = np.floor(r * buckets).astype(np.int64) - 1
+    np.clip(j, 0, buckets - 1, out=j)
+    idx = first[j]
+    active = np.arange(r.size)
+    n = cdf.size
+    while active.size:
+        ia = idx[active]
+        step = ia < n
+        step[step] = cdf[ia[step]] <= r[active[step]]
+        active = active[step]
+        idx[active] += 1
+    return idx
+
+
 def chung_lu(n: int, mean_deg: float, gamma: float, seed: int,
              lcc: bool = True, chunk: int = 1 << 24) -> Csr:
     """Chung-Lu power-law graph by weighted endpoint sampling.
@@ -179,12 +201,14 @@ def chung_lu(n: int, mean_deg: float, gamma: float, seed: int,
     cdf = np.cumsum(w)
     cdf /= cdf[-1]
     m = int(round(n * mean_deg / 2.0))
+    buckets = 4 * n
+    first = np.searchsorted(cdf, np.arange(buckets, dtype=np.float64) / buckets, side="right")
     keys = []
     left = m
     while left > 0:
         c = min(chunk, left)
-        a = np.searchsorted(cdf, rng.random(c), side="right")
-        b = np.searchsorted(cdf, rng.random(c), side="right")
+        a = _inverse_cdf(cdf, rng.random(c), first, buckets)
+        b = _inverse_cdf(cdf, rng.random(c), first, buckets)
         np.minimum(a, n - 1, out=a)
         np.minimum(b, n - 1, out=b)
         lo = np.minimum(a, b)

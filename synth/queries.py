@@ -43,3 +43,24 @@ def workload_batch(key: str, n: int, count: int | None = None):
     eps, L = mixed_eps_L(total, eps_choices, L_choices, seed + 1)
     m = total if count is None else count
     return s[:m], t[:m], eps[:m], L[:m]
+
+
+def served_requests(n: int, count: int, seed: int, max_log2: int = 12,
+                    eps_choices=(0.02, 0.05, 0.1)):
+    """``count`` request batches: sizes 2^U with U uniform on {0..max_log2}
+    (1 to 4,096 pairs), uniform pairs, eps drawn per query. Returns a list of
+    (s, t, eps) arrays."""
+    rng = np.random.default_rng(seed)
+    sizes = 2 ** rng.integers(0, max_log2 + 1, size=count)
+    out = []
+    for i, m in enumerate(sizes):
+        s, t = uniform_pairs(n, int(m), seed + 1 + i)
+        eps = np.asarray(eps_choices, dtype=np.float64)[rng.integers(0, len(eps_choices), size=int(m))]
+        out.append((s, t, eps))
+    return out
+
+
+def poisson_arrivals(count: int, rate: float, seed: int) -> np.ndarray:
+    """Arrival times (seconds from 0) of a Poisson process of the given rate."""
+    rng = np.random.default_rng(seed)
+    return np.cumsum(rng.exponential(1.0 / rate, size=count))

@@ -91,7 +91,7 @@ def test_result_layout_matches_header(tmp_path):
                      ctypes.sizeof(binding.BdExec), ctypes.sizeof(binding.BdStats),
                      ctypes.sizeof(binding.BdServerCfg), ctypes.sizeof(binding.BdGraphInfo),
                      ctypes.sizeof(binding.BdRoofline)]
-    assert ctypes.sizeof(binding.BdExec) == 24
+    assert ctypes.sizeof(binding.BdExec) == 28
 
 
 def test_binding_has_no_fallback(monkeypatch, tmp_path):

@@ -43,9 +43,12 @@ def test_split_probe_parity(flags):
     pol = B.policy("fixed", B=1, R=5000)
     plan = OP.plan(0.1, L, 1, 1, 1, OP.Policy("fixed", B_fixed=1, R_fixed=5000))
     ob, oq, oy = E.estimate(g, [s], [t], L, [plan], SEED, uid=[3], want_q=True, threads=1)
-    for mode in ("batched", "plain"):
-        res, q, y = B.bd_query_probes(dg, s, t, 0.1, L, 3, SEED, pol, B.exec_cfg(mode))
-        assert np.array_equal(q, oq), mode
+    # batched: automatic kernel choice, forced wave-uniform kernel, general only
+    for ex in (B.exec_cfg("batched"), B.exec_cfg("batched", uniform_min_r=48),
+               B.exec_cfg("batched", uniform_min_r=-1), B.exec_cfg("batched", uniform_min_r=-1, chunk_pairs=700),
+               B.exec_cfg("plain")):
+        res, q, y = B.bd_query_probes(dg, s, t, 0.1, L, 3, SEED, pol, ex)
+        assert np.array_equal(q, oq), ex.as_dict()
         assert np.array_equal(y, oy) and res["beta"] == ob[0]
 
 
@@ -71,6 +74,10 @@ def test_batched_equals_plain_with_splits():
     b = B.bd_query_batch(dg, s, t, eps, L, SEED, pol, B.exec_cfg("batched"))
     c = B.bd_query_batch(dg, s, t, eps, L, SEED, pol, B.exec_cfg("batched", grid_wgs=7))
     assert np.array_equal(a["beta"], b["beta"]) and np.array_equal(a["beta"], c["beta"])
+    for ex in (B.exec_cfg("batched", uniform_min_r=48), B.exec_cfg("batched", uniform_min_r=1, queues=3),
+               B.exec_cfg("batched", uniform_min_r=-1, chunk_pairs=1000)):
+        d = B.bd_query_batch(dg, s, t, eps, L, SEED, pol, ex)
+        assert np.array_equal(a["beta"], d["beta"]), ex.as_dict()
 
 
 def test_served_alone_equals_mix():

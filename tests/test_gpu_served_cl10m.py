@@ -1,0 +1,100 @@
+"""Served mode at full size: Chung-Lu n=10^7 (mean degree 10, exponent 2.3,
+largest component) resident on the device in the compact layout.
+
+Requests of mixed size (1 to 4,096 pairs, eps per query from {0.02, 0.05,
+0.1}, L=1000) are submitted while others run. Sampled queries are checked bit
+for bit against the oracle, and against the same queries submitted alone and
+run through bd_query_batch (results do not depend on what else shares the
+device). Walk counts: the throughput setting of
+paper_2512_05460_amd/budgets.py.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import estimator as E
+from oracle import planner as OP
+from paper_2512_05460_amd import binding as B
+from paper_2512_05460_amd.budgets import BUDGETS, budget_policy
+from synth import graphs, queries
+
+pytestmark = pytest.mark.gpu
+
+SEED = graphs.PHILOX_SEED
+L = 1000
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def cl10m():
+    _say("[cl10m] building the graph")
+    g = graphs.workload_graph("cl10m")
+    _say(f"[cl10m] n={g.n} nnz={g.nnz}; loading")
+    dg = B.graph_load_csr(g.n, g.row_ptr, g.col, B.BD_LAYOUT_COMPACT)
+    yield g, dg
+    dg.free()
+
+
+def test_cl10m_resident(cl10m):
+    g, dg = cl10m
+    info = dg.info()
+    assert info["n"] == g.n and info["nnz"] == g.nnz and info["d_min"] == 1
+    assert info["layout"] == 2 and info["bipartite"] == 0
+    # compact: 4 bytes per row offset, 3 per adjacency entry (+ padding)
+    assert 4 * g.n + 3 * g.nnz <= info["device_bytes"] <= 4 * g.n + 3 * g.nnz + (1 << 20)
+    _say(f"[cl10m] device bytes {info['device_bytes']:,}")
+
+
+@pytest.mark.timeout(900)
+def test_served_mix_equals_oracle_and_alone(cl10m):
+    g, dg = cl10m
+    pol = budget_policy("cl10m")
+    c_B, c_R, _ = BUDGETS["cl10m"]
+    op = OP.Policy("scaled", c_B=c_B, c_R=c_R)
+    reqs = queries.served_requests(g.n, 10, graphs.GRAPH_SEED + 3 + graphs.QUERY_SEED_OFFSET + 0x77)
+    seeds = [SEED + 31 * i for i in range(len(reqs))]
+    srv = B.Server(dg, pol)
+    # half submitted at once, the rest while those run
+    rids = [srv.submit(s, t, e, L, seeds[i]) for i, (s, t, e) in enumerate(reqs[:5])]
+    rids += [srv.submit(s, t, e, L, seeds[5 + i]) for i, (s, t, e) in enumerate(reqs[5:])]
+    outs = []
+    for rid in rids:
+        o, lat = srv.wait(rid)
+        assert np.all(o["status"] == 0)
+        outs.append(o)
+    _say(f"[cl10m] request sizes {[r[0].size for r in reqs]}")
+    # sampled queries: up to 3 per request with oracle-sized walk counts
+    d = g.deg
+    picks = []
+    for ri, (s, t, e) in enumerate(reqs):
+        for qi in range(min(s.size, 3)):
+            B_, G_, K_, R_ = OP.plan(float(e[qi]), L, int(d[s[qi]]), int(d[t[qi]]), g.d_min, op)
+            assert (outs[ri]["K"][qi], outs[ri]["R"][qi]) == (K_, R_)
+            if 2 * K_ * R_ * L <= 3e8:
+                picks.append((ri, qi, (B_, G_, K_, R_)))
+    assert len(picks) >= 12
+    ps = np.array([reqs[ri][0][qi] for ri, qi, _ in picks])
+    pt = np.array([reqs[ri][1][qi] for ri, qi, _ in picks])
+    got = np.array([outs[ri]["beta"][qi] for ri, qi, _ in picks])
+    # the oracle takes one seed per call: group the picks by request
+    ref = np.zeros(len(picks))
+    for ri in sorted({p[0] for p in picks}):
+        sel = [j for j, p in enumerate(picks) if p[0] == ri]
+        ref[sel] = E.estimate(g, ps[sel], pt[sel], L, [picks[j][2] for j in sel], seeds[ri],
+                              uid=np.array([picks[j][1] for j in sel], dtype=np.uint32), threads=16)
+    assert np.array_equal(got, ref), got - ref
+    # alone: one-query requests with the same uid and seed, and the plain mode
+    for j, (ri, qi, _) in enumerate(picks[:6]):
+        s, t, e = reqs[ri]
+        rid = srv.submit(s[qi:qi + 1], t[qi:qi + 1], e[qi:qi + 1], L, seeds[ri], uid=[qi])
+        o, _ = srv.wait(rid)
+        assert o["beta"][0] == got[j]
+        p = B.bd_query_batch(dg, s[qi:qi + 1], t[qi:qi + 1], e[qi:qi + 1], L, seeds[ri], pol,
+                             B.exec_cfg("plain"), uid=[qi])
+        assert p["beta"][0] == got[j]
+    srv.destroy()

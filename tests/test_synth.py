@@ -68,3 +68,33 @@ def test_uniform_pairs():
     # uniform over ordered pairs: each node appears as t about 20000/50 times
     cnt = np.bincount(t, minlength=50)
     assert abs(cnt.mean() - 400) < 1e-9 and cnt.std() < 60
+
+
+def test_inverse_cdf_equals_searchsorted():
+    rng = np.random.default_rng(3)
+    for n, gamma in ((1, 2.5), (7, 2.1), (1000, 2.5), (200_000, 2.3)):
+        w = np.arange(1, n + 1, dtype=np.float64) ** (-1.0 / (gamma - 1.0))
+        cdf = np.cumsum(w)
+        cdf /= cdf[-1]
+        first = np.searchsorted(cdf, np.arange(4 * n, dtype=np.float64) / (4 * n), side="right")
+        r = rng.random(200_000)
+        r[:4] = [0.0, np.nextafter(1.0, 0.0), cdf[n // 2], np.nextafter(cdf[n // 2], 0.0)]
+        assert np.array_equal(graphs._inverse_cdf(cdf, r, first, 4 * n),
+                              np.searchsorted(cdf, r, side="right"))
+
+
+def test_largest_component_matches_rebuild():
+    # several components: the kept one rebuilt from its edge list is identical
+    g = graphs.chung_lu(3000, 1.5, 2.2, 11, lcc=False)
+    lc = graphs.largest_component(g)
+    import scipy.sparse.csgraph as csgraph
+    _, labels = csgraph.connected_components(g.scipy(), directed=False)
+    big = np.argmax(np.bincount(labels))
+    keep = labels == big
+    assert lc.n == keep.sum() < g.n
+    new_id = np.cumsum(keep) - 1
+    rows = np.repeat(np.arange(g.n), g.deg)
+    m = keep[rows]
+    ref = graphs.csr_from_edges(lc.n, new_id[rows[m]], new_id[g.col[m]])
+    assert np.array_equal(lc.row_ptr, ref.row_ptr) and np.array_equal(lc.col, ref.col)
+    assert lc.col.dtype == np.int32
