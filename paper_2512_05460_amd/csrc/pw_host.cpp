@@ -1423,6 +1423,15 @@ size_t comp_bytes(const bd_server* S)
     return 16 + (size_t)S->slots * sizeof(Completion);
 }
 
+// completions copied back after every slice; a slice that finishes more
+// queries than this has the rest fetched when it is read
+constexpr uint32_t kCompPrefix = 4096;
+
+size_t comp_prefix_bytes(const bd_server* S)
+{
+    return 16 + (size_t)std::min(S->slots, kCompPrefix) * sizeof(Completion);
+}
+
 void finish_request(bd_server* S, uint64_t id, Request& r)
 {
     (void)id;
@@ -1461,16 +1470,15 @@ int admit(bd_server* S)
             S->rr.push_back(id);
             r.in_rr = true;
         }
+        std::vector<uint32_t> taken(need);
         for (size_t i = 0; i < need; ++i) {
             const uint32_t sl = S->free_slots.back();
             S->free_slots.pop_back();
+            taken[i] = sl;
             QueryDesc d = r.desc[i];
             d.slot = sl;
             d.psum_base = base[i];
             S->h_qd.as<QueryDesc>()[sl] = d;
-            if (hipMemcpyAsync(S->d_qd.as<QueryDesc>() + sl, S->h_qd.as<QueryDesc>() + sl, sizeof(QueryDesc),
-                               hipMemcpyHostToDevice, S->st) != hipSuccess)
-                return BD_E_HIP;
             SlotState& ss = S->slot[sl];
             ss.req = id;
             ss.ridx = r.index[i];
@@ -1487,6 +1495,16 @@ int admit(bd_server* S)
             S->inflight_steps += ss.steps;
             r.rr_slots.push_back(sl);
         }
+        // descriptors to the device, one copy per run of consecutive slots
+        std::sort(taken.begin(), taken.end());
+        for (size_t i = 0; i < need;) {
+            size_t j = i + 1;
+            while (j < need && taken[j] == taken[j - 1] + 1) ++j;
+            if (hipMemcpyAsync(S->d_qd.as<QueryDesc>() + taken[i], S->h_qd.as<QueryDesc>() + taken[i],
+                               (j - i) * sizeof(QueryDesc), hipMemcpyHostToDevice, S->st) != hipSuccess)
+                return BD_E_HIP;
+            i = j;
+        }
         if (need > 0) {
             // slices launched from now on wait for these descriptor copies
             if (hipEventRecord(S->ev_admit, S->st) != hipSuccess) return BD_E_HIP;
@@ -1496,10 +1514,16 @@ int admit(bd_server* S)
     return BD_OK;
 }
 
-// Read the completion ring snapshot of a finished slice. Caller holds mu.
-void process_completions(bd_server* S, const Slice& sl)
+// Read the completion ring of a finished slice. Caller holds mu.
+int process_completions(bd_server* S, const Slice& sl)
 {
     const uint32_t count = std::min(*sl.comp_h.as<const uint32_t>(), S->slots);
+    if (count > kCompPrefix) {
+        const size_t off = 16 + (size_t)kCompPrefix * sizeof(Completion);
+        if (hipMemcpy(sl.comp_h.as<char>() + off, sl.d_comp.as<char>() + off,
+                      (size_t)(count - kCompPrefix) * sizeof(Completion), hipMemcpyDeviceToHost) != hipSuccess)
+            return BD_E_HIP;
+    }
     const Completion* ring = reinterpret_cast<const Completion*>(sl.comp_h.as<const char>() + 16);
     for (uint32_t i = 0; i < count; ++i) {
         const Completion c = ring[i];
@@ -1515,6 +1539,7 @@ void process_completions(bd_server* S, const Slice& sl)
         ss.psum_n = 0;
         S->free_slots.push_back(c.slot);
     }
+    return BD_OK;
 }
 
 // Take chunks round-robin for one slice. Caller holds mu.
@@ -1590,7 +1615,7 @@ int launch_slice(bd_server* S, Slice& sl)
         if (grid && launch_walk(ap, S->g->layout, part == 0, grid, st) != hipSuccess)
             return BD_E_HIP;
     }
-    if (hipMemcpyAsync(sl.comp_h.p, sl.d_comp.p, comp_bytes(S), hipMemcpyDeviceToHost, st) != hipSuccess)
+    if (hipMemcpyAsync(sl.comp_h.p, sl.d_comp.p, comp_prefix_bytes(S), hipMemcpyDeviceToHost, st) != hipSuccess)
         return BD_E_HIP;
     if (hipEventRecord(sl.ev, st) != hipSuccess) return BD_E_HIP;
     sl.inflight = true;
@@ -1637,7 +1662,7 @@ void server_loop(bd_server* S)
                 const double dt = tn - std::max(sl.t_launch, S->t_last_done);
                 S->t_last_done = tn;
                 if (dt > 0.5 && sl.steps > 0) S->steps_per_ms = 0.7 * S->steps_per_ms + 0.3 * (sl.steps / dt);
-                process_completions(S, sl);
+                rc = process_completions(S, sl);
             }
             sl.inflight = false;
         }

@@ -110,6 +110,28 @@ def test_served_alone_equals_mix():
         srv.destroy()
 
 
+def test_served_many_completions_per_slice():
+    # 20,000 one-step queries fit one slice: its completion ring holds more
+    # entries than the part copied back after every slice
+    g, dg = _graph("ba1k", B.BD_LAYOUT_COMPACT)
+    n = 20000
+    s, t = queries.uniform_pairs(g.n, n, 404)
+    pol = B.policy("fixed", B=1, R=2)
+    ref = B.bd_query_batch(dg, s, t, 0.5, 1, SEED, pol, B.exec_cfg("batched"))
+    srv = B.Server(dg, pol)
+    try:
+        out, _ = srv.wait(srv.submit(s, t, 0.5, 1, SEED))
+        assert np.all(out["status"] == 0)
+        assert np.array_equal(out["beta"], ref["beta"])
+        # and in several requests at once
+        rids = [srv.submit(s[i::3], t[i::3], 0.5, 1, SEED, uid=np.arange(n)[i::3]) for i in range(3)]
+        for i, rid in enumerate(rids):
+            o, _ = srv.wait(rid)
+            assert np.array_equal(o["beta"], ref["beta"][i::3])
+    finally:
+        srv.destroy()
+
+
 def test_served_admission_caps_and_split():
     g, dg = _graph("ba1k", B.BD_LAYOUT_COMPACT)
     pol = B.policy("fixed", B=1, R=4500)  # every probe split into two parts
