@@ -25,6 +25,16 @@ BUDGETS = {
     # L in {500, 2000, 5000}: no exact reference was computed at this size, so
     # these are throughput settings (B = 16/3/1, R = 2..49), not calibrated.
     "grid1414": (0.0064, 128.0 / 2 ** 28, "throughput setting, not calibrated"),
+    # The same grid at one L at a time, calibrated against the truncated
+    # distance beta^(L) of 32 pairs (tests/golden) at eps in {.02,.05,.1}:
+    # c_R = 16/(L+1)^2 gives R = 38..68 at every L (the (L+1)^2 of Algorithm 1
+    # overstates the grid's walk variance, which grows about like L log L while
+    # beta^(L) grows like L), and B = 256 at eps = 0.05. Within eps: 99.0%
+    # (L=500), 100% (L=2000), 96.9% (L=5000) of 96 queries; half the
+    # replicas failed at L=5000 (91.7%), half the probes at every L.
+    "grid1414@500": (0.64, 16.0 / 501 ** 2, "calibrated: 99.0% of 96 queries within eps (calibration seed)"),
+    "grid1414@2000": (0.64, 16.0 / 2001 ** 2, "calibrated: 100% of 96 queries within eps (calibration seed)"),
+    "grid1414@5000": (0.64, 16.0 / 5001 ** 2, "calibrated: 96.9% of 96 queries within eps (calibration seed)"),
     # Chung-Lu n=1e7 (served requests of 1-4,096 pairs), eps in {.02,.05,.1},
     # L=1000: B = 100/16/4 and R median 3 (up to ~1,800 for hub pairs), a
     # throughput setting for the serving measurement, not calibrated.

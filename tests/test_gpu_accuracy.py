@@ -4,6 +4,9 @@
     pseudoinverse (oracle); at least 95% of queries within eps.
   * Chung-Lu n=1e5, the 128 reference pairs of tests/golden (CG, two solves),
     eps=0.05, L=1000: at least 95% within eps.
+  * 1,414 x 1,414 grid (bipartite), the 32 pairs of tests/golden at eps in
+    {0.02, 0.05, 0.1} and L in {500, 2000, 5000}: at least 95% within eps of
+    the truncated distance beta^(L) (binary64 series, oracle).
   * Theorem 3.8 with the paper's own constants (448, 128) on tiny graphs: the
     proof's bound |beta-hat - beta^(L)| <= (eps/4) beta^(L) for every seed.
 Walk counts are the scaled policy (paper_2512_05460_amd/budgets.py), whose
@@ -25,6 +28,7 @@ pytestmark = pytest.mark.gpu
 
 SEED = graphs.PHILOX_SEED
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "cl100k_cg_reference.txt")
+GRID_GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "grid1414_truncated_reference.txt")
 
 
 def _say(*a):
@@ -65,6 +69,31 @@ def test_accuracy_cl100k():
     _say(f"[cl100k] within eps: {frac:.3f}, median rel err {np.median(err):.4f}, "
          f"{st['walk_steps']:.3e} steps in {st['walk_kernel_ms']:.0f} ms")
     assert frac >= 0.95
+
+
+@pytest.mark.timeout(600)
+def test_accuracy_grid_truncated():
+    # The bipartite grid: judged against beta^(L) (the series does not converge
+    # to beta), 32 golden pairs x eps in {.02, .05, .1} x L in {500, 2000, 5000}
+    g = graphs.workload_graph("grid1414")
+    ref = np.loadtxt(GRID_GOLDEN, comments="#")
+    s = ref[:, 1].astype(np.int32)
+    t = ref[:, 2].astype(np.int32)
+    assert np.array_equal(ref[:, 3], g.deg[s]) and np.array_equal(ref[:, 4], g.deg[t])
+    dg = B.graph_load_csr(g.n, g.row_ptr, g.col, B.BD_LAYOUT_COMPACT)
+    hits, total = 0, 0
+    for li, L in enumerate((500, 2000, 5000)):
+        beta = ref[:, 5 + li]
+        for eps in (0.02, 0.05, 0.1):
+            res = B.bd_query_batch(dg, s, t, eps, L, SEED, budget_policy(f"grid1414@{L}"), B.exec_cfg("batched"))
+            assert np.all(res["status"] == 0)
+            ok = np.abs(res["beta"] - beta) <= eps * beta
+            _say(f"[grid] L={L} eps={eps}: {ok.mean():.3f} within eps, R {res['R'].min()}..{res['R'].max()}")
+            hits += int(ok.sum())
+            total += ok.size
+    dg.free()
+    _say(f"[grid] within eps: {hits}/{total}")
+    assert hits >= 0.95 * total
 
 
 @pytest.mark.parametrize("maker,s,t", [(lambda: graphs.cycle_graph(5), 0, 2),
