@@ -33,7 +33,7 @@ def lib():
                                      ctypes.c_uint32, ctypes.c_uint32, _P, _P]
         L.pwo_walk_trace.restype = None
         L.pwo_estimate.argtypes = [ctypes.c_uint32, _P, _P, ctypes.c_int64, _P, _P, _P, _P,
-                                   _P, _P, _P, _P, _P, ctypes.c_uint64, ctypes.c_int,
+                                   _P, _P, _P, _P, _P, _P, ctypes.c_uint64, ctypes.c_int,
                                    _P, _P, _P]
         L.pwo_estimate.restype = ctypes.c_int
         L.pwo_replicas.argtypes = [ctypes.c_uint32, _P, _P, ctypes.c_int32, ctypes.c_int32,
@@ -43,8 +43,8 @@ def lib():
         L.pwo_q_from_u.argtypes = [ctypes.c_int64, _P]
         L.pwo_q_from_u.restype = ctypes.c_double
         L.pwo_probe_q.argtypes = [ctypes.c_uint32, _P, _P, ctypes.c_int32, ctypes.c_int32,
-                                  ctypes.c_int32, ctypes.c_uint32, ctypes.c_int64, ctypes.c_uint64,
-                                  ctypes.c_int64, _P, ctypes.c_int, _P]
+                                  ctypes.c_int32, ctypes.c_uint32, ctypes.c_int64, ctypes.c_int64,
+                                  ctypes.c_int64, ctypes.c_uint64, ctypes.c_int64, _P, ctypes.c_int, _P]
         L.pwo_probe_q.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -100,10 +100,11 @@ def q_from_u(U) -> float:
 
 
 def estimate(g, s, t, L, plans, seed: int, uid=None, threads: int = 1,
-             k_end=None, want_q: bool = False):
+             k_end=None, want_q: bool = False, share=1):
     """Run Algorithm 1 for each query.
 
-    ``plans`` is a sequence of (B, G, K, R) tuples, one per query.
+    ``plans`` is a sequence of (B, G, K, R) tuples, one per query. ``share``
+    (scalar or per query) is the walk-sharing group size M; 1 is Algorithm 1.
     Returns beta-hat per query, and (when ``want_q``) the per-probe Q and the
     G block means of query 0.
     """
@@ -116,6 +117,7 @@ def estimate(g, s, t, L, plans, seed: int, uid=None, threads: int = 1,
     G = np.array([p[1] for p in plans], dtype=np.int64)
     K = np.array([p[2] for p in plans], dtype=np.int64)
     R = np.array([p[3] for p in plans], dtype=np.int64)
+    M = np.ascontiguousarray(np.broadcast_to(np.asarray(share, dtype=np.int64), s.shape))
     uid_a = None if uid is None else np.ascontiguousarray(uid, dtype=np.uint32)
     kend = None if k_end is None else np.ascontiguousarray(k_end, dtype=np.int64)
     beta = np.zeros(nq, dtype=np.float64)
@@ -125,7 +127,7 @@ def estimate(g, s, t, L, plans, seed: int, uid=None, threads: int = 1,
     col = np.ascontiguousarray(g.col, dtype=np.int32)
     rc = lib().pwo_estimate(
         g.n, _ptr(rp), _ptr(col), nq, _ptr(s), _ptr(t), _ptr(L),
-        None if uid_a is None else _ptr(uid_a), _ptr(K), _ptr(R), _ptr(B), _ptr(G),
+        None if uid_a is None else _ptr(uid_a), _ptr(K), _ptr(R), _ptr(B), _ptr(G), _ptr(M),
         None if kend is None else _ptr(kend), seed, threads, _ptr(beta),
         None if q0 is None else _ptr(q0), None if y0 is None else _ptr(y0))
     if rc != 0:
@@ -135,12 +137,15 @@ def estimate(g, s, t, L, plans, seed: int, uid=None, threads: int = 1,
     return beta
 
 
-def probe_q(g, s: int, t: int, L: int, uid: int, R: int, seed: int, ks, threads: int = 1):
-    """Q_R(z^(k)) for each probe index in ``ks`` (threads over probes)."""
+def probe_q(g, s: int, t: int, L: int, uid: int, R: int, seed: int, ks, threads: int = 1,
+            B: int = 1, share: int = 1):
+    """Q_R(z^(k)) for each probe index in ``ks`` (threads over probes). With walk
+    sharing (group size ``share`` inside blocks of ``B`` probes) probe k is
+    scored on the walks of its group."""
     ks = np.ascontiguousarray(ks, dtype=np.uint32)
     out = np.zeros(ks.size, dtype=np.float64)
     rp = np.ascontiguousarray(g.row_ptr, dtype=np.int64)
     col = np.ascontiguousarray(g.col, dtype=np.int32)
-    lib().pwo_probe_q(g.n, _ptr(rp), _ptr(col), s, t, L, uid, R, seed, ks.size, _ptr(ks), threads,
-                      _ptr(out))
+    lib().pwo_probe_q(g.n, _ptr(rp), _ptr(col), s, t, L, uid, R, B, share, seed, ks.size, _ptr(ks),
+                      threads, _ptr(out))
     return out

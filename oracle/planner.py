@@ -16,6 +16,9 @@ Readings:
   * R is at least 2 (the U-statistic needs two replicas, Lemma 3.4).
   * Policies: "paper" uses 448 and 128; "scaled" keeps the formulas with
     smaller constants (c_B, c_R); "fixed" takes B and R as given.
+  * ``share`` (walk sharing, an extension): the probes of a block are scored
+    in groups of ``share`` on common walks; B, G, K and R are unchanged and
+    the walk count drops by about that factor.
 """
 
 from __future__ import annotations
@@ -38,6 +41,7 @@ class Policy:
     delta: float = 0.01
     B_fixed: int = 0
     R_fixed: int = 0
+    share: int = 1  # walk-sharing group size M (1 = Algorithm 1)
 
 
 PAPER = Policy()
@@ -56,6 +60,13 @@ def plan(eps: float, L: int, d_s: int, d_t: int, d_min: int, policy: Policy = PA
     B = max(B, 1)
     R = max(R, 2)
     return B, G, B * G, R
+
+
+def walk_steps(B: int, G: int, R: int, L: int, share: int = 1) -> int:
+    """Transitions a query runs: 2 R L per walk pair, R pairs per group of
+    ``share`` probes, ceil(B / share) groups in each of the G blocks."""
+    groups = G * -(-B // max(1, share))
+    return 2 * groups * R * L
 
 
 def theorem_L(n: int, eps: float, lam: float, d_s: int, d_t: int) -> int:

@@ -14,6 +14,14 @@
  *     S1 = sum_p U_p,  S2 = sum_p U_p^2,  Q_k = (S1^2 - S2)/(R(R-1))  (U-statistic)
  *   G blocks of B consecutive probes; block means; median    (median-of-means)
  *
+ * Walk sharing (an extension the paper does not make; off when M = 1): the
+ * probes of each block are taken in groups of M consecutive probes (the last
+ * group of a block may be smaller); all probes of a group are scored on the
+ * same R walk pairs, whose random streams are keyed by the group's first
+ * probe index. Groups never cross a block, so the G block means stay
+ * independent, and each Q_k is still unbiased (its walks are independent of
+ * its probe). With M = 1 this is Algorithm 1 exactly.
+ *
  * Conventions this oracle fixes where the paper leaves freedom (each is a
  * reading of the paper, the GPU path implements the same reading on its own):
  *   - Randomness: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11), key =
@@ -246,6 +254,46 @@ static float walk_sum(const graph_t* g, const domain_t* d, const probe_t* pr,
     return acc;
 }
 
+/* The sums of m probes over one walk: acc[j] = sum_i z^(j)_{X_i}/d_{X_i}, each in
+ * binary32 in step order, the walk's stream keyed by kwalk. */
+static void walk_sums(const graph_t* g, const domain_t* d, const probe_t* prs, int m,
+                      uint32_t start, int32_t L, uint64_t seed, uint32_t uid,
+                      uint32_t kwalk, uint32_t p, uint32_t side, float* acc)
+{
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t x = start;
+    for (int j = 0; j < m; j++) {
+        acc[j] = 0.0f;
+        int z = probe_z(d, &prs[j], x);
+        if (z > 0) acc[j] = acc[j] + g->inv[x];
+        else if (z < 0) acc[j] = acc[j] - g->inv[x];
+    }
+    uint32_t words[4] = {0, 0, 0, 0};
+    for (int32_t i = 1; i <= L; i++) {
+        uint32_t step = (uint32_t)(i - 1);
+        if ((step & 3u) == 0u) {
+            uint32_t c[4] = {step >> 2, p, kwalk, (uid << 1) | side};
+            philox4x32_10(c, key, words);
+        }
+        uint32_t u = words[step & 3u];
+        uint64_t deg = (uint64_t)(g->row_ptr[x + 1] - g->row_ptr[x]);
+        uint64_t jn = ((uint64_t)u * deg) >> 32;
+        x = (uint32_t)g->col[g->row_ptr[x] + (int64_t)jn];
+        for (int j = 0; j < m; j++) {
+            int z = probe_z(d, &prs[j], x);
+            if (z > 0) acc[j] = acc[j] + g->inv[x];
+            else if (z < 0) acc[j] = acc[j] - g->inv[x];
+        }
+    }
+}
+
+/* First probe of the walk-sharing group that holds probe k (blocks of B, groups of M). */
+static int64_t group_first(int64_t k, int64_t B, int64_t M)
+{
+    int64_t blk = k / B;
+    return blk * B + ((k - blk * B) / M) * M;
+}
+
 void pwo_walk_trace(uint32_t n, const int64_t* row_ptr, const int32_t* col,
                     uint32_t start, int32_t L, uint64_t seed, uint32_t uid,
                     uint32_t k, uint32_t p, uint32_t side, int32_t* trace, float* acc_out)
@@ -306,6 +354,7 @@ typedef struct {
     int32_t s, t, L;
     uint32_t uid;
     int64_t K, R, B, G;
+    int64_t M;              /* walk-sharing group size (1 = none) */
     int64_t k_begin, k_end; /* probe range to run (sampling); [0, K) for a full query */
     double beta;
     double* q_out;      /* optional, K entries */
@@ -316,25 +365,43 @@ static void run_query(const graph_t* g, uint64_t seed, query_t* q)
 {
     domain_t d = make_domain(g->n);
     i128* block_sum = (i128*)calloc((size_t)q->G, sizeof(i128));
-    for (int64_t k = q->k_begin; k < q->k_end; k++) {
-        probe_t pr;
-        make_probe(seed, q->uid, (uint32_t)k, g->n, &pr);
-        i128 S1 = 0;
-        u128 S2 = 0;
-        for (int64_t p = 0; p < q->R; p++) {
-            float a = walk_sum(g, &d, &pr, (uint32_t)q->s, q->L, seed, q->uid,
-                               (uint32_t)k, (uint32_t)p, 0u, NULL);
-            float b = walk_sum(g, &d, &pr, (uint32_t)q->t, q->L, seed, q->uid,
-                               (uint32_t)k, (uint32_t)p, 1u, NULL);
-            float U = a - b;
-            S1 += fix54(U);
-            S2 += sqfix64(U);
+    const int64_t M = q->M;
+    probe_t* prs = (probe_t*)malloc(sizeof(probe_t) * (size_t)M);
+    i128* S1 = (i128*)malloc(sizeof(i128) * (size_t)M);
+    u128* S2 = (u128*)malloc(sizeof(u128) * (size_t)M);
+    float* a = (float*)malloc(sizeof(float) * (size_t)M);
+    float* b = (float*)malloc(sizeof(float) * (size_t)M);
+    /* groups of M consecutive probes inside each block; k_end cuts at a group */
+    for (int64_t k0 = q->k_begin; k0 < q->k_end;) {
+        const int64_t blk_end = (k0 / q->B + 1) * q->B;
+        const int m = (int)(M < blk_end - k0 ? M : blk_end - k0);
+        for (int j = 0; j < m; j++) {
+            make_probe(seed, q->uid, (uint32_t)(k0 + j), g->n, &prs[j]);
+            S1[j] = 0;
+            S2[j] = 0;
         }
-        double Q = probe_q(S1, S2, q->R);
-        if (q->q_out) q->q_out[k] = Q;
-        i128 Qfix = (i128)ldexp(Q, 64); /* truncation toward zero */
-        block_sum[k / q->B] += Qfix;
+        for (int64_t p = 0; p < q->R; p++) {
+            walk_sums(g, &d, prs, m, (uint32_t)q->s, q->L, seed, q->uid, (uint32_t)k0, (uint32_t)p, 0u, a);
+            walk_sums(g, &d, prs, m, (uint32_t)q->t, q->L, seed, q->uid, (uint32_t)k0, (uint32_t)p, 1u, b);
+            for (int j = 0; j < m; j++) {
+                float U = a[j] - b[j];
+                S1[j] += fix54(U);
+                S2[j] += sqfix64(U);
+            }
+        }
+        for (int j = 0; j < m; j++) {
+            double Q = probe_q(S1[j], S2[j], q->R);
+            if (q->q_out) q->q_out[k0 + j] = Q;
+            i128 Qfix = (i128)ldexp(Q, 64); /* truncation toward zero */
+            block_sum[(k0 + j) / q->B] += Qfix;
+        }
+        k0 += m;
     }
+    free(prs);
+    free(S1);
+    free(S2);
+    free(a);
+    free(b);
     double* ybar = (double*)malloc(sizeof(double) * (size_t)q->G);
     for (int64_t gi = 0; gi < q->G; gi++)
         ybar[gi] = ldexp((double)block_sum[gi], -64) / (double)q->B;
@@ -371,14 +438,15 @@ static void* worker(void* arg)
 /*
  * Estimate a batch of queries; one query per thread at a time.
  *   K, R, B, G: per-query walk counts (the planner lives on the Python side).
+ *   M:  per-query walk-sharing group size (NULL = 1 for all: Algorithm 1).
  *   k_end: per-query number of probes actually run (k_end == K for a full
- *          query; smaller values time a sample of the probes).
+ *          query; smaller values time a sample of the probes; whole groups).
  *   q_out: optional K-entry array per query for query 0 only (may be NULL).
  */
 int pwo_estimate(uint32_t n, const int64_t* row_ptr, const int32_t* col,
                  int64_t nq, const int32_t* s, const int32_t* t, const int32_t* L,
                  const uint32_t* uid, const int64_t* K, const int64_t* R,
-                 const int64_t* B, const int64_t* G, const int64_t* k_end,
+                 const int64_t* B, const int64_t* G, const int64_t* M, const int64_t* k_end,
                  uint64_t seed, int nthreads, double* beta_out,
                  double* q_out0, double* ybar_out0)
 {
@@ -390,6 +458,7 @@ int pwo_estimate(uint32_t n, const int64_t* row_ptr, const int32_t* col,
         qs[i].s = s[i]; qs[i].t = t[i]; qs[i].L = L[i];
         qs[i].uid = uid ? uid[i] : (uint32_t)i;
         qs[i].K = K[i]; qs[i].R = R[i]; qs[i].B = B[i]; qs[i].G = G[i];
+        qs[i].M = (M && M[i] > 1) ? M[i] : 1;
         qs[i].k_begin = 0;
         qs[i].k_end = k_end ? k_end[i] : K[i];
         qs[i].q_out = (i == 0) ? q_out0 : NULL;
@@ -448,7 +517,7 @@ typedef struct {
     uint64_t seed;
     int32_t s, t, L;
     uint32_t uid;
-    int64_t R;
+    int64_t R, B, M;
     const uint32_t* ks;
     double* q;
     int64_t count;
@@ -466,13 +535,16 @@ static void* q_worker(void* arg)
         pthread_mutex_unlock(&pl->mu);
         if (i >= pl->count) break;
         uint32_t k = pl->ks[i];
+        /* the walks of probe k are those of its walk-sharing group */
+        uint32_t kw = (uint32_t)group_first((int64_t)k, pl->B, pl->M);
         probe_t pr;
         make_probe(pl->seed, pl->uid, k, pl->g->n, &pr);
         i128 S1 = 0;
         u128 S2 = 0;
         for (int64_t p = 0; p < pl->R; p++) {
-            float a = walk_sum(pl->g, &d, &pr, (uint32_t)pl->s, pl->L, pl->seed, pl->uid, k, (uint32_t)p, 0u, NULL);
-            float b = walk_sum(pl->g, &d, &pr, (uint32_t)pl->t, pl->L, pl->seed, pl->uid, k, (uint32_t)p, 1u, NULL);
+            float a, b;
+            walk_sums(pl->g, &d, &pr, 1, (uint32_t)pl->s, pl->L, pl->seed, pl->uid, kw, (uint32_t)p, 0u, &a);
+            walk_sums(pl->g, &d, &pr, 1, (uint32_t)pl->t, pl->L, pl->seed, pl->uid, kw, (uint32_t)p, 1u, &b);
             float U = a - b;
             S1 += fix54(U);
             S2 += sqfix64(U);
@@ -483,13 +555,15 @@ static void* q_worker(void* arg)
 }
 
 int pwo_probe_q(uint32_t n, const int64_t* row_ptr, const int32_t* col, int32_t s, int32_t t,
-                int32_t L, uint32_t uid, int64_t R, uint64_t seed, int64_t count,
+                int32_t L, uint32_t uid, int64_t R, int64_t B, int64_t M, uint64_t seed, int64_t count,
                 const uint32_t* ks, int nthreads, double* q_out)
 {
     graph_t g = {n, row_ptr, col, NULL};
     g.inv = (float*)malloc(sizeof(float) * n);
     for (uint32_t v = 0; v < n; v++) g.inv[v] = 1.0f / (float)(row_ptr[v + 1] - row_ptr[v]);
-    qpool_t pl = {&g, seed, s, t, L, uid, R, ks, q_out, count, 0, PTHREAD_MUTEX_INITIALIZER};
+    if (B < 1) B = 1;
+    if (M < 1) M = 1;
+    qpool_t pl = {&g, seed, s, t, L, uid, R, B, M, ks, q_out, count, 0, PTHREAD_MUTEX_INITIALIZER};
     if (nthreads < 1) nthreads = 1;
     if (nthreads > count) nthreads = (int)(count > 0 ? count : 1);
     pthread_t* th = (pthread_t*)malloc(sizeof(pthread_t) * (size_t)nthreads);

@@ -202,6 +202,30 @@ def test_budget_cap_and_invalid_queries(ba1k):
     assert res["status"].tolist() == [0, B.BD_E_BUDGET]
 
 
+def test_empty_and_all_invalid_batches(ba1k):
+    dg = load(ba1k, B.BD_LAYOUT_COMPACT)
+    pol = B.policy("fixed", B=1, R=2)
+    e = np.zeros(0, dtype=np.int32)
+    for ex in (B.exec_cfg("plain"), B.exec_cfg("batched"), B.exec_cfg("batched", use_graph=True)):
+        assert B.bd_query_batch(dg, e, e, 0.1, 5, SEED, pol, ex).size == 0
+        bad = B.bd_query_batch(dg, [1, 4], [1, 4], 0.1, 5, SEED, pol, ex)   # s == t only
+        assert bad["status"].tolist() == [B.BD_E_INVALID] * 2 and np.all(bad["beta"] == 0)
+    assert B.bd_truncated_beta(dg, e, e, 10).size == 0
+    srv = B.Server(dg, pol)
+    try:
+        out, _ = srv.wait(srv.submit(e, e, 0.1, 5, SEED))
+        assert out.size == 0
+        out, _ = srv.wait(srv.submit([3], [3], 0.1, 5, SEED))
+        assert out["status"].tolist() == [B.BD_E_INVALID]
+    finally:
+        srv.destroy()
+    # the smallest walk counts (K = 37, R = 2) at L = 0 and L = 1 against the oracle
+    for L in (0, 1):
+        r = B.bd_query_batch(dg, [5], [600], 0.1, L, SEED, pol, B.exec_cfg("batched"))
+        ref = E.estimate(ba1k, [5], [600], L, [(1, 37, 37, 2)], SEED, uid=[0])
+        assert r["beta"][0] == ref[0]
+
+
 def _mixed_batch(g, n, seed):
     s, t = queries.uniform_pairs(g.n, n, seed)
     eps, L = queries.mixed_eps_L(n, [0.3, 0.5, 0.7], [0, 1, 7, 60, 200], seed + 1)
