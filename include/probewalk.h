@@ -106,6 +106,13 @@ typedef struct {
     double   delta;          /* failure probability; G = ceil(8 ln(1/delta)); 0 -> 0.01 */
     int64_t  B_fixed, R_fixed;
     uint64_t max_steps_per_query;  /* 0 = no cap; a query above it gets BD_E_BUDGET */
+    int32_t  share;          /* walk sharing, an extension of Algorithm 1 (0 or 1 = off,
+                                at most 4): the probes of each median-of-means block are
+                                taken in groups of `share` consecutive probes scored on
+                                one set of R walk pairs, whose random streams are keyed
+                                by the group's first probe. Groups never cross a block,
+                                so the G block means stay independent and each Q_k stays
+                                unbiased; walk steps drop by about that factor. */
 } bd_policy;
 
 typedef struct {
@@ -113,7 +120,8 @@ typedef struct {
     int64_t  K, R;           /* probes and replicas per probe */
     int32_t  B, G, L;
     int32_t  status;         /* BD_OK, BD_E_INVALID or BD_E_BUDGET for this query */
-    int64_t  walk_steps;     /* 2*K*R*L transitions (saturates at INT64_MAX) */
+    int64_t  walk_steps;     /* 2*R*L transitions per walk pair, K*R pairs (G*ceil(B/share)*R
+                                with walk sharing); saturates at INT64_MAX */
 } bd_result;
 
 /*

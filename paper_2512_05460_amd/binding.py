@@ -61,7 +61,7 @@ EXPORTS = ("graph_load_csr", "graph_free", "bd_graph_get_info", "bd_plan", "bd_q
 class BdPolicy(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("c_B", ctypes.c_double), ("c_R", ctypes.c_double),
                 ("delta", ctypes.c_double), ("B_fixed", ctypes.c_int64), ("R_fixed", ctypes.c_int64),
-                ("max_steps_per_query", ctypes.c_uint64)]
+                ("max_steps_per_query", ctypes.c_uint64), ("share", ctypes.c_int32)]
 
 
 class BdExec(ctypes.Structure):
@@ -192,9 +192,9 @@ def _stream(stream):
     return stream.cuda_stream
 
 
-def policy(kind="paper", c_B=448.0, c_R=128.0, delta=0.01, B=0, R=0, max_steps=0) -> BdPolicy:
+def policy(kind="paper", c_B=448.0, c_R=128.0, delta=0.01, B=0, R=0, max_steps=0, share=1) -> BdPolicy:
     k = {"paper": BD_POLICY_PAPER, "scaled": BD_POLICY_SCALED, "fixed": BD_POLICY_FIXED}[kind]
-    return BdPolicy(k, c_B, c_R, delta, B, R, max_steps)
+    return BdPolicy(k, c_B, c_R, delta, B, R, max_steps, share)
 
 
 def exec_cfg(mode="batched", chunk_probes=0, grid_wgs=0, use_graph=False, chunk_pairs=0, queues=0,

@@ -358,6 +358,12 @@ int64_t ceil_guarded(double x)
     return (int64_t)std::ceil(x * kCeilGuard);
 }
 
+// walk-sharing group size of a policy (0 and 1: none)
+uint32_t policy_share(const bd_policy& p)
+{
+    return p.share > 1 ? (uint32_t)p.share : 1u;
+}
+
 bd_policy default_policy()
 {
     bd_policy p{};
@@ -375,7 +381,7 @@ void plan_one(const bd_graph* g, int32_t s, int32_t t, double eps, int32_t L, co
     std::memset(r, 0, sizeof(*r));
     r->L = L;
     if (s < 0 || t < 0 || s >= g->n || t >= g->n || s == t || !(eps > 0.0 && eps < 1.0) || L < 0 ||
-        L > kMaxL) {
+        L > kMaxL || pol.share < 0 || pol.share > (int32_t)kMaxShare) {
         r->status = BD_E_INVALID;
         return;
     }
@@ -406,14 +412,17 @@ void plan_one(const bd_graph* g, int32_t s, int32_t t, double eps, int32_t L, co
     const u128 i64max = (u128)INT64_MAX;
     const u128 K = (u128)(uint64_t)B * (u128)(uint64_t)G;
     r->K = K > i64max ? INT64_MAX : (int64_t)K;
+    // walks: R pairs per walk-sharing group, ceil(B/M) groups per block
+    const uint64_t M = pol.share > 1 ? (uint64_t)pol.share : 1u;
+    const u128 groups = (u128)(((uint64_t)B + M - 1) / M) * (u128)(uint64_t)G;
     u128 steps;
     if (L == 0) {
         steps = 0;
-    } else if ((K >> 64) != 0) {
+    } else if ((groups >> 64) != 0) {
         steps = i64max + 1;
     } else {
-        const u128 KR = K * (u128)(uint64_t)R;  // < 2^127
-        steps = (KR >> 112) != 0 ? i64max + 1 : 2 * KR * (u128)(uint64_t)L;  // L < 2^14
+        const u128 GR = groups * (u128)(uint64_t)R;  // < 2^127
+        steps = (GR >> 112) != 0 ? i64max + 1 : 2 * GR * (u128)(uint64_t)L;  // L < 2^14
     }
     r->walk_steps = steps > i64max ? INT64_MAX : (int64_t)steps;
     if (G > kMaxG || B > INT32_MAX || K >= 4294967295u || R >= (int64_t)4294967295LL)
@@ -457,10 +466,10 @@ GraphTables tables(const bd_graph* g)
     return t;
 }
 
-int resident_wgs(const bd_graph* g, int uniform)
+int resident_wgs(const bd_graph* g, int uniform, int share = 1)
 {
     int per_cu = 0;
-    if (walk_occupancy(g->layout, uniform, &per_cu) != 0 || per_cu < 1) per_cu = 1;
+    if (walk_occupancy(g->layout, uniform, share, &per_cu) != 0 || per_cu < 1) per_cu = 1;
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, g->device) != hipSuccess) return per_cu * 256;
     return per_cu * prop.multiProcessorCount;
@@ -478,66 +487,90 @@ uint32_t exec_queues(const bd_exec& ex)
 }
 
 struct ChunkPlan {
-    uint32_t kc = 1;       // probes per chunk (whole-probe chunks)
-    uint32_t part = 0;     // replicas per part, 0 = probes are not split
+    uint32_t gc = 1;       // walk-sharing groups per chunk (whole-group chunks)
+    uint32_t part = 0;     // replicas per part, 0 = groups are not split
 };
 
-ChunkPlan chunk_plan(const bd_exec& ex, uint32_t K, uint32_t R)
+// The walk-sharing groups of a query: each of the G blocks of B probes holds
+// ceil(B/M) groups of M consecutive probes (the last one may be smaller).
+struct Groups {
+    uint32_t B = 1, M = 1, per_block = 1, n = 0;
+    Groups() = default;
+    Groups(const QueryDesc& d)
+        : B(d.B), M(std::max<uint32_t>(d.share, 1u)), per_block((d.B + M - 1) / M), n(d.G * per_block)
+    {
+    }
+    uint32_t first(uint32_t gi) const { return (gi / per_block) * B + (gi % per_block) * M; }
+    uint32_t size(uint32_t gi) const { return std::min(M, B - (gi % per_block) * M); }
+};
+
+ChunkPlan chunk_plan(const bd_exec& ex, const QueryDesc& d)
 {
     ChunkPlan cp;
+    const Groups grp(d);
+    const uint32_t R = d.R;
     const uint32_t pairs = ex.chunk_pairs > 0 ? std::max<uint32_t>((uint32_t)ex.chunk_pairs, 64u)
                            : ex.mode == BD_MODE_PLAIN ? (uint32_t)kBlockThreads : kSplitReplicas;
     if (ex.mode != BD_MODE_PLAIN && R >= kUniformMinR && R > pairs) {
         const uint32_t parts = (R + pairs - 1) / pairs;
         cp.part = ((R + parts - 1) / parts + 63u) & ~63u;
-        cp.kc = 1;
+        cp.gc = 1;
         return cp;
     }
-    uint32_t kc;
+    uint32_t gc;
     if (ex.chunk_probes > 0) {
-        kc = (uint32_t)ex.chunk_probes;
+        gc = std::max<uint32_t>(1u, (uint32_t)ex.chunk_probes / grp.M);
     } else {
-        kc = (uint32_t)std::max<uint64_t>(1, ((uint64_t)pairs + R - 1) / R);
+        gc = (uint32_t)std::max<uint64_t>(1, ((uint64_t)pairs + R - 1) / R);
     }
-    kc = std::min<uint32_t>(kc, (uint32_t)kMaxChunkProbes);
-    kc = std::min<uint32_t>(kc, std::max<uint32_t>(K, 1));
-    cp.kc = std::max<uint32_t>(kc, 1);
+    gc = std::min<uint32_t>(gc, (uint32_t)kMaxChunkProbes / grp.M);
+    gc = std::min<uint32_t>(gc, std::max<uint32_t>(grp.n, 1));
+    cp.gc = std::max<uint32_t>(gc, 1);
     return cp;
 }
 
-// Emits the chunks of one query in order: (next_k, next_p) is the cursor.
+// Emits the chunks of one query in order: (next_g, next_p) is the cursor.
 struct ChunkCursor {
-    uint32_t q = 0, K = 0, R = 0;
+    uint32_t q = 0, R = 0;
+    Groups grp;
     ChunkPlan plan;
-    uint32_t next_k = 0, next_p = 0;
-    bool done() const { return next_k >= K; }
+    uint32_t next_g = 0, next_p = 0;
+    ChunkCursor() = default;
+    ChunkCursor(uint32_t q_, const QueryDesc& d, const bd_exec& ex)
+        : q(q_), R(d.R), grp(d), plan(chunk_plan(ex, d))
+    {
+    }
+    bool done() const { return next_g >= grp.n; }
     Chunk next()
     {
         Chunk c{};
         c.q = q;
-        c.k0 = next_k;
+        c.g0 = next_g;
         if (plan.part) {
-            c.kc = 1;
+            c.gc = 1;
             c.p0 = next_p;
             c.pc = std::min<uint32_t>(plan.part, R - next_p);
             next_p += c.pc;
             if (next_p >= R) {
                 next_p = 0;
-                ++next_k;
+                ++next_g;
             }
         } else {
-            c.kc = std::min<uint32_t>(plan.kc, K - next_k);
+            c.gc = std::min<uint32_t>(plan.gc, grp.n - next_g);
             c.p0 = 0;
             c.pc = R;
-            next_k += c.kc;
+            next_g += c.gc;
         }
+        c.k0 = grp.first(c.g0);
+        const uint32_t last = c.g0 + c.gc - 1;
+        c.kc = grp.first(last) + grp.size(last) - c.k0;
         return c;
     }
-    // walk steps of the next chunk (2 walks of L steps per replica)
+    // walk steps of the next chunk (2 walks of L steps per replica and group)
     uint64_t chunk_steps(uint32_t L) const
     {
         const uint64_t pairs = plan.part ? (uint64_t)std::min<uint32_t>(plan.part, R - next_p)
-                                         : (uint64_t)std::min<uint32_t>(plan.kc, K - next_k) * R;
+                                         : (uint64_t)std::min<uint32_t>(plan.gc, grp.n - next_g) * R;
         return 2ull * pairs * ((uint64_t)L + 1);
     }
 };
@@ -554,6 +587,7 @@ struct Batch {
     // the rest; qoff[part][i] is the first chunk of queue i relative to the part
     uint32_t nqueues = 1;
     uint32_t qoff[2][kMaxQueues + 1] = {};
+    int share = 1;                      // kernel instance for the walk-sharing factor
 };
 
 // Run one set of valid queries: zero the tables, launch, read the results.
@@ -615,7 +649,7 @@ int run_batch(bd_graph* g, const Batch& b, const bd_exec& ex, hipStream_t user_s
     const uint32_t parts[3] = {0u, b.n_uniform, (uint32_t)b.chunks.size()};
     for (int part = 0; part < 2; ++part) {
         const uint32_t nch = parts[part + 1] - parts[part];
-        uint32_t grid = ex.grid_wgs > 0 ? (uint32_t)ex.grid_wgs : (uint32_t)resident_wgs(g, part == 0);
+        uint32_t grid = ex.grid_wgs > 0 ? (uint32_t)ex.grid_wgs : (uint32_t)resident_wgs(g, part == 0, b.share);
         grids[part] = std::min<uint32_t>(grid, nch);
     }
     auto launch_persistent = [&](hipStream_t s2) -> int {
@@ -628,7 +662,7 @@ int run_batch(bd_graph* g, const Batch& b, const bd_exec& ex, hipStream_t user_s
             ab.persistent = 1;
             ab.nqueues = b.nqueues;
             for (uint32_t i = 0; i <= b.nqueues; ++i) ab.qoff[i] = b.qoff[part][i];
-            if (launch_walk(ab, layout, part == 0, grids[part], s2) != hipSuccess) return BD_E_HIP;
+            if (launch_walk(ab, layout, part == 0, b.share, grids[part], s2) != hipSuccess) return BD_E_HIP;
         }
         return BD_OK;
     };
@@ -666,7 +700,7 @@ int run_batch(bd_graph* g, const Batch& b, const bd_exec& ex, hipStream_t user_s
             aq.persistent = 0;
             const int uniform = b.qd[q].R >= kUniformMinR;
             status = timed([&] {
-                return launch_walk(aq, layout, uniform, c1 - c0, st) == hipSuccess ? BD_OK : BD_E_HIP;
+                return launch_walk(aq, layout, uniform, b.share, c1 - c0, st) == hipSuccess ? BD_OK : BD_E_HIP;
             });
         }
     } else if (!graph_mode) {
@@ -725,8 +759,11 @@ int run_batch(bd_graph* g, const Batch& b, const bd_exec& ex, hipStream_t user_s
 
 // Build descriptors and the chunk table for the valid queries of a batch.
 void build_batch(const bd_graph* g, int64_t nq, const int32_t* s, const int32_t* t, const int32_t* L,
-                 const uint32_t* uid, uint64_t seed, const bd_result* plans, const bd_exec& ex, Batch& b)
+                 const uint32_t* uid, uint64_t seed, const bd_result* plans, const bd_exec& ex, uint32_t share,
+                 Batch& b)
 {
+    share = std::max<uint32_t>(share, 1u);
+    b.share = share_class(share);
     for (int64_t i = 0; i < nq; ++i) {
         const bd_result& r = plans[i];
         if (r.status != BD_OK) continue;
@@ -742,6 +779,7 @@ void build_batch(const bd_graph* g, int64_t nq, const int32_t* s, const int32_t*
         d.slot = (uint32_t)b.qd.size();
         d.seed_lo = (uint32_t)seed;
         d.seed_hi = (uint32_t)(seed >> 32);
+        d.share = share;
         b.G = std::max<uint32_t>(b.G, d.G);
         b.index.push_back(i);
         b.qd.push_back(d);
@@ -758,10 +796,11 @@ void build_batch(const bd_graph* g, int64_t nq, const int32_t* s, const int32_t*
         uint64_t nu = 0;
         for (const QueryDesc& d : b.qd) {
             if ((int64_t)d.R < umin) continue;
-            const ChunkPlan cp = chunk_plan(ex, d.K, d.R);
-            nu += cp.part ? (uint64_t)d.K * ((d.R + cp.part - 1) / cp.part) : (d.K + cp.kc - 1) / cp.kc;
+            const ChunkPlan cp = chunk_plan(ex, d);
+            const uint32_t ng = Groups(d).n;
+            nu += cp.part ? (uint64_t)ng * ((d.R + cp.part - 1) / cp.part) : (ng + cp.gc - 1) / cp.gc;
         }
-        if (nu < (uint64_t)resident_wgs(g, 1)) umin = INT64_MAX;
+        if (nu < (uint64_t)resident_wgs(g, 1, b.share)) umin = INT64_MAX;
     }
     auto uniform = [&](size_t q) { return ex.mode != BD_MODE_PLAIN && (int64_t)b.qd[q].R >= umin; };
     std::vector<size_t> order(b.qd.size());
@@ -776,11 +815,7 @@ void build_batch(const bd_graph* g, int64_t nq, const int32_t* s, const int32_t*
     b.chunk_begin.assign(b.qd.size(), 0);
     auto emit = [&](size_t q) {
         QueryDesc& d = b.qd[q];
-        ChunkCursor cur;
-        cur.q = (uint32_t)q;
-        cur.K = d.K;
-        cur.R = d.R;
-        cur.plan = chunk_plan(ex, d.K, d.R);
+        ChunkCursor cur((uint32_t)q, d, ex);
         if (cur.plan.part) {
             d.psum_base = b.split_probes;
             b.split_probes += d.K;
@@ -833,7 +868,7 @@ extern "C" int bd_query_batch(bd_graph* g, int64_t nq, const int32_t* s, const i
     }
     std::lock_guard<std::mutex> lock(g->mu);
     Batch b;
-    build_batch(g, nq, s, t, L, uid, seed, out, ex, b);
+    build_batch(g, nq, s, t, L, uid, seed, out, ex, policy_share(p), b);
     std::vector<double> beta;
     const int rc = run_batch(g, b, ex, (hipStream_t)stream, beta, stats, nullptr, nullptr);
     if (rc != BD_OK) return rc;
@@ -842,7 +877,8 @@ extern "C" int bd_query_batch(bd_graph* g, int64_t nq, const int32_t* s, const i
         r.beta = beta[q];
         if (stats) {
             stats->walk_steps += r.walk_steps;
-            stats->walk_pairs += r.K * r.R;
+            const int64_t M = (int64_t)policy_share(p);
+            stats->walk_pairs += (int64_t)r.G * ((r.B + M - 1) / M) * r.R;
         }
     }
     if (stats) stats->total_ms = now_ms() - t0;
@@ -863,7 +899,7 @@ extern "C" int bd_query_probes(bd_graph* g, int32_t s, int32_t t, double eps, in
     if (out->status != BD_OK) return out->status;
     std::lock_guard<std::mutex> lock(g->mu);
     Batch b;
-    build_batch(g, 1, &s, &t, &L, &uid, seed, out, ex, b);
+    build_batch(g, 1, &s, &t, &L, &uid, seed, out, ex, policy_share(p), b);
     std::vector<double> beta;
     const int rc = run_batch(g, b, ex, (hipStream_t)stream, beta, nullptr, q_out, ybar_out);
     if (rc != BD_OK) return rc;
@@ -1190,7 +1226,7 @@ extern "C" int bd_gather_roofline(bd_graph* g, int32_t chains_per_lane, int32_t 
         (chains_per_lane != 1 && chains_per_lane != 2 && chains_per_lane != 4 && chains_per_lane != 8))
         return BD_E_INVALID;
     hipStream_t st = (hipStream_t)stream;
-    uint32_t grid = work_groups > 0 ? (uint32_t)work_groups : 4u * (uint32_t)resident_wgs(g, 1);
+    uint32_t grid = work_groups > 0 ? (uint32_t)work_groups : 4u * (uint32_t)resident_wgs(g, 1, 1);
     DevBuf sink;
     int rc = sink.alloc((size_t)grid * kBlockThreads * 4);
     if (rc != BD_OK) return rc;
@@ -1458,9 +1494,9 @@ int admit(bd_server* S)
         bool fits = true;
         for (size_t i = 0; i < need && fits; ++i) {
             const QueryDesc& d = r.desc[i];
-            if (chunk_plan(ex, d.K, d.R).part && !S->psum_alloc.alloc(d.K, &base[i])) {
+            if (chunk_plan(ex, d).part && !S->psum_alloc.alloc(d.K, &base[i])) {
                 for (size_t j = 0; j < i; ++j)
-                    if (chunk_plan(ex, r.desc[j].K, r.desc[j].R).part) S->psum_alloc.release(base[j], r.desc[j].K);
+                    if (chunk_plan(ex, r.desc[j]).part) S->psum_alloc.release(base[j], r.desc[j].K);
                 fits = false;
             }
         }
@@ -1482,11 +1518,7 @@ int admit(bd_server* S)
             SlotState& ss = S->slot[sl];
             ss.req = id;
             ss.ridx = r.index[i];
-            ss.cur = ChunkCursor();
-            ss.cur.q = sl;
-            ss.cur.K = d.K;
-            ss.cur.R = d.R;
-            ss.cur.plan = chunk_plan(ex, d.K, d.R);
+            ss.cur = ChunkCursor(sl, d, ex);
             ss.L = (uint32_t)d.L;
             ss.steps = (uint64_t)r.res[(size_t)ss.ridx].walk_steps;
             ss.uniform = d.R >= kUniformMinR;
@@ -1612,7 +1644,8 @@ int launch_slice(bd_server* S, Slice& sl)
         ap.qoff[0] = 0;
         ap.qoff[1] = ap.nchunks;
         const uint32_t grid = std::min<uint32_t>((uint32_t)S->resident[part == 0], ap.nchunks);
-        if (grid && launch_walk(ap, S->g->layout, part == 0, grid, st) != hipSuccess)
+        if (grid && launch_walk(ap, S->g->layout, part == 0, share_class(policy_share(S->pol)), grid, st) !=
+                        hipSuccess)
             return BD_E_HIP;
     }
     if (hipMemcpyAsync(sl.comp_h.p, sl.d_comp.p, comp_prefix_bytes(S), hipMemcpyDeviceToHost, st) != hipSuccess)
@@ -1709,8 +1742,8 @@ extern "C" int bd_server_create(bd_graph* g, const bd_server_cfg* cfg, bd_server
         delete S;
         return BD_E_BUDGET;
     }
-    S->resident[0] = resident_wgs(g, 0);
-    S->resident[1] = resident_wgs(g, 1);
+    S->resident[0] = resident_wgs(g, 0, share_class(policy_share(S->pol)));
+    S->resident[1] = resident_wgs(g, 1, share_class(policy_share(S->pol)));
     int rc = S->d_qd.alloc((size_t)S->slots * sizeof(QueryDesc));
     if (rc == BD_OK) rc = S->d_bs.alloc((size_t)S->slots * S->gdim * 16);
     if (rc == BD_OK) rc = S->d_done.alloc((size_t)S->slots * 4);
@@ -1779,13 +1812,14 @@ extern "C" int bd_server_submit(bd_server* S, int64_t nq, const int32_t* s, cons
         d.G = (uint32_t)pr.G;
         d.seed_lo = (uint32_t)seed;
         d.seed_hi = (uint32_t)(seed >> 32);
+        d.share = policy_share(S->pol);
         r.desc.push_back(d);
         r.index.push_back(i);
         r.steps += (uint64_t)pr.walk_steps;
         bd_exec ex{};
         ex.mode = BD_MODE_BATCHED;
         ex.chunk_probes = S->cfg.chunk_probes;
-        if (chunk_plan(ex, d.K, d.R).part) r.split_probes += d.K;
+        if (chunk_plan(ex, d).part) r.split_probes += d.K;
     }
     r.remaining = (int64_t)r.desc.size();
     if (r.desc.size() > S->slots || r.split_probes > S->arena) return BD_E_FULL;

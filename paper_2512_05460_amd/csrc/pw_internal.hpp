@@ -15,18 +15,24 @@ struct QueryDesc {
     uint32_t slot;      // row of the block-sum / done / result tables
     uint32_t seed_lo, seed_hi;  // 64-bit Philox key of this query
     uint32_t psum_base; // first per-probe accumulator of a query whose probes are split
+    uint32_t share;     // walk-sharing group size M (1 = every probe has its own walks)
 };
 
-// A work-group chunk: replicas [p0, p0 + pc) of probes [k0, k0 + kc) of query q.
-// Either pc == R (whole probes), or kc == 1 and the probe's replicas are split
-// over several chunks whose partial sums meet in a per-probe accumulator.
+// A work-group chunk: replicas [p0, p0 + pc) of the walk-sharing groups
+// [g0, g0 + gc) of query q, which hold probes [k0, k0 + kc). Groups number
+// ceil(B/M) per block: group j of block b holds probes bB + jM .. up to M of
+// them, never past the block. Either pc == R (whole groups), or gc == 1 and
+// the group's replicas are split over several chunks whose partial sums meet
+// in per-probe accumulators. With M = 1 a group is a probe (g0 = k0).
 struct Chunk {
     uint32_t q;
     uint32_t k0;
     uint32_t kc;
     uint32_t p0;
     uint32_t pc;
-    uint32_t pad[3];
+    uint32_t g0;
+    uint32_t gc;
+    uint32_t pad;
 };
 
 struct DomainParams {
@@ -77,6 +83,11 @@ struct WalkArgs {
     uint32_t qoff[9];
 };
 
+// Largest walk-sharing group the kernels are built for.
+constexpr uint32_t kMaxShare = 4;
+// Kernel instance for a sharing factor M: 1, 2 or 4 probes per walk.
+inline int share_class(uint32_t M) { return M <= 1 ? 1 : M <= 2 ? 2 : 4; }
+
 constexpr int kBlockThreads = 256;
 constexpr uint32_t kMaxQueues = 8;      // one chunk queue per XCD
 constexpr int kMaxChunkProbes = 256;
@@ -91,7 +102,7 @@ constexpr uint32_t kSplitReplicas = 4096;
 // Launchers (defined in pw_kernels.hip). All return hipError_t of the launch.
 // uniform: every chunk of the launch has R >= kUniformMinR.
 // layout: 0 CSR, 1 fat, 2 compact.
-hipError_t launch_walk(const WalkArgs& a, int layout, int uniform, uint32_t grid, hipStream_t st);
+hipError_t launch_walk(const WalkArgs& a, int layout, int uniform, int share, uint32_t grid, hipStream_t st);
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);
 hipError_t launch_trace(const GraphTables& g, int layout, uint32_t count, const int32_t* start,
                         const uint32_t* uid, const uint32_t* k, const uint32_t* p,
@@ -113,6 +124,6 @@ hipError_t launch_colsum(const double* H, uint32_t n, uint32_t Q, double* sq, do
 hipError_t launch_nmul(const uint32_t* rp, const uint32_t* col, const uint32_t* col24, uint32_t n, const double* x,
                        double* y, hipStream_t st);
 // Work groups of the walk kernel that fit on the device at once.
-int walk_occupancy(int layout, int uniform, int* wgs_per_cu);
+int walk_occupancy(int layout, int uniform, int share, int* wgs_per_cu);
 
 }  // namespace pw

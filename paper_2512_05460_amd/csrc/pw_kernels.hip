@@ -90,6 +90,81 @@ __device__ __forceinline__ float walk_pair(const DevGraph& G, const Probe& pr, W
     return __fsub_rn(a, b);
 }
 
+// Walk sharing: one walk scored against the m <= kShare probes of a group.
+// The terms of each probe enter its own binary32 sum in step order, exactly as
+// in advance/walk_pair.
+template <int kLayout, int kShare>
+__device__ __forceinline__ void advance_m(WalkState& w, float* acc, uint32_t m, uint32_t u, const DevGraph& G,
+                                          const Probe* pr)
+{
+    const uint32_t xp = w.x;
+    const float ip = w.inv;
+    step<kLayout>(w, u, G);
+#pragma unroll
+    for (int j = 0; j < kShare; ++j)
+        if ((uint32_t)j < m) acc[j] = add_term(acc[j], xp, ip, pr[j], G.dom);
+}
+
+// U_p for each probe of a group; the walks' streams are keyed by kw, the
+// group's first probe.
+template <int kLayout, int kShare>
+__device__ __forceinline__ void walk_pair_m(const DevGraph& G, const Probe* pr, uint32_t m, WalkState ws,
+                                            WalkState wt, int L, uint32_t p, uint32_t kw, uint32_t uid,
+                                            uint32_t slo, uint32_t shi, float* U)
+{
+    float a[kShare], b[kShare];
+#pragma unroll
+    for (int j = 0; j < kShare; ++j) a[j] = b[j] = 0.0f;
+    const uint32_t cs = uid << 1, ct = (uid << 1) | 1u;
+    const int full = L >> 2;
+    for (int blk = 0; blk < full; ++blk) {
+        const U4 rs = philox10((uint32_t)blk, p, kw, cs, slo, shi);
+        const U4 rt = philox10((uint32_t)blk, p, kw, ct, slo, shi);
+        advance_m<kLayout, kShare>(ws, a, m, rs.x, G, pr);
+        advance_m<kLayout, kShare>(wt, b, m, rt.x, G, pr);
+        advance_m<kLayout, kShare>(ws, a, m, rs.y, G, pr);
+        advance_m<kLayout, kShare>(wt, b, m, rt.y, G, pr);
+        advance_m<kLayout, kShare>(ws, a, m, rs.z, G, pr);
+        advance_m<kLayout, kShare>(wt, b, m, rt.z, G, pr);
+        advance_m<kLayout, kShare>(ws, a, m, rs.w, G, pr);
+        advance_m<kLayout, kShare>(wt, b, m, rt.w, G, pr);
+    }
+    const int rem = L & 3;
+    if (rem) {
+        const U4 rs = philox10((uint32_t)full, p, kw, cs, slo, shi);
+        const U4 rt = philox10((uint32_t)full, p, kw, ct, slo, shi);
+        advance_m<kLayout, kShare>(ws, a, m, rs.x, G, pr);
+        advance_m<kLayout, kShare>(wt, b, m, rt.x, G, pr);
+        if (rem > 1) {
+            advance_m<kLayout, kShare>(ws, a, m, rs.y, G, pr);
+            advance_m<kLayout, kShare>(wt, b, m, rt.y, G, pr);
+        }
+        if (rem > 2) {
+            advance_m<kLayout, kShare>(ws, a, m, rs.z, G, pr);
+            advance_m<kLayout, kShare>(wt, b, m, rt.z, G, pr);
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < kShare; ++j) {
+        if ((uint32_t)j < m) {
+            a[j] = add_term(a[j], ws.x, ws.inv, pr[j], G.dom);
+            b[j] = add_term(b[j], wt.x, wt.inv, pr[j], G.dom);
+        }
+        U[j] = __fsub_rn(a[j], b[j]);
+    }
+}
+
+// Probes [*kf, *kf + *sz) of walk-sharing group gi: groups of M probes inside
+// each block of B (the last group of a block may be smaller).
+__device__ __forceinline__ void group_probes(uint32_t gi, uint32_t B, uint32_t M, uint32_t gpb, uint32_t* kf,
+                                             uint32_t* sz)
+{
+    const uint32_t blk = gi / gpb;
+    const uint32_t j = gi - blk * gpb;
+    *kf = blk * B + j * M;
+    *sz = min(M, B - j * M);
+}
+
 __device__ __forceinline__ void lds_add_i128(unsigned long long* p, i128 v)
 {
     const unsigned long long lo = (unsigned long long)(u128)v;
@@ -137,7 +212,7 @@ __device__ void finalize_query(const WalkArgs& A, const QueryDesc& d, double* ys
     __threadfence();
 }
 
-template <int kLayout, int kUniform>
+template <int kLayout, int kUniform, int kShare>
 __device__ void run_chunk(const WalkArgs& A, const DevGraph& G, uint32_t ci,
                           unsigned long long* acc, double* ys)
 {
@@ -149,71 +224,116 @@ __device__ void run_chunk(const WalkArgs& A, const DevGraph& G, uint32_t ci,
 
     const WalkState s0 = start_at<kLayout>(G, (uint32_t)d.s);
     const WalkState t0 = start_at<kLayout>(G, (uint32_t)d.t);
+    // walk sharing: M probes per group, ceil(B/M) groups per block
+    const uint32_t M = kShare == 1 ? 1u : d.share;
+    const uint32_t gpb = (d.B + M - 1) / M;
     if (kUniform) {
-        // Each wave takes blocks of 64 consecutive replicas of one probe, so the
-        // probe index and every probe key are uniform across the wave (scalar
-        // registers); only the last block of a probe runs partially masked.
+        // Each wave takes blocks of 64 consecutive replicas of one group, so the
+        // group and every probe key are uniform across the wave (scalar
+        // registers); only the last block of a group runs partially masked.
         const uint32_t wave = __builtin_amdgcn_readfirstlane((uint32_t)tid >> 6);
         const uint32_t lane = (uint32_t)tid & 63u;
         const uint32_t nb = (c.pc + 63u) >> 6;
-        const uint32_t units = c.kc * nb;
+        const uint32_t units = c.gc * nb;
         const uint32_t pend = c.p0 + c.pc;
         for (uint32_t u = wave; u < units; u += kBlockThreads / 64) {
-            const uint32_t kk = u / nb;
-            const uint32_t p = c.p0 + (u - kk * nb) * 64u + lane;
-            const uint32_t k = c.k0 + kk;
+            const uint32_t gg = u / nb;
+            const uint32_t p = c.p0 + (u - gg * nb) * 64u + lane;
             if (p < pend) {
-                const Probe pr = make_probe(d.seed_lo, d.seed_hi, d.uid, k, G.dom.n);
-                const float U = walk_pair<kLayout>(G, pr, s0, t0, d.L, p, k, d.uid, d.seed_lo, d.seed_hi);
-                lds_add_i128(acc + 4 * kk, fix54(U));
-                lds_add_i128(acc + 4 * kk + 2, (i128)sqfix64(U));
+                if constexpr (kShare == 1) {
+                    const uint32_t k = c.k0 + gg;
+                    const Probe pr = make_probe(d.seed_lo, d.seed_hi, d.uid, k, G.dom.n);
+                    const float U = walk_pair<kLayout>(G, pr, s0, t0, d.L, p, k, d.uid, d.seed_lo, d.seed_hi);
+                    lds_add_i128(acc + 4 * gg, fix54(U));
+                    lds_add_i128(acc + 4 * gg + 2, (i128)sqfix64(U));
+                } else {
+                    uint32_t kf, sz;
+                    group_probes(c.g0 + gg, d.B, M, gpb, &kf, &sz);
+                    Probe pr[kShare];
+#pragma unroll
+                    for (int j = 0; j < kShare; ++j)
+                        if ((uint32_t)j < sz) pr[j] = make_probe(d.seed_lo, d.seed_hi, d.uid, kf + j, G.dom.n);
+                    float U[kShare];
+                    walk_pair_m<kLayout, kShare>(G, pr, sz, s0, t0, d.L, p, kf, d.uid, d.seed_lo, d.seed_hi, U);
+#pragma unroll
+                    for (int j = 0; j < kShare; ++j) {
+                        if ((uint32_t)j < sz) {
+                            unsigned long long* a4 = acc + 4 * (kf + j - c.k0);
+                            lds_add_i128(a4, fix54(U[j]));
+                            lds_add_i128(a4 + 2, (i128)sqfix64(U[j]));
+                        }
+                    }
+                }
             }
         }
     } else {
-        // Any replica count: lanes stride over the chunk's (probe, replica)
-        // pairs, so one wave can cover several probes.
-        const uint64_t total = (uint64_t)c.kc * c.pc;
+        // Any replica count: lanes stride over the chunk's (group, replica)
+        // pairs, so one wave can cover several groups.
+        const uint64_t total = (uint64_t)c.gc * c.pc;
         for (uint64_t base = 0; base < total; base += kBlockThreads) {
             const uint64_t w = base + (uint64_t)tid;
             if (w < total) {
-                const uint32_t kk = (uint32_t)(w / c.pc);
-                const uint32_t p = c.p0 + (uint32_t)(w - (uint64_t)kk * c.pc);
-                const uint32_t k = c.k0 + kk;
-                const Probe pr = make_probe(d.seed_lo, d.seed_hi, d.uid, k, G.dom.n);
-                const float U = walk_pair<kLayout>(G, pr, s0, t0, d.L, p, k, d.uid, d.seed_lo, d.seed_hi);
-                lds_add_i128(acc + 4 * kk, fix54(U));
-                lds_add_i128(acc + 4 * kk + 2, (i128)sqfix64(U));
+                const uint32_t gg = (uint32_t)(w / c.pc);
+                const uint32_t p = c.p0 + (uint32_t)(w - (uint64_t)gg * c.pc);
+                if constexpr (kShare == 1) {
+                    const uint32_t k = c.k0 + gg;
+                    const Probe pr = make_probe(d.seed_lo, d.seed_hi, d.uid, k, G.dom.n);
+                    const float U = walk_pair<kLayout>(G, pr, s0, t0, d.L, p, k, d.uid, d.seed_lo, d.seed_hi);
+                    lds_add_i128(acc + 4 * gg, fix54(U));
+                    lds_add_i128(acc + 4 * gg + 2, (i128)sqfix64(U));
+                } else {
+                    uint32_t kf, sz;
+                    group_probes(c.g0 + gg, d.B, M, gpb, &kf, &sz);
+                    Probe pr[kShare];
+#pragma unroll
+                    for (int j = 0; j < kShare; ++j)
+                        if ((uint32_t)j < sz) pr[j] = make_probe(d.seed_lo, d.seed_hi, d.uid, kf + j, G.dom.n);
+                    float U[kShare];
+                    walk_pair_m<kLayout, kShare>(G, pr, sz, s0, t0, d.L, p, kf, d.uid, d.seed_lo, d.seed_hi, U);
+#pragma unroll
+                    for (int j = 0; j < kShare; ++j) {
+                        if ((uint32_t)j < sz) {
+                            unsigned long long* a4 = acc + 4 * (kf + j - c.k0);
+                            lds_add_i128(a4, fix54(U[j]));
+                            lds_add_i128(a4 + 2, (i128)sqfix64(U[j]));
+                        }
+                    }
+                }
             }
         }
     }
     __syncthreads();
 
     if (c.pc < d.R) {
-        // Part of a split probe: add the partial sums to the probe's accumulator;
-        // the chunk that brings its replica count to R forms Q_R.
+        // Part of a split group: add each probe's partial sums to its
+        // accumulator; the chunk that brings a probe's replica count to R forms
+        // its Q_R.
         if (tid == 0) {
-            const size_t pi = (size_t)d.psum_base + c.k0;
-            unsigned long long* ps = A.psum + pi * 4;
-            atomic_add_i128(ps, (i128)(((u128)acc[1] << 64) | (u128)acc[0]));
-            atomic_add_i128(ps + 2, (i128)(((u128)acc[3] << 64) | (u128)acc[2]));
-            __threadfence();
-            const uint32_t prev = atomicAdd(A.pcount + pi, c.pc);
-            if (prev + c.pc == d.R) {
+            for (uint32_t j = 0; j < c.kc; ++j) {
+                const uint32_t k = c.k0 + j;
+                const size_t pi = (size_t)d.psum_base + k;
+                unsigned long long* ps = A.psum + pi * 4;
+                atomic_add_i128(ps, (i128)(((u128)acc[4 * j + 1] << 64) | (u128)acc[4 * j]));
+                atomic_add_i128(ps + 2, (i128)(((u128)acc[4 * j + 3] << 64) | (u128)acc[4 * j + 2]));
                 __threadfence();
-                const i128 S1 = load_i128(ps);
-                const u128 S2 = (u128)load_i128(ps + 2);
-                const double Q = probe_q(S1, S2, d.R);
-                if (A.q_debug) A.q_debug[c.k0] = Q;
-                atomic_add_i128(A.blocksum + ((size_t)d.slot * A.gdim + c.k0 / d.B) * 2,
-                                f64_to_i128_trunc(Q * 0x1p64));
-                // every part of this probe has been added: clear it for reuse
-                ps[0] = ps[1] = ps[2] = ps[3] = 0ull;
-                A.pcount[pi] = 0u;
-                __threadfence();
-                const uint32_t old = atomicAdd(A.done + d.slot, 1u);
-                if (old + 1u == d.K) {
+                const uint32_t prev = atomicAdd(A.pcount + pi, c.pc);
+                if (prev + c.pc == d.R) {
                     __threadfence();
-                    finalize_query(A, d, ys);
+                    const i128 S1 = load_i128(ps);
+                    const u128 S2 = (u128)load_i128(ps + 2);
+                    const double Q = probe_q(S1, S2, d.R);
+                    if (A.q_debug) A.q_debug[k] = Q;
+                    atomic_add_i128(A.blocksum + ((size_t)d.slot * A.gdim + k / d.B) * 2,
+                                    f64_to_i128_trunc(Q * 0x1p64));
+                    // every part of this probe has been added: clear it for reuse
+                    ps[0] = ps[1] = ps[2] = ps[3] = 0ull;
+                    A.pcount[pi] = 0u;
+                    __threadfence();
+                    const uint32_t old = atomicAdd(A.done + d.slot, 1u);
+                    if (old + 1u == d.K) {
+                        __threadfence();
+                        finalize_query(A, d, ys);
+                    }
                 }
             }
         }
@@ -244,8 +364,9 @@ __device__ void run_chunk(const WalkArgs& A, const DevGraph& G, uint32_t ci,
 
 // kUniform: every chunk of the launch has R >= kUniformMinR (see run_chunk).
 // Eight waves per SIMD where the kernel fits 64 VGPRs without spilling.
-template <int kLayout, int kUniform>
-__global__ __launch_bounds__(kBlockThreads, (kUniform || kLayout == kLayoutCompact) ? 8 : 1) void walk_kernel(
+template <int kLayout, int kUniform, int kShare>
+__global__ __launch_bounds__(kBlockThreads,
+                             kShare == 1 && (kUniform || kLayout == kLayoutCompact) ? 8 : 1) void walk_kernel(
     WalkArgs A)
 {
     __shared__ unsigned long long acc[kMaxChunkProbes * 4];
@@ -253,7 +374,7 @@ __global__ __launch_bounds__(kBlockThreads, (kUniform || kLayout == kLayoutCompa
     __shared__ uint32_t next;
     const DevGraph G = make_graph(A.g);
     if (!A.persistent) {
-        if (blockIdx.x < A.nchunks) run_chunk<kLayout, kUniform>(A, G, blockIdx.x, acc, ys);
+        if (blockIdx.x < A.nchunks) run_chunk<kLayout, kUniform, kShare>(A, G, blockIdx.x, acc, ys);
         return;
     }
     // Claim chunks from the queue of this XCD first, then from the others in
@@ -290,39 +411,54 @@ __global__ __launch_bounds__(kBlockThreads, (kUniform || kLayout == kLayoutCompa
         const uint32_t ci = next;
         __syncthreads();
         if (ci >= A.nchunks) break;
-        run_chunk<kLayout, kUniform>(A, G, ci, acc, ys);
+        run_chunk<kLayout, kUniform, kShare>(A, G, ci, acc, ys);
     }
 }
 
-static const void* walk_fn(int layout, int uniform)
+template <int kLayout>
+static const void* walk_fn_l(int uniform, int share)
 {
-    if (layout == kLayoutFat) return uniform ? (const void*)walk_kernel<1, 1> : (const void*)walk_kernel<1, 0>;
-    if (layout == kLayoutCompact) return uniform ? (const void*)walk_kernel<2, 1> : (const void*)walk_kernel<2, 0>;
-    return uniform ? (const void*)walk_kernel<0, 1> : (const void*)walk_kernel<0, 0>;
+    if (share == 4) return uniform ? (const void*)walk_kernel<kLayout, 1, 4> : (const void*)walk_kernel<kLayout, 0, 4>;
+    if (share == 2) return uniform ? (const void*)walk_kernel<kLayout, 1, 2> : (const void*)walk_kernel<kLayout, 0, 2>;
+    return uniform ? (const void*)walk_kernel<kLayout, 1, 1> : (const void*)walk_kernel<kLayout, 0, 1>;
 }
 
-hipError_t launch_walk(const WalkArgs& a, int layout, int uniform, uint32_t grid, hipStream_t st)
+static const void* walk_fn(int layout, int uniform, int share)
+{
+    if (layout == kLayoutFat) return walk_fn_l<kLayoutFat>(uniform, share);
+    if (layout == kLayoutCompact) return walk_fn_l<kLayoutCompact>(uniform, share);
+    return walk_fn_l<kLayoutCsr>(uniform, share);
+}
+
+template <int kLayout, int kUniform>
+static void launch_l(const WalkArgs& a, int share, uint32_t grid, hipStream_t st)
+{
+    if (share == 4) hipLaunchKernelGGL((walk_kernel<kLayout, kUniform, 4>), dim3(grid), dim3(kBlockThreads), 0, st, a);
+    else if (share == 2) hipLaunchKernelGGL((walk_kernel<kLayout, kUniform, 2>), dim3(grid), dim3(kBlockThreads), 0, st, a);
+    else hipLaunchKernelGGL((walk_kernel<kLayout, kUniform, 1>), dim3(grid), dim3(kBlockThreads), 0, st, a);
+}
+
+hipError_t launch_walk(const WalkArgs& a, int layout, int uniform, int share, uint32_t grid, hipStream_t st)
 {
     if (grid == 0) return hipSuccess;
-#define PW_WALK(Lay, U) hipLaunchKernelGGL((walk_kernel<Lay, U>), dim3(grid), dim3(kBlockThreads), 0, st, a)
     if (layout == kLayoutFat) {
-        if (uniform) PW_WALK(1, 1);
-        else PW_WALK(1, 0);
+        if (uniform) launch_l<kLayoutFat, 1>(a, share, grid, st);
+        else launch_l<kLayoutFat, 0>(a, share, grid, st);
     } else if (layout == kLayoutCompact) {
-        if (uniform) PW_WALK(2, 1);
-        else PW_WALK(2, 0);
+        if (uniform) launch_l<kLayoutCompact, 1>(a, share, grid, st);
+        else launch_l<kLayoutCompact, 0>(a, share, grid, st);
     } else {
-        if (uniform) PW_WALK(0, 1);
-        else PW_WALK(0, 0);
+        if (uniform) launch_l<kLayoutCsr, 1>(a, share, grid, st);
+        else launch_l<kLayoutCsr, 0>(a, share, grid, st);
     }
-#undef PW_WALK
     return hipGetLastError();
 }
 
-int walk_occupancy(int layout, int uniform, int* wgs_per_cu)
+int walk_occupancy(int layout, int uniform, int share, int* wgs_per_cu)
 {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, walk_fn(layout, uniform), kBlockThreads, 0) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, walk_fn(layout, uniform, share), kBlockThreads, 0) !=
+        hipSuccess)
         return -1;
     *wgs_per_cu = nb;
     return 0;
