@@ -292,6 +292,7 @@ def main():
     ap.add_argument("--no-roofline", action="store_true")
     ap.add_argument("--no-small", action="store_true")
     ap.add_argument("--no-grid", action="store_true")
+    ap.add_argument("--no-sharing", action="store_true")
     ap.add_argument("--no-served-cl10m", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calib", type=int, default=0,
@@ -386,6 +387,30 @@ def main():
         srv.destroy()
         extra["served"] = {"queries_per_s": nq / dts, "vs_plain": (nq / dts) / qps,
                            "request_latency_ms": lats}
+    if not args.no_sharing:
+        # the same batch, plain mode, with walk sharing at its own calibrated budget
+        from paper_2512_05460_amd.budgets import SHARED_BUDGETS
+        log("walk sharing, same batch, plain mode")
+        spol = budget_policy(WORKLOAD, shared=True)
+        splan = B.bd_plan(dg, s, t, EPS, L, spol)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        kms_sh = 0.0
+        for i in range(nq):
+            r, st = B.bd_query_batch(dg, s[i:i + 1], t[i:i + 1], EPS, L, seed, spol, plain, uid=[i],
+                                     stream=stream, with_stats=True)
+            assert r["status"][0] == 0
+            kms_sh += st["walk_kernel_ms"]
+        torch.cuda.synchronize()
+        dts = time.perf_counter() - t1
+        M, cb, cr, how = SHARED_BUDGETS[WORKLOAD]
+        extra["walk_sharing"] = {
+            "what": ("probes of each median-of-means block scored in groups of M on one set of walks "
+                     "(an extension of Algorithm 1), at its own calibrated walk counts"),
+            "policy": {"kind": "scaled", "share": M, "c_B": cb, "c_R": cr, "calibration": how},
+            "queries_per_s": nq / dts, "vs_plain": (nq / dts) / qps,
+            "walk_steps_per_s": float(splan["walk_steps"].sum()) / dts,
+            "kernel_walk_steps_per_s": float(splan["walk_steps"].sum()) / (kms_sh / 1e3)}
     if not args.no_small:
         extra["small_queries"] = small_queries(B, torch, stream)
     if not args.no_grid:

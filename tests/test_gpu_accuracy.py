@@ -4,6 +4,8 @@
     pseudoinverse (oracle); at least 95% of queries within eps.
   * Chung-Lu n=1e5, the 128 reference pairs of tests/golden (CG, two solves),
     eps=0.05, L=1000: at least 95% within eps.
+  * The same 128 pairs with walk sharing (4 probes per walk set) at its own
+    calibrated budget: at least 95% within eps.
   * 1,414 x 1,414 grid (bipartite), the 32 pairs of tests/golden at eps in
     {0.02, 0.05, 0.1} and L in {500, 2000, 5000}: at least 95% within eps of
     the truncated distance beta^(L) (binary64 series, oracle).
@@ -68,6 +70,25 @@ def test_accuracy_cl100k():
     frac = float((err <= 0.05).mean())
     _say(f"[cl100k] within eps: {frac:.3f}, median rel err {np.median(err):.4f}, "
          f"{st['walk_steps']:.3e} steps in {st['walk_kernel_ms']:.0f} ms")
+    assert frac >= 0.95
+
+
+@pytest.mark.timeout(600)
+def test_accuracy_cl100k_walk_sharing():
+    # walk sharing (groups of 4 probes per walk set) at its own calibrated budget
+    g = graphs.workload_graph("cl100k")
+    ref = np.loadtxt(GOLDEN, comments="#")
+    s = ref[:, 1].astype(np.int32)
+    t = ref[:, 2].astype(np.int32)
+    beta = ref[:, 5]
+    dg = B.graph_load_csr(g.n, g.row_ptr, g.col, B.BD_LAYOUT_COMPACT)
+    pol = budget_policy("cl100k", shared=True)
+    assert pol.share == 4
+    res, st = B.bd_query_batch(dg, s, t, 0.05, 1000, SEED, pol, B.exec_cfg("batched"), with_stats=True)
+    assert np.all(res["status"] == 0)
+    frac = float((np.abs(res["beta"] - beta) <= 0.05 * beta).mean())
+    _say(f"[cl100k shared] within eps: {frac:.3f}, {st['walk_steps']:.3e} steps in {st['walk_kernel_ms']:.0f} ms")
+    dg.free()
     assert frac >= 0.95
 
 
