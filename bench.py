@@ -280,6 +280,70 @@ def served_cl10m(B, torch, seconds_per_load=10.0):
     return out
 
 
+def scale_cl40m(B, torch, stream, served_queries=65536):
+    """The scale workload: Chung-Lu n=4*10^7 (mean degree 25, exponent 2.2,
+    largest component, about 10^9 adjacency entries; native generator), CSR
+    layout with hubs stored first; the 262,144 queries (eps = 0.05, L over
+    {1000, 10000}) in one persistent launch, then the first `served_queries`
+    of them as requests of 4,096 submitted together to the server;
+    throughput walk counts."""
+    from paper_2512_05460_amd.budgets import BUDGETS, budget_policy
+    from synth import graphs, queries
+
+    log("scale: building Chung-Lu n=4e7")
+    t0 = time.perf_counter()
+    g = graphs.workload_graph("cl40m")
+    t_gen = time.perf_counter() - t0
+    log(f"scale: n={g.n} nnz={g.nnz} in {t_gen:.0f} s; loading")
+    t0 = time.perf_counter()
+    dg = B.graph_load_csr(g.n, g.row_ptr, g.col, B.BD_LAYOUT_CSR | B.BD_RELABEL_DEGREE)
+    t_load = time.perf_counter() - t0
+    s, t, eps, Ls = queries.workload_batch("cl40m", g.n)
+    pol = budget_policy("cl40m")
+    seed = graphs.PHILOX_SEED
+    plan = B.bd_plan(dg, s, t, eps, Ls, pol)
+    steps = float(plan["walk_steps"].sum())
+    log(f"scale: {s.size} queries, {steps:.3e} walk steps, batched")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r, st = B.bd_query_batch(dg, s, t, eps, Ls, seed, pol, B.exec_cfg("batched"), stream=stream, with_stats=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    assert np.all(r["status"] == 0)
+    m = served_queries
+    srv = B.Server(dg, pol)
+    log(f"scale: served, {m} queries as requests of 4096")
+    t0 = time.perf_counter()
+    rids = [srv.submit(s[j:j + 4096], t[j:j + 4096], eps[j:j + 4096], Ls[j:j + 4096], seed,
+                       uid=np.arange(j, j + 4096)) for j in range(0, m, 4096)]
+    lat = []
+    for k, rid in enumerate(rids):
+        o, l_ms = srv.wait(rid)
+        assert np.array_equal(o["beta"], r["beta"][4096 * k:4096 * k + 4096])
+        lat.append(l_ms)
+    dts = time.perf_counter() - t0
+    srv.destroy()
+    steps_m = float(plan["walk_steps"][:m].sum())
+    roof = max((B.bd_gather_roofline(dg, c, 1000) for c in (2, 4, 8)), key=lambda x: x["steps_per_s"])
+    info = dg.info()
+    dg.free()
+    c_B, c_R, how = BUDGETS["cl40m"]
+    return {
+        "workload": ("Chung-Lu n=40,000,000 mean degree 25 exponent 2.2 LCC; 262,144 uniform pairs; eps=0.05; "
+                     "L over {1000, 10000}"),
+        "graph": {"n": g.n, "nnz": g.nnz, "layout": "csr, hubs first", "device_bytes": info["device_bytes"],
+                  "generate_s": t_gen, "load_s": t_load},
+        "policy": {"kind": "scaled", "c_B": c_B, "c_R": c_R, "calibration": how},
+        "walk_steps": steps,
+        "batched_queries_per_s": s.size / dt, "batched_walk_steps_per_s": steps / dt,
+        "kernel_walk_steps_per_s": steps / (st["walk_kernel_ms"] / 1e3),
+        "gather_roofline_steps_per_s": roof["steps_per_s"],
+        "gather_roofline_frac": steps / (st["walk_kernel_ms"] / 1e3) / roof["steps_per_s"],
+        "served_queries": m, "served_queries_per_s": m / dts, "served_walk_steps_per_s": steps_m / dts,
+        "served_request_latency_ms": {"p50": float(np.percentile(lat, 50)), "max": float(max(lat))},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -293,6 +357,8 @@ def main():
     ap.add_argument("--no-small", action="store_true")
     ap.add_argument("--no-grid", action="store_true")
     ap.add_argument("--no-sharing", action="store_true")
+    ap.add_argument("--scale", action="store_true",
+                    help="also run the Chung-Lu n=4e7 workload (about 3 minutes more)")
     ap.add_argument("--no-served-cl10m", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calib", type=int, default=0,
@@ -417,6 +483,8 @@ def main():
         extra["grid_batched"] = grid_batched(B, torch, stream)
     if not args.no_served_cl10m:
         extra["served_cl10m"] = served_cl10m(B, torch)
+    if args.scale:
+        extra["scale_cl40m"] = scale_cl40m(B, torch, stream)
     roof = None
     if not args.no_roofline:
         log("gather roofline")

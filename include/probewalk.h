@@ -298,14 +298,16 @@ typedef struct {
     int64_t   max_queries_inflight;   /* admission cap on resident queries (0 = 65536) */
     uint64_t  max_steps_inflight;     /* admission cap on outstanding walk steps (0 = none) */
     int32_t   chunk_probes;           /* 0 = automatic */
-    double    slice_ms;               /* target device time per scheduling slice (0 = 20) */
+    double    slice_ms;               /* least device time per scheduling slice (0 = 20); a slice
+                                         also lasts at least four times its longest chunk */
 } bd_server_cfg;
 
 /*
  * Create a server over a loaded graph. The server owns a host scheduler thread
- * and a device stream; requests submitted while others run are admitted at
+ * and device streams; requests submitted while others run are admitted at
  * the next slice boundary as capacity frees up, and their chunks share the
- * device with the running ones. The graph must outlive the server.
+ * device with the running ones (round-robin over requests, replica parts of
+ * at most 1024 pairs). The graph must outlive the server.
  */
 int  bd_server_create(bd_graph* g, const bd_server_cfg* cfg, bd_server** out);
 /* Submit nq queries (host arrays, copied). Returns a request id. BD_E_FULL if

@@ -39,7 +39,10 @@ BUDGETS = {
     # L=1000: B = 100/16/4 and R median 3 (up to ~1,800 for hub pairs), a
     # throughput setting for the serving measurement, not calibrated.
     "cl10m": (0.04, 128.0 / 2 ** 28, "throughput setting, not calibrated"),
-    "cl40m": (448.0 / 1024, 128.0 / 2 ** 18, "provisional"),
+    # Chung-Lu n=4e7 (1e9 adjacency entries), eps=0.05, L in {1000, 10000}:
+    # B = 1 (K = 37) and R = 2 for most pairs (up to ~6,000 for hub pairs), a
+    # throughput setting for the full 262,144-query set, not calibrated.
+    "cl40m": (0.0025, 128.0 / 2 ** 37, "throughput setting, not calibrated"),
 }
 
 

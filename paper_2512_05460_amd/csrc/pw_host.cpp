@@ -1404,6 +1404,8 @@ struct RangeAlloc {
 };
 
 struct Slice {
+    double max_cost = 0;  // largest chunk cost (L + 1) * passes over the work group's lanes
+    double sum_cost = 0;  // summed chunk costs
     PinnedBuf chunks_h;
     DevBuf chunks_d;
     DevBuf d_cursor;   // chunk cursors of the slice's launches
@@ -1419,6 +1421,7 @@ struct Slice {
 };
 
 constexpr uint32_t kSliceMaxChunks = 1u << 18;
+constexpr int32_t kServerChunkPairs = 1024;
 
 }  // namespace
 
@@ -1450,9 +1453,23 @@ struct bd_server {
     uint64_t inflight_steps = 0;
     double steps_per_ms = 5e7;
     double t_last_done = 0;
+    // a lane's time per walk step (ms): a chunk needs about (L + 1) steps per
+    // pass of the work group over its pairs, however few pairs it has
+    double ms_per_lane_step = 1e-3;
 };
 
 namespace {
+
+// How the server cuts queries into chunks: as the batched mode, with replica
+// parts of at most 1024 pairs so that no chunk holds a slice open for long.
+bd_exec server_exec(const bd_server* S)
+{
+    bd_exec ex{};
+    ex.mode = BD_MODE_BATCHED;
+    ex.chunk_probes = S->cfg.chunk_probes;
+    ex.chunk_pairs = kServerChunkPairs;
+    return ex;
+}
 
 size_t comp_bytes(const bd_server* S)
 {
@@ -1487,9 +1504,7 @@ int admit(bd_server* S)
         const uint64_t cap = S->cfg.max_steps_inflight;
         if (cap && S->inflight_steps > 0 && S->inflight_steps + r.steps > cap) break;
         // memory admission: accumulators of split probes, all or nothing
-        bd_exec ex{};
-        ex.mode = BD_MODE_BATCHED;
-        ex.chunk_probes = S->cfg.chunk_probes;
+        const bd_exec ex = server_exec(S);
         std::vector<uint32_t> base(need, 0);
         bool fits = true;
         for (size_t i = 0; i < need && fits; ++i) {
@@ -1575,16 +1590,26 @@ int process_completions(bd_server* S, const Slice& sl)
 }
 
 // Take chunks round-robin for one slice. Caller holds mu.
+// A slice lasts at least as long as its longest chunk, so its work target is
+// the larger of slice_ms and four times that chunk's expected time: a slice
+// then holds several chunks per work group and its tail stays short. Within
+// the slice, the longest chunks start first.
 void fill_slice(bd_server* S, Slice& sl)
 {
     const double slice_ms = S->cfg.slice_ms > 0 ? S->cfg.slice_ms : 20.0;
-    const double target = slice_ms * S->steps_per_ms;
     Chunk* out = sl.chunks_h.as<Chunk>();
     sl.n = 0;
     sl.steps = 0;
-    std::vector<Chunk> small;  // chunks of queries with R < kUniformMinR go after the others
-    while (!S->rr.empty() && sl.n + small.size() < kSliceMaxChunks &&
-           ((double)sl.steps < target || sl.n + small.size() < (size_t)S->resident[1])) {
+    sl.max_cost = 0;
+    sl.sum_cost = 0;
+    double target = slice_ms * S->steps_per_ms;
+    struct Item {
+        double cost;
+        Chunk c;
+    };
+    std::vector<Item> big, small;  // wave-uniform chunks, then the rest
+    while (!S->rr.empty() && big.size() + small.size() < kSliceMaxChunks &&
+           ((double)sl.steps < target || big.size() + small.size() < (size_t)S->resident[1])) {
         const uint64_t id = S->rr.front();
         S->rr.pop_front();
         Request& r = S->reqs[id];
@@ -1593,18 +1618,28 @@ void fill_slice(bd_server* S, Slice& sl)
         SlotState& ss = S->slot[q];
         sl.steps += ss.cur.chunk_steps(ss.L);
         const Chunk c = ss.cur.next();
-        if (ss.uniform) out[sl.n++] = c;
-        else small.push_back(c);
+        const double cost = ((double)ss.L + 1.0) *
+                            (double)(((uint64_t)c.gc * c.pc + kBlockThreads - 1) / kBlockThreads);
+        sl.sum_cost += cost;
+        if (cost > sl.max_cost) {
+            sl.max_cost = cost;
+            target = std::max(target, 4.0 * cost * S->ms_per_lane_step * S->steps_per_ms);
+        }
+        (ss.uniform ? big : small).push_back(Item{cost, c});
         if (!ss.cur.done()) r.rr_slots.push_back(q);
         if (!r.rr_slots.empty()) S->rr.push_back(id);
         else r.in_rr = false;
     }
+    auto longest_first = [](const Item& a, const Item& b) { return a.cost > b.cost; };
+    std::stable_sort(big.begin(), big.end(), longest_first);
+    std::stable_sort(small.begin(), small.end(), longest_first);
+    for (const Item& it : big) out[sl.n++] = it.c;
     // The wave-uniform chunks get a launch of their own only when they can fill
     // the device; otherwise the general kernel (which runs any chunk) takes them
     // at the head of its table, so the slice is one launch and no part of it
     // waits for a nearly empty one.
     sl.n_uniform = sl.n >= (uint32_t)S->resident[1] ? sl.n : 0u;
-    for (const Chunk& c : small) out[sl.n++] = c;
+    for (const Item& it : small) out[sl.n++] = it.c;
 }
 
 int launch_slice(bd_server* S, Slice& sl)
@@ -1695,6 +1730,10 @@ void server_loop(bd_server* S)
                 const double dt = tn - std::max(sl.t_launch, S->t_last_done);
                 S->t_last_done = tn;
                 if (dt > 0.5 && sl.steps > 0) S->steps_per_ms = 0.7 * S->steps_per_ms + 0.3 * (sl.steps / dt);
+                // resident work groups ran the slice's summed chunk costs in dt
+                if (dt > 0.5 && sl.sum_cost > 0)
+                    S->ms_per_lane_step = 0.7 * S->ms_per_lane_step +
+                                          0.3 * std::min(dt * (double)S->resident[0] / sl.sum_cost, 1e-2);
                 rc = process_completions(S, sl);
             }
             sl.inflight = false;
@@ -1816,9 +1855,7 @@ extern "C" int bd_server_submit(bd_server* S, int64_t nq, const int32_t* s, cons
         r.desc.push_back(d);
         r.index.push_back(i);
         r.steps += (uint64_t)pr.walk_steps;
-        bd_exec ex{};
-        ex.mode = BD_MODE_BATCHED;
-        ex.chunk_probes = S->cfg.chunk_probes;
+        const bd_exec ex = server_exec(S);
         if (chunk_plan(ex, d).part) r.split_probes += d.K;
     }
     r.remaining = (int64_t)r.desc.size();

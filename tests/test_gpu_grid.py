@@ -48,6 +48,7 @@ def _oracle_plans(g, s, t, eps, L):
     return [OP.plan(float(eps[i]), int(L[i]), int(d[s[i]]), int(d[t[i]]), g.d_min, op) for i in range(s.size)]
 
 
+@pytest.mark.timeout(300)
 def test_grid_info(grid):
     g, dg = grid
     info = dg.info()

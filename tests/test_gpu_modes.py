@@ -36,8 +36,8 @@ def _graph(key, flags):
 
 @pytest.mark.parametrize("flags", [B.BD_LAYOUT_COMPACT, B.BD_LAYOUT_CSR | B.BD_RELABEL_DEGREE])
 def test_split_probe_parity(flags):
-    # R = 5000 > 4096: batched and served launches cut each probe's replicas
-    # into parts (2560 + 2440); plain launches keep whole probes.
+    # R = 5000 > the replica-part size: batched and served launches cut each probe's replicas
+    # into parts (2560 + 2440 in batched launches); plain launches keep whole probes.
     g, dg = _graph("ba1k", flags)
     s, t, L = 10, 900, 5
     pol = B.policy("fixed", B=1, R=5000)
@@ -134,7 +134,7 @@ def test_served_many_completions_per_slice():
 
 def test_served_admission_caps_and_split():
     g, dg = _graph("ba1k", B.BD_LAYOUT_COMPACT)
-    pol = B.policy("fixed", B=1, R=4500)  # every probe split into two parts
+    pol = B.policy("fixed", B=1, R=4500)  # every probe split into replica parts
     srv = B.Server(dg, pol, max_queries=4)
     try:
         with pytest.raises(B.ProbeWalkError) as ei:

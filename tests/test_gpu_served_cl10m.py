@@ -40,6 +40,7 @@ def cl10m():
     dg.free()
 
 
+@pytest.mark.timeout(600)
 def test_cl10m_resident(cl10m):
     g, dg = cl10m
     info = dg.info()

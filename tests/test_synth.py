@@ -98,3 +98,21 @@ def test_largest_component_matches_rebuild():
     ref = graphs.csr_from_edges(lc.n, new_id[rows[m]], new_id[g.col[m]])
     assert np.array_equal(lc.row_ptr, ref.row_ptr) and np.array_equal(lc.col, ref.col)
     assert lc.col.dtype == np.int32
+
+
+def test_native_chung_lu():
+    # canonical CSR, connected, independent of the thread count, degrees near target
+    a = graphs.chung_lu_native(50_000, 25.0, 2.2, 3, threads=1)
+    b = graphs.chung_lu_native(50_000, 25.0, 2.2, 3, threads=4)
+    assert np.array_equal(a.row_ptr, b.row_ptr) and np.array_equal(a.col, b.col)
+    assert a.col.dtype == np.int32 and a.row_ptr.dtype == np.int64
+    A = a.scipy()
+    assert (A != A.T).nnz == 0 and A.diagonal().sum() == 0
+    for v in range(0, a.n, 97):
+        row = a.col[a.row_ptr[v]:a.row_ptr[v + 1]]
+        assert np.all(np.diff(row) > 0)
+    import scipy.sparse.csgraph as csgraph
+    assert csgraph.connected_components(A, directed=False)[0] == 1
+    assert 0.9 * 50_000 < a.n <= 50_000 and 22 < a.nnz / a.n < 26
+    c = graphs.chung_lu_native(50_000, 25.0, 2.2, 4, threads=2)
+    assert not np.array_equal(a.col[:1000], c.col[:1000])
