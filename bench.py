@@ -5,8 +5,11 @@ connected component (99,163 nodes, 997,038 adjacency entries); uniform (s,t)
 pairs; eps = 0.05, L = 1000; walk counts from the scaled policy of Algorithm 1
 (constants in paper_2512_05460_amd/budgets.py). One step = one batch of
 queries run in the plain mode (one query per launch, fixed tiling). The same
-batch is also run in the batched (persistent, work-stealing) mode and through
-the server (continuous batching), reported beside the headline.
+batch is also run in the batched (persistent, work-stealing) mode, through
+the server (continuous batching) and with walk sharing, reported beside the
+headline; so are the small-query, grid (mixed eps and L, hipGraph) and served
+Chung-Lu n=10^7 (Poisson arrivals) workloads, and with --scale the Chung-Lu
+n=4*10^7 one.
 
 Prints one JSON line. The graph is resident on the device before the timed
 region; each query's 48-byte descriptor travels host->device inside the call
