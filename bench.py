@@ -219,7 +219,7 @@ def served_cl10m(B, torch, seconds_per_load=10.0):
 
     log("served: building Chung-Lu n=10^7")
     g = graphs.workload_graph("cl10m")
-    dg = B.graph_load_csr(g.n, g.row_ptr, g.col, B.BD_LAYOUT_COMPACT)
+    dg = B.graph_load_csr(g.n, g.row_ptr, g.col, B.BD_LAYOUT_COMPACT | B.BD_RELABEL_DEGREE)
     pol = budget_policy("cl10m")
     seed = graphs.PHILOX_SEED
     base = graphs.GRAPH_SEED + 3 + graphs.QUERY_SEED_OFFSET + 0x10
@@ -242,7 +242,8 @@ def served_cl10m(B, torch, seconds_per_load=10.0):
     out = {"workload": ("Chung-Lu n=10,000,000 mean degree 10 exponent 2.3 LCC; Poisson arrivals of request "
                         "batches of 2^U uniform pairs, U uniform on 0..12; eps per query from {0.02, 0.05, 0.1}; "
                         "L=1000"),
-           "graph": {"n": g.n, "nnz": g.nnz, "layout": "compact", "device_bytes": dg.info()["device_bytes"]},
+           "graph": {"n": g.n, "nnz": g.nnz, "layout": "compact, hubs first",
+                     "device_bytes": dg.info()["device_bytes"]},
            "policy": {"kind": "scaled", "c_B": BUDGETS["cl10m"][0], "c_R": BUDGETS["cl10m"][1],
                       "calibration": BUDGETS["cl10m"][2]},
            "admission": "slots 65,536 queries; per-probe accumulator arena; no walk-step cap",
@@ -353,7 +354,8 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--queries", type=int, default=32, help="queries per step")
-    ap.add_argument("--layout", choices=["compact", "csr", "fat"], default="compact")
+    ap.add_argument("--layout", choices=["hubs", "compact", "csr", "fat"], default="hubs",
+                    help="hubs: compact layout with nodes in descending-degree order and hub entries in LDS")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--no-roofline", action="store_true")
@@ -386,7 +388,8 @@ def main():
     s_all, t_all = queries.uniform_pairs(g.n, 4096, graphs.GRAPH_SEED + 1 + graphs.QUERY_SEED_OFFSET)
     nq = args.queries
     s, t = s_all[:nq], t_all[:nq]
-    flags = {"compact": B.BD_LAYOUT_COMPACT, "csr": B.BD_LAYOUT_CSR | B.BD_RELABEL_DEGREE,
+    flags = {"hubs": B.BD_LAYOUT_COMPACT | B.BD_RELABEL_DEGREE, "compact": B.BD_LAYOUT_COMPACT,
+             "csr": B.BD_LAYOUT_CSR | B.BD_RELABEL_DEGREE,
              "fat": B.BD_LAYOUT_FAT | B.BD_RELABEL_DEGREE}[args.layout]
     dg = B.graph_load_csr(g.n, g.row_ptr, g.col, flags)
     pol = budget_policy(WORKLOAD)

@@ -65,14 +65,17 @@ typedef struct bd_graph bd_graph;
                                    result are unchanged */
 #define BD_LAYOUT_COMPACT   8u  /* 32-bit row offsets + 3-byte neighbour ids, 1/degree
                                    recomputed: the smallest footprint (n <= 2^24; not with
-                                   BD_LAYOUT_FAT or BD_RELABEL_DEGREE) */
+                                   BD_LAYOUT_FAT). With BD_RELABEL_DEGREE: 8-byte node
+                                   entries {row offset, original id} in descending-degree
+                                   order, the 1024 highest-degree ones staged in LDS by
+                                   every work group (layout code 3) */
 
 typedef struct {
     int64_t  n, nnz;
     int32_t  d_min, d_max;
     int32_t  bipartite;      /* 1 if the graph is bipartite (section 2.1 assumes not;
                                 the estimator still targets beta^(L)) */
-    int32_t  layout;         /* 0 CSR, 1 fat, 2 compact */
+    int32_t  layout;         /* 0 CSR, 1 fat, 2 compact, 3 compact with hubs first */
     int64_t  device_bytes;   /* device memory held by the graph tables */
 } bd_graph_info;
 

@@ -168,14 +168,22 @@ __device__ __forceinline__ int probe_value(uint32_t x, const Probe& pr, const Do
 // Compact layout (ids as given, n <= 2^24): row offsets rp[0..n] as uint32 and
 // neighbour ids packed in 3 bytes each; 1.0f/degree is recomputed (correctly
 // rounded) at every step instead of stored.
-constexpr int kLayoutCsr = 0, kLayoutFat = 1, kLayoutCompact = 2;
+// Compact layout with hubs first: storage ids in descending-degree order, node
+// entries {row offset, original id} (8 bytes; entry n = {nnz, 0}), neighbour
+// storage ids packed in 3 bytes; the entries of the first kHubNodes storage ids
+// (the highest-degree nodes, which the walks visit most) are staged in LDS.
+constexpr int kLayoutCsr = 0, kLayoutFat = 1, kLayoutCompact = 2, kLayoutCompactHub = 3;
+constexpr uint32_t kHubNodes = 1024;
 
 struct DevGraph {
     const uint4* node;      // n entries (CSR and fat layouts)
     const uint32_t* col;    // nnz entries (CSR layout)
     const uint4* adj;       // nnz entries (fat layout)
     const uint32_t* rp;     // n + 1 entries (compact layout)
-    const uint32_t* col24;  // 3 nnz bytes + padding, read as aligned words (compact layout)
+    const uint32_t* col24;  // 3 nnz bytes + padding, read as aligned words (compact layouts)
+    const uint2* node8;     // n + 1 entries {row offset, original id} (compact layout, hubs first)
+    const uint2* hub;       // LDS copy of node8[0 .. nhub] (nhub = 0: none)
+    uint32_t nhub;
     Domain dom;
 };
 
@@ -200,6 +208,24 @@ __device__ __forceinline__ void compact_row(const DevGraph& G, uint32_t x, WalkS
     w.inv = __fdiv_rn(1.0f, (float)w.deg);
 }
 
+// Node x of the compact layout with hubs first: entries x and x + 1 (LDS for
+// the staged hubs, else one 16-byte global load), the probe sees the original id.
+__device__ __forceinline__ void hub_row(const DevGraph& G, uint32_t x, WalkState& w)
+{
+    uint2 a, b;
+    if (x < G.nhub) {
+        a = G.hub[x];
+        b = G.hub[x + 1];
+    } else {
+        a = G.node8[x];
+        b = G.node8[x + 1];
+    }
+    w.x = a.y;
+    w.off = a.x;
+    w.deg = b.x - a.x;
+    w.inv = __fdiv_rn(1.0f, (float)w.deg);
+}
+
 // Walk state at internal id x (the start of a walk).
 template <int kLayout>
 __device__ __forceinline__ WalkState start_at(const DevGraph& G, uint32_t x)
@@ -207,6 +233,11 @@ __device__ __forceinline__ WalkState start_at(const DevGraph& G, uint32_t x)
     if (kLayout == kLayoutCompact) {
         WalkState w;
         compact_row(G, x, w);
+        return w;
+    }
+    if (kLayout == kLayoutCompactHub) {
+        WalkState w;
+        hub_row(G, x, w);
         return w;
     }
     return start_state(G.node[x]);
@@ -224,20 +255,35 @@ __device__ __forceinline__ void step(WalkState& w, uint32_t u, const DevGraph& G
         w.off = e.y;
         w.deg = e.z;
         w.inv = __uint_as_float(e.w);
-    } else if (kLayout == kLayoutCompact) {
+    } else if (kLayout == kLayoutCompact || kLayout == kLayoutCompactHub) {
         // the 3 bytes at byte offset 3*pos lie in the aligned 8 bytes at word (3*pos)/4
         const uint32_t o = pos * 3u;
         const uint32_t wi = o >> 2;
         const uint32_t lo = G.col24[wi];
         const uint32_t hi = G.col24[wi + 1];
         const uint32_t x = __builtin_amdgcn_alignbit(hi, lo, (o & 3u) * 8u) & 0xFFFFFFu;
-        compact_row(G, x, w);
+        if (kLayout == kLayoutCompact) compact_row(G, x, w);
+        else hub_row(G, x, w);
     } else {
         const uint4 e = G.node[G.col[pos]];
         w.x = e.w;
         w.off = e.x;
         w.deg = e.y;
         w.inv = __uint_as_float(e.z);
+    }
+}
+
+// Copy the hub entries of the compact layout with hubs first into LDS (every
+// thread of the block must call it); other layouts keep nhub = 0.
+template <int kLayout>
+__device__ __forceinline__ void stage_hubs(DevGraph& G, uint2* lds)
+{
+    if constexpr (kLayout == kLayoutCompactHub) {
+        const uint32_t nh = min(kHubNodes, G.dom.n);
+        for (uint32_t i = threadIdx.x; i <= nh; i += blockDim.x) lds[i] = G.node8[i];
+        __syncthreads();
+        G.hub = lds;
+        G.nhub = nh;
     }
 }
 

@@ -45,6 +45,7 @@ struct GraphTables {
     const uint4* adj;
     const uint32_t* rp;
     const uint32_t* col24;
+    const uint2* node8;
     DomainParams dom;
 };
 

@@ -26,6 +26,9 @@ __device__ __forceinline__ DevGraph make_graph(const GraphTables& g)
     G.adj = g.adj;
     G.rp = g.rp;
     G.col24 = g.col24;
+    G.node8 = g.node8;
+    G.hub = nullptr;
+    G.nhub = 0;
     G.dom.n = g.dom.n;
     G.dom.rb = g.dom.rb;
     G.dom.mask = g.dom.mask;
@@ -365,14 +368,16 @@ __device__ void run_chunk(const WalkArgs& A, const DevGraph& G, uint32_t ci,
 // kUniform: every chunk of the launch has R >= kUniformMinR (see run_chunk).
 // Eight waves per SIMD where the kernel fits 64 VGPRs without spilling.
 template <int kLayout, int kUniform, int kShare>
-__global__ __launch_bounds__(kBlockThreads,
-                             kShare == 1 && (kUniform || kLayout == kLayoutCompact) ? 8 : 1) void walk_kernel(
+__global__ __launch_bounds__(kBlockThreads, kShare == 1 && (kUniform || kLayout == kLayoutCompact ||
+                                                            kLayout == kLayoutCompactHub) ? 8 : 1) void walk_kernel(
     WalkArgs A)
 {
     __shared__ unsigned long long acc[kMaxChunkProbes * 4];
     __shared__ double ys[kMaxG];
     __shared__ uint32_t next;
-    const DevGraph G = make_graph(A.g);
+    __shared__ uint2 hub_lds[kLayout == kLayoutCompactHub ? kHubNodes + 1 : 1];
+    DevGraph G = make_graph(A.g);
+    stage_hubs<kLayout>(G, hub_lds);
     if (!A.persistent) {
         if (blockIdx.x < A.nchunks) run_chunk<kLayout, kUniform, kShare>(A, G, blockIdx.x, acc, ys);
         return;
@@ -427,6 +432,7 @@ static const void* walk_fn(int layout, int uniform, int share)
 {
     if (layout == kLayoutFat) return walk_fn_l<kLayoutFat>(uniform, share);
     if (layout == kLayoutCompact) return walk_fn_l<kLayoutCompact>(uniform, share);
+    if (layout == kLayoutCompactHub) return walk_fn_l<kLayoutCompactHub>(uniform, share);
     return walk_fn_l<kLayoutCsr>(uniform, share);
 }
 
@@ -447,6 +453,9 @@ hipError_t launch_walk(const WalkArgs& a, int layout, int uniform, int share, ui
     } else if (layout == kLayoutCompact) {
         if (uniform) launch_l<kLayoutCompact, 1>(a, share, grid, st);
         else launch_l<kLayoutCompact, 0>(a, share, grid, st);
+    } else if (layout == kLayoutCompactHub) {
+        if (uniform) launch_l<kLayoutCompactHub, 1>(a, share, grid, st);
+        else launch_l<kLayoutCompactHub, 0>(a, share, grid, st);
     } else {
         if (uniform) launch_l<kLayoutCsr, 1>(a, share, grid, st);
         else launch_l<kLayoutCsr, 0>(a, share, grid, st);
@@ -541,6 +550,7 @@ hipError_t launch_trace(const GraphTables& g, int layout, uint32_t count, const 
 #define PW_TRACE(Lay) hipLaunchKernelGGL(trace_kernel<Lay>, dim3(blocks), dim3(128), 0, st, g, count, start, uid, k, p, side, L, slo, shi, trace, acc)
     if (layout == kLayoutFat) PW_TRACE(1);
     else if (layout == kLayoutCompact) PW_TRACE(2);
+    else if (layout == kLayoutCompactHub) PW_TRACE(3);
     else PW_TRACE(0);
 #undef PW_TRACE
     return hipGetLastError();
@@ -582,7 +592,9 @@ template <int kLayout, int kChains>
 __global__ __launch_bounds__(kBlockThreads) void gather_kernel(GraphTables gt, int32_t steps, uint32_t seed,
                                                                uint32_t* sink)
 {
-    const DevGraph G = make_graph(gt);
+    __shared__ uint2 hub_lds[kLayout == kLayoutCompactHub ? kHubNodes + 1 : 1];
+    DevGraph G = make_graph(gt);
+    stage_hubs<kLayout>(G, hub_lds);
     const uint32_t gid = blockIdx.x * blockDim.x + threadIdx.x;
     WalkState w[kChains];
     uint32_t rng[kChains];
@@ -625,6 +637,7 @@ hipError_t launch_gather(const GraphTables& g, int layout, int chains, uint32_t 
     } while (0)
     if (layout == kLayoutFat) PW_GATHER_C(1);
     else if (layout == kLayoutCompact) PW_GATHER_C(2);
+    else if (layout == kLayoutCompactHub) PW_GATHER_C(3);
     else PW_GATHER_C(0);
 #undef PW_GATHER_C
 #undef PW_GATHER

@@ -62,7 +62,8 @@ def test_device_info():
 
 
 @pytest.mark.parametrize("layout,code", [(B.BD_LAYOUT_CSR, 0), (B.BD_LAYOUT_FAT, 1),
-                                         (B.BD_LAYOUT_FAT | B.BD_RELABEL_DEGREE, 1), (B.BD_LAYOUT_COMPACT, 2)])
+                                         (B.BD_LAYOUT_FAT | B.BD_RELABEL_DEGREE, 1), (B.BD_LAYOUT_COMPACT, 2),
+                                         (B.BD_LAYOUT_COMPACT | B.BD_RELABEL_DEGREE, 3)])
 def test_graph_info(ba1k, layout, code):
     gi = load(ba1k, layout).info()
     assert gi["n"] == ba1k.n and gi["nnz"] == ba1k.nnz
@@ -90,7 +91,7 @@ def test_probe_parity(name):
 
 
 LAYOUTS = [B.BD_LAYOUT_CSR, B.BD_LAYOUT_FAT, B.BD_LAYOUT_CSR | B.BD_RELABEL_DEGREE,
-           B.BD_LAYOUT_FAT | B.BD_RELABEL_DEGREE, B.BD_LAYOUT_COMPACT]
+           B.BD_LAYOUT_FAT | B.BD_RELABEL_DEGREE, B.BD_LAYOUT_COMPACT, B.BD_LAYOUT_COMPACT | B.BD_RELABEL_DEGREE]
 
 
 @pytest.mark.parametrize("layout", LAYOUTS)
@@ -264,7 +265,7 @@ def test_alone_equals_in_batch(ba1k):
     assert not np.array_equal(other["beta"], full["beta"])
 
 
-@pytest.mark.parametrize("layout", [B.BD_LAYOUT_COMPACT, B.BD_LAYOUT_FAT])
+@pytest.mark.parametrize("layout", [B.BD_LAYOUT_COMPACT, B.BD_LAYOUT_FAT, B.BD_LAYOUT_COMPACT | B.BD_RELABEL_DEGREE])
 def test_full_size_sampled_parity(cl100k, layout):
     # Bench shape: Chung-Lu n=1e5, L = 1000, eps = 0.05; per-probe Q checked on
     # sampled probes (the oracle runs R walk pairs of 1000 steps per probe).

@@ -20,7 +20,8 @@ from synth import graphs, queries
 pytestmark = pytest.mark.gpu
 
 SEED = graphs.PHILOX_SEED
-LAYOUTS = [B.BD_LAYOUT_COMPACT, B.BD_LAYOUT_CSR | B.BD_RELABEL_DEGREE, B.BD_LAYOUT_FAT]
+LAYOUTS = [B.BD_LAYOUT_COMPACT, B.BD_LAYOUT_CSR | B.BD_RELABEL_DEGREE, B.BD_LAYOUT_FAT,
+           B.BD_LAYOUT_COMPACT | B.BD_RELABEL_DEGREE]
 
 _cache = {}
 
