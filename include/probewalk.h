@@ -233,7 +233,7 @@ int bd_query_stabilized(bd_graph* g, int64_t nq, const int32_t* s, const int32_t
 /*
  * Autotuner: runs the (small, representative) sample batch once per candidate
  * execution configuration and returns the fastest by walk-kernel time in *best:
- * chunk_pairs in {256, 512, ..., 16384} with 8 chunk queues, then (BATCHED)
+ * chunk_pairs in {128, 256, ..., 16384} with 8 chunk queues, then (BATCHED)
  * the best of those with 1 queue. times_ms (host, may be NULL) receives the
  * kernel time of each of the n_candidates (<= 16) candidates in that order;
  * *n_candidates is set to the count.

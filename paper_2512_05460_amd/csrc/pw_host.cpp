@@ -1138,7 +1138,7 @@ extern "C" int bd_autotune(bd_graph* g, int64_t nq, const int32_t* s, const int3
                            bd_exec* best, double* times_ms, int32_t* n_candidates)
 {
     if (!g || !best || nq < 1 || !s || !t || !eps || !L) return BD_E_INVALID;
-    const int32_t cands[7] = {256, 512, 1024, 2048, 4096, 8192, 16384};
+    const int32_t cands[8] = {128, 256, 512, 1024, 2048, 4096, 8192, 16384};
     std::vector<bd_result> res((size_t)nq);
     double best_ms = 1e300;
     int n = 0;
@@ -1154,7 +1154,7 @@ extern "C" int bd_autotune(bd_graph* g, int64_t nq, const int32_t* s, const int3
         }
         return BD_OK;
     };
-    for (int i = 0; i < 7; ++i) {
+    for (int i = 0; i < 8; ++i) {
         bd_exec ex{};
         ex.mode = mode;
         ex.chunk_pairs = mode == BD_MODE_PLAIN ? std::max(cands[i] / 16, 64) : cands[i];

@@ -202,7 +202,7 @@ def test_autotune():
     pol = B.policy("scaled", c_B=0.05, c_R=0.05)
     best, times = B.bd_autotune(dg, s, t, 0.3, 100, SEED, pol, "batched")
     _say(f"[autotune] best chunk_pairs={best.chunk_pairs} queues={best.queues} times={np.round(times, 2)}")
-    assert len(times) == 8 and best.chunk_pairs in (256, 512, 1024, 2048, 4096, 8192, 16384)
+    assert len(times) == 9 and best.chunk_pairs in (128, 256, 512, 1024, 2048, 4096, 8192, 16384)
     assert best.queues in (1, 8)
     a = B.bd_query_batch(dg, s, t, 0.3, 100, SEED, pol, best)
     b = B.bd_query_batch(dg, s, t, 0.3, 100, SEED, pol)
