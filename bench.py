@@ -205,7 +205,7 @@ def grid_batched(B, torch, stream, plain_sample=512):
     }
 
 
-def served_cl10m(B, torch, seconds_per_load=10.0):
+def served_cl10m(B, torch, seconds_per_load=20.0):
     """Continuous batching under Poisson arrivals: Chung-Lu n=10^7 (mean degree
     10, exponent 2.3, largest component, compact layout resident on the
     device); request batches of 2^U uniform pairs (U uniform on 0..12, 1 to
