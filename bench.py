@@ -207,13 +207,14 @@ def grid_batched(B, torch, stream, plain_sample=512):
 
 def served_cl10m(B, torch, seconds_per_load=20.0):
     """Continuous batching under Poisson arrivals: Chung-Lu n=10^7 (mean degree
-    10, exponent 2.3, largest component, compact layout resident on the
-    device); request batches of 2^U uniform pairs (U uniform on 0..12, 1 to
-    4,096 pairs), eps per query from {0.02, 0.05, 0.1}, L=1000, throughput walk
-    counts. Capacity comes from a burst of requests submitted at once; then
-    Poisson arrivals at 50%, 80% and 95% of it, each for `seconds_per_load`
-    seconds of arrivals. Latency is per request, from submission to completion
-    as the server records it."""
+    10, exponent 2.3, largest component, compact layout with hubs first
+    resident on the device); request batches of 2^U uniform pairs (U uniform
+    on 0..12, 1 to 4,096 pairs), eps per query from {0.02, 0.05, 0.1}, L=1000,
+    throughput walk counts. Capacity comes from a burst of requests submitted
+    at once; then Poisson arrivals at 50%, 80% and 95% of it, each for
+    `seconds_per_load` seconds of arrivals. Latency is per request, from
+    submission to completion as the server records it. Last, one set at
+    eps = 0.05, L = 1000 in the plain, batched and served modes."""
     from paper_2512_05460_amd.budgets import BUDGETS, budget_policy
     from synth import graphs, queries
 
@@ -279,6 +280,39 @@ def served_cl10m(B, torch, seconds_per_load=20.0):
                                             "p99": float(np.percentile(lat, 99)), "max": float(lat.max())},
                              "latency_ms_requests_le_64": float(np.percentile(lat[sizes <= 64], 50))
                              if np.any(sizes <= 64) else None})
+    # The three modes on one set at eps = 0.05, L = 1000 (4,096 uniform pairs):
+    # the served requests are 16 of 256 pairs submitted together; the plain
+    # mode (one query per launch) runs the first 256 queries.
+    log("served: plain / batched / served at eps=0.05, L=1000")
+    s5, t5 = queries.uniform_pairs(g.n, 4096, base + 0x5005)
+    r_b, _ = B.bd_query_batch(dg, s5, t5, 0.05, Lq, seed, pol, B.exec_cfg("batched"), with_stats=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r_b = B.bd_query_batch(dg, s5, t5, 0.05, Lq, seed, pol, B.exec_cfg("batched"))
+    torch.cuda.synchronize()
+    dt_b = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    rids = [srv.submit(s5[j:j + 256], t5[j:j + 256], 0.05, Lq, seed, uid=np.arange(j, j + 256))
+            for j in range(0, 4096, 256)]
+    for k, rid in enumerate(rids):
+        o, _ = srv.wait(rid)
+        assert np.array_equal(o["beta"], r_b["beta"][256 * k:256 * k + 256])
+    dt_s = time.perf_counter() - t0
+    plain = B.exec_cfg("plain")
+    t0 = time.perf_counter()
+    for i in range(256):
+        o = B.bd_query_batch(dg, s5[i:i + 1], t5[i:i + 1], 0.05, Lq, seed, pol, plain, uid=[i])
+        assert o["beta"][0] == r_b["beta"][i]
+    torch.cuda.synchronize()
+    dt_p = time.perf_counter() - t0
+    steps5 = B.bd_plan(dg, s5, t5, 0.05, Lq, pol)["walk_steps"].astype(float)
+    out["modes_eps005_L1000"] = {
+        "queries": 4096, "walk_steps_per_query_mean": float(steps5.mean()),
+        "plain_queries_per_s": 256 / dt_p, "batched_queries_per_s": 4096 / dt_b,
+        "served_queries_per_s": 4096 / dt_s,
+        "batched_vs_plain": (4096 / dt_b) / (256 / dt_p), "served_vs_plain": (4096 / dt_s) / (256 / dt_p),
+        "plain_walk_steps_per_s": float(steps5[:256].sum()) / dt_p,
+        "batched_walk_steps_per_s": float(steps5.sum()) / dt_b}
     srv.destroy()
     dg.free()
     return out
