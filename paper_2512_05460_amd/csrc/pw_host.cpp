@@ -731,9 +731,11 @@ int run_batch(bd_graph* g, const Batch& b, const bd_exec& ex, hipStream_t user_s
     } else {
         // key: everything the captured launches depend on
         std::vector<uint64_t> key = {nv, b.chunks.size(), b.n_uniform, b.split_probes, gdim, grids[0],
-                                           grids[1], (uint64_t)layout, (uint64_t)(uintptr_t)w.qd.p,
-                                           (uint64_t)(uintptr_t)w.chunks.p, (uint64_t)(uintptr_t)w.bs.p,
-                                           (uint64_t)(uintptr_t)w.psum.p, b.nqueues};
+                                     grids[1], (uint64_t)layout, (uint64_t)b.share, b.nqueues,
+                                     (uint64_t)(uintptr_t)w.qd.p, (uint64_t)(uintptr_t)w.chunks.p,
+                                     (uint64_t)(uintptr_t)w.bs.p, (uint64_t)(uintptr_t)w.psum.p,
+                                     (uint64_t)(uintptr_t)w.pcount.p, (uint64_t)(uintptr_t)w.done.p,
+                                     (uint64_t)(uintptr_t)w.beta.p, (uint64_t)(uintptr_t)w.cursor.p};
         for (int part = 0; part < 2; ++part)
             for (uint32_t i = 0; i <= b.nqueues; ++i) key.push_back(b.qoff[part][i]);
         if (!w.gexec || w.gkey != key) {

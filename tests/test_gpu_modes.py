@@ -194,6 +194,12 @@ def test_graph_replay_matches_eager():
         assert np.array_equal(got["beta"], ref["beta"]), rep
         again = B.bd_query_batch(dg, s, t, eps, L, seed, pol, ex_graph, uid=uid)
         assert np.array_equal(again["beta"], ref["beta"]), rep
+    # alternating walk-sharing factors on one batch: each replay matches eager
+    for M in (1, 2, 4, 1, 4):
+        pm = B.policy("fixed", B=4, R=64, share=M)
+        got = B.bd_query_batch(dg, s, t, eps, L, SEED, pm, ex_graph)
+        ref = B.bd_query_batch(dg, s, t, eps, L, SEED, pm, ex_eager)
+        assert np.array_equal(got["beta"], ref["beta"]), M
 
 
 def test_autotune():
