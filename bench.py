@@ -396,6 +396,7 @@ def main():
     ap.add_argument("--no-small", action="store_true")
     ap.add_argument("--no-grid", action="store_true")
     ap.add_argument("--no-sharing", action="store_true")
+    ap.add_argument("--no-stabilize", action="store_true")
     ap.add_argument("--scale", action="store_true",
                     help="also run the Chung-Lu n=4e7 workload (about 3 minutes more)")
     ap.add_argument("--no-served-cl10m", action="store_true")
@@ -517,6 +518,21 @@ def main():
             "queries_per_s": nq / dts, "vs_plain": (nq / dts) / qps,
             "walk_steps_per_s": float(splan["walk_steps"].sum()) / dts,
             "kernel_walk_steps_per_s": float(splan["walk_steps"].sum()) / (kms_sh / 1e3)}
+    if not args.no_stabilize:
+        # the stabilization rule (section 4.3) and its proxy relative error
+        # against the estimate at L_max = 256, eps = 0.1, on the same graph
+        log("stabilization rule, 32 pairs, eps=0.1, L_max=256")
+        s_st, t_st = s_all[-32:], t_all[-32:]
+        t1 = time.perf_counter()
+        r_st, Ls = B.bd_query_stabilized(dg, s_st, t_st, 0.1, 256, seed, pol)
+        dt_st = time.perf_counter() - t1
+        r_mx = B.bd_query_batch(dg, s_st, t_st, 0.1, 256, seed, pol)
+        proxy = np.abs(r_st["beta"] - r_mx["beta"]) / np.abs(r_mx["beta"])
+        extra["stabilization"] = {
+            "eps": 0.1, "L_max": 256, "queries": 32, "seconds": dt_st,
+            "L_stop_counts": {str(int(v)): int((Ls == v).sum()) for v in np.unique(Ls)},
+            "proxy_rel_error": {"p50": float(np.median(proxy)), "p90": float(np.percentile(proxy, 90)),
+                                "max": float(proxy.max()), "frac_within_eps": float((proxy <= 0.1).mean())}}
     if not args.no_small:
         extra["small_queries"] = small_queries(B, torch, stream)
     if not args.no_grid:

@@ -264,3 +264,23 @@ def test_stabilized_matches_oracle():
     for i in range(6):
         ob, oL = OS.stabilized(g, int(s[i]), int(t[i]), 0.3, 64, SEED, i, opol)
         assert Ls[i] == oL and res["beta"][i] == ob, (i, Ls[i], oL)
+
+
+@pytest.mark.timeout(300)
+def test_stabilization_proxy_error():
+    # Section 4.3's check of the rule: relative gap between the estimate at
+    # L_stop and the estimate at L_max = 256, here on the Chung-Lu n=1e5 graph
+    # at eps = 0.1 with its calibrated walk counts
+    from paper_2512_05460_amd.budgets import budget_policy
+    g, dg = _graph("cl100k", B.BD_LAYOUT_COMPACT | B.BD_RELABEL_DEGREE)
+    s, t = queries.uniform_pairs(g.n, 24, 515)
+    pol = budget_policy("cl100k")
+    eps = 0.1
+    res, Ls = B.bd_query_stabilized(dg, s, t, eps, 256, SEED, pol)
+    ref = B.bd_query_batch(dg, s, t, eps, 256, SEED, pol)
+    assert np.all(res["status"] == 0) and np.all(ref["status"] == 0)
+    assert np.all((Ls >= 2) & (Ls <= 256)) and np.all((Ls & (Ls - 1)) == 0)
+    proxy = np.abs(res["beta"] - ref["beta"]) / np.abs(ref["beta"])
+    _say(f"[stabilize] L_stop {np.bincount(np.log2(Ls).astype(int)).tolist()}, proxy error median "
+         f"{np.median(proxy):.4f}, max {proxy.max():.4f}, within eps {(proxy <= eps).mean():.3f}")
+    assert np.median(proxy) <= eps
