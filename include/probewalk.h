@@ -24,6 +24,15 @@
  *     traffic it runs in.
  *   - Limits: 2 <= n <= 2^30, nnz < 2^31, max degree < 2^24, L <= 16383,
  *     K and R < 2^32.
+ *   - Threads: calls on different graphs may run concurrently. Calls that run
+ *     work on one graph (queries, traces, bd_truncated_beta, bd_graph_lambda)
+ *     take that graph's lock and run one at a time, since they share its
+ *     work buffers; a server on the graph has buffers of its own and runs
+ *     beside them. graph_free must not race with any other call on the graph.
+ *   - Walk sharing (bd_policy.share > 1) is an extension of Algorithm 1;
+ *     every other result follows the algorithm as the paper states it, with
+ *     the readings fixed where the paper leaves freedom written out in the
+ *     oracle's sources.
  */
 #ifndef PROBEWALK_H
 #define PROBEWALK_H
@@ -41,7 +50,8 @@ extern "C" {
                              eps outside (0,1), L < 0 or L > 16383 */
 #define BD_E_GRAPH    -2  /* graph is not simple, symmetric, sorted and connected */
 #define BD_E_RANGE    -3  /* n, nnz or a degree beyond the limits above */
-#define BD_E_BUDGET   -4  /* per query: 2*K*R*L above the policy cap, or K, R >= 2^32 */
+#define BD_E_BUDGET   -4  /* per query: walk steps (2*K*R*L without walk sharing) above the
+                             policy cap, or K, R >= 2^32 */
 #define BD_E_HIP      -5  /* a HIP runtime call failed */
 #define BD_E_NOMEM    -6  /* device or host allocation failed */
 #define BD_E_NODEVICE -7  /* no usable gfx950 device */
