@@ -24,11 +24,12 @@
  *     traffic it runs in.
  *   - Limits: 2 <= n <= 2^30, nnz < 2^31, max degree < 2^24, L <= 16383,
  *     K and R < 2^32.
- *   - Threads: calls on different graphs may run concurrently. Calls that run
- *     work on one graph (queries, traces, bd_truncated_beta, bd_graph_lambda)
- *     take that graph's lock and run one at a time, since they share its
- *     work buffers; a server on the graph has buffers of its own and runs
- *     beside them. graph_free must not race with any other call on the graph.
+ *   - Threads: calls on different graphs may run concurrently. The calls that
+ *     use a graph's work buffers (bd_query_batch, bd_query_probes,
+ *     bd_query_stabilized, bd_autotune, bd_truncated_beta, bd_graph_lambda)
+ *     take that graph's lock and run one at a time; the validation entry
+ *     points and servers have buffers of their own and run beside them.
+ *     graph_free must not race with any other call on the graph.
  *   - Walk sharing (bd_policy.share > 1) is an extension of Algorithm 1;
  *     every other result follows the algorithm as the paper states it, with
  *     the readings fixed where the paper leaves freedom written out in the
