@@ -252,9 +252,11 @@ def served_cl10m(B, torch, seconds_per_load=20.0):
                                                                  "seconds": dt},
            "loads": []}
     for li, f in enumerate((0.5, 0.8, 0.95)):
-        rate = f * cap_qps / mean_size
-        count = max(8, int(round(rate * seconds_per_load)))
+        count = max(8, int(round(f * cap_qps / mean_size * seconds_per_load)))
         reqs = queries.served_requests(g.n, count, base + 1000 * (li + 1))
+        # the arrival rate is set from the drawn request sizes, so that the
+        # offered queries/s is exactly f times the capacity whatever the draw
+        rate = count * f * cap_qps / sum(x[0].size for x in reqs)
         arr = queries.poisson_arrivals(count, rate, base + 1000 * (li + 1) + 1)
         log(f"served: offered load {f:.0%} of capacity, {count} requests at {rate:.2f}/s")
         start = time.perf_counter()
@@ -274,7 +276,8 @@ def served_cl10m(B, torch, seconds_per_load=20.0):
         end = max(sub[i] + lat[i] / 1e3 for i in range(count))
         nq = sum(x[0].size for x in reqs)
         sizes = np.array([x[0].size for x in reqs])
-        out["loads"].append({"offered_fraction": f, "offered_requests_per_s": rate, "requests": count,
+        out["loads"].append({"offered_fraction": f, "offered_queries_per_s": f * cap_qps,
+                             "offered_requests_per_s": rate, "requests": count,
                              "queries": int(nq), "queries_per_s": nq / end,
                              "latency_ms": {"p50": float(np.percentile(lat, 50)),
                                             "p99": float(np.percentile(lat, 99)), "max": float(lat.max())},
