@@ -92,8 +92,15 @@ def cpu_baseline(g, s, t, plans, seed, target_s=20.0):
     steps = float((kend * per_probe).sum())
     full = np.array([2.0 * p[2] * p[3] * L for p in plans])
     sps = steps / dt
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": sps / full.mean(), "unit": "queries/s", "cores": threads, "kind": "oracle",
-            "walk_steps_per_s": sps,
+            "cpu_model": model, "walk_steps_per_s": sps, "walk_steps_per_s_per_core": sps / threads,
+            "single_thread_seconds_per_query": full.mean() / (sps / threads),
             "sample": (f"{threads} of the step's queries, first {int(kend.min())}-{int(kend.max())} of their "
                        f"probes each at full R and L, one query per thread; {steps:.3e} walk steps in "
                        f"{dt:.1f} s; queries/s = steps/s / mean full-query steps of the batch")}
@@ -612,6 +619,10 @@ def main():
             "gather_roofline": roof,
         },
         "cpu_baseline": cpu,
+        "paper_context": ("per-query times of the same estimator in the paper (Table 3): one thread of an "
+                          "AMD EPYC 7713, Python, eps=0.01, L by the stabilization rule; median 1.4 s / 9.9 s / "
+                          "9.4 s and mean 34 s / 55 s / 301 s on Bluesky, Twitter-2010, Friendster (other graphs "
+                          "and unstated walk counts: context, not a baseline)"),
         "device": dev,
         **extra,
     }
