@@ -330,11 +330,12 @@ def served_cl10m(B, torch, seconds_per_load=20.0):
 
 def scale_cl40m(B, torch, stream, served_queries=65536):
     """The scale workload: Chung-Lu n=4*10^7 (mean degree 25, exponent 2.2,
-    largest component, about 10^9 adjacency entries; native generator), CSR
-    layout with hubs stored first; the 262,144 queries (eps = 0.05, L over
-    {1000, 10000}) in one persistent launch, then the first `served_queries`
-    of them as requests of 4,096 submitted together to the server;
-    throughput walk counts."""
+    largest component, about 10^9 adjacency entries; native generator); the
+    262,144 queries (eps = 0.05, L over {1000, 10000}) in one persistent launch
+    on the CSR layout and on the compact layout with hubs first (4-byte ids at
+    this size), then on the latter the first `served_queries` of them as
+    requests of 4,096 submitted together to the server; throughput walk
+    counts."""
     from paper_2512_05460_amd.budgets import BUDGETS, budget_policy
     from synth import graphs, queries
 
@@ -342,22 +343,38 @@ def scale_cl40m(B, torch, stream, served_queries=65536):
     t0 = time.perf_counter()
     g = graphs.workload_graph("cl40m")
     t_gen = time.perf_counter() - t0
-    log(f"scale: n={g.n} nnz={g.nnz} in {t_gen:.0f} s; loading")
-    t0 = time.perf_counter()
-    dg = B.graph_load_csr(g.n, g.row_ptr, g.col, B.BD_LAYOUT_CSR | B.BD_RELABEL_DEGREE)
-    t_load = time.perf_counter() - t0
     s, t, eps, Ls = queries.workload_batch("cl40m", g.n)
     pol = budget_policy("cl40m")
     seed = graphs.PHILOX_SEED
-    plan = B.bd_plan(dg, s, t, eps, Ls, pol)
-    steps = float(plan["walk_steps"].sum())
-    log(f"scale: {s.size} queries, {steps:.3e} walk steps, batched")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    r, st = B.bd_query_batch(dg, s, t, eps, Ls, seed, pol, B.exec_cfg("batched"), stream=stream, with_stats=True)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    assert np.all(r["status"] == 0)
+    layouts = {}
+    r = dg = None
+    # CSR (16-byte node entries) first, then the compact layout with hubs
+    # first (8-byte entries, 4-byte ids above 2^24 nodes, hubs in LDS), which
+    # also runs the served part
+    for name, flags in (("csr, hubs first", B.BD_LAYOUT_CSR | B.BD_RELABEL_DEGREE),
+                        ("compact, hubs first", B.BD_LAYOUT_COMPACT | B.BD_RELABEL_DEGREE)):
+        if dg is not None:
+            dg.free()
+        log(f"scale: n={g.n} nnz={g.nnz}; loading ({name})")
+        t0 = time.perf_counter()
+        dg = B.graph_load_csr(g.n, g.row_ptr, g.col, flags)
+        t_load = time.perf_counter() - t0
+        plan = B.bd_plan(dg, s, t, eps, Ls, pol)
+        steps = float(plan["walk_steps"].sum())
+        log(f"scale: {s.size} queries, {steps:.3e} walk steps, batched ({name})")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r, st = B.bd_query_batch(dg, s, t, eps, Ls, seed, pol, B.exec_cfg("batched"), stream=stream,
+                                 with_stats=True)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        assert np.all(r["status"] == 0)
+        roof = max((B.bd_gather_roofline(dg, c, 1000) for c in (2, 4, 8)), key=lambda x: x["steps_per_s"])
+        layouts[name] = {"device_bytes": dg.info()["device_bytes"], "load_s": t_load,
+                         "batched_queries_per_s": s.size / dt, "batched_walk_steps_per_s": steps / dt,
+                         "kernel_walk_steps_per_s": steps / (st["walk_kernel_ms"] / 1e3),
+                         "gather_roofline_steps_per_s": roof["steps_per_s"],
+                         "gather_roofline_frac": steps / (st["walk_kernel_ms"] / 1e3) / roof["steps_per_s"]}
     m = served_queries
     srv = B.Server(dg, pol)
     log(f"scale: served, {m} queries as requests of 4096")
@@ -372,21 +389,18 @@ def scale_cl40m(B, torch, stream, served_queries=65536):
     dts = time.perf_counter() - t0
     srv.destroy()
     steps_m = float(plan["walk_steps"][:m].sum())
-    roof = max((B.bd_gather_roofline(dg, c, 1000) for c in (2, 4, 8)), key=lambda x: x["steps_per_s"])
-    info = dg.info()
     dg.free()
     c_B, c_R, how = BUDGETS["cl40m"]
+    best = layouts["compact, hubs first"]
     return {
         "workload": ("Chung-Lu n=40,000,000 mean degree 25 exponent 2.2 LCC; 262,144 uniform pairs; eps=0.05; "
                      "L over {1000, 10000}"),
-        "graph": {"n": g.n, "nnz": g.nnz, "layout": "csr, hubs first", "device_bytes": info["device_bytes"],
-                  "generate_s": t_gen, "load_s": t_load},
+        "graph": {"n": g.n, "nnz": g.nnz, "generate_s": t_gen},
         "policy": {"kind": "scaled", "c_B": c_B, "c_R": c_R, "calibration": how},
         "walk_steps": steps,
-        "batched_queries_per_s": s.size / dt, "batched_walk_steps_per_s": steps / dt,
-        "kernel_walk_steps_per_s": steps / (st["walk_kernel_ms"] / 1e3),
-        "gather_roofline_steps_per_s": roof["steps_per_s"],
-        "gather_roofline_frac": steps / (st["walk_kernel_ms"] / 1e3) / roof["steps_per_s"],
+        "layouts": layouts,
+        "batched_queries_per_s": best["batched_queries_per_s"],
+        "batched_walk_steps_per_s": best["batched_walk_steps_per_s"],
         "served_queries": m, "served_queries_per_s": m / dts, "served_walk_steps_per_s": steps_m / dts,
         "served_request_latency_ms": {"p50": float(np.percentile(lat, 50)), "max": float(max(lat))},
     }

@@ -79,14 +79,18 @@ typedef struct bd_graph bd_graph;
                                    BD_LAYOUT_FAT). With BD_RELABEL_DEGREE: 8-byte node
                                    entries {row offset, original id} in descending-degree
                                    order, the 1024 highest-degree ones staged in LDS by
-                                   every work group (layout code 3) */
+                                   every work group (layout code 3); above 2^24 nodes the
+                                   neighbour ids take 4 bytes (layout code 4) */
+#define BD_WIDE_IDS        16u  /* with BD_LAYOUT_COMPACT | BD_RELABEL_DEGREE: 4-byte
+                                   neighbour ids (layout code 4) at any n */
 
 typedef struct {
     int64_t  n, nnz;
     int32_t  d_min, d_max;
     int32_t  bipartite;      /* 1 if the graph is bipartite (section 2.1 assumes not;
                                 the estimator still targets beta^(L)) */
-    int32_t  layout;         /* 0 CSR, 1 fat, 2 compact, 3 compact with hubs first */
+    int32_t  layout;         /* 0 CSR, 1 fat, 2 compact, 3 compact with hubs first,
+                                4 hubs first with 4-byte neighbour ids */
     int64_t  device_bytes;   /* device memory held by the graph tables */
 } bd_graph_info;
 

@@ -172,12 +172,13 @@ __device__ __forceinline__ int probe_value(uint32_t x, const Probe& pr, const Do
 // entries {row offset, original id} (8 bytes; entry n = {nnz, 0}), neighbour
 // storage ids packed in 3 bytes; the entries of the first kHubNodes storage ids
 // (the highest-degree nodes, which the walks visit most) are staged in LDS.
-constexpr int kLayoutCsr = 0, kLayoutFat = 1, kLayoutCompact = 2, kLayoutCompactHub = 3;
+// Above 2^24 nodes the same layout keeps 4-byte neighbour storage ids.
+constexpr int kLayoutCsr = 0, kLayoutFat = 1, kLayoutCompact = 2, kLayoutCompactHub = 3, kLayoutHub32 = 4;
 constexpr uint32_t kHubNodes = 1024;
 
 struct DevGraph {
     const uint4* node;      // n entries (CSR and fat layouts)
-    const uint32_t* col;    // nnz entries (CSR layout)
+    const uint32_t* col;    // nnz entries (CSR layout; hubs-first layout above 2^24 nodes)
     const uint4* adj;       // nnz entries (fat layout)
     const uint32_t* rp;     // n + 1 entries (compact layout)
     const uint32_t* col24;  // 3 nnz bytes + padding, read as aligned words (compact layouts)
@@ -235,7 +236,7 @@ __device__ __forceinline__ WalkState start_at(const DevGraph& G, uint32_t x)
         compact_row(G, x, w);
         return w;
     }
-    if (kLayout == kLayoutCompactHub) {
+    if (kLayout == kLayoutCompactHub || kLayout == kLayoutHub32) {
         WalkState w;
         hub_row(G, x, w);
         return w;
@@ -264,6 +265,8 @@ __device__ __forceinline__ void step(WalkState& w, uint32_t u, const DevGraph& G
         const uint32_t x = __builtin_amdgcn_alignbit(hi, lo, (o & 3u) * 8u) & 0xFFFFFFu;
         if (kLayout == kLayoutCompact) compact_row(G, x, w);
         else hub_row(G, x, w);
+    } else if (kLayout == kLayoutHub32) {
+        hub_row(G, G.col[pos], w);
     } else {
         const uint4 e = G.node[G.col[pos]];
         w.x = e.w;
@@ -278,7 +281,7 @@ __device__ __forceinline__ void step(WalkState& w, uint32_t u, const DevGraph& G
 template <int kLayout>
 __device__ __forceinline__ void stage_hubs(DevGraph& G, uint2* lds)
 {
-    if constexpr (kLayout == kLayoutCompactHub) {
+    if constexpr (kLayout == kLayoutCompactHub || kLayout == kLayoutHub32) {
         const uint32_t nh = min(kHubNodes, G.dom.n);
         for (uint32_t i = threadIdx.x; i <= nh; i += blockDim.x) lds[i] = G.node8[i];
         __syncthreads();

@@ -203,9 +203,12 @@ extern "C" int graph_load_csr(int64_t n, const int64_t* row_ptr, const int32_t* 
         dmax = std::max<int32_t>(dmax, (int32_t)d);
     }
     if (dmin < 1) return BD_E_GRAPH;  // an isolated node: not connected
+    // compact layouts: 3-byte ids up to 2^24 nodes; hubs first keeps 4-byte ids above that
+    const bool wide = (flags & BD_LAYOUT_COMPACT) && (flags & BD_RELABEL_DEGREE) &&
+                      (n > (int64_t(1) << 24) || (flags & BD_WIDE_IDS));
     if (flags & BD_LAYOUT_COMPACT) {
         if (flags & BD_LAYOUT_FAT) return BD_E_INVALID;
-        if (n > (int64_t(1) << 24) || 3 * nnz + 8 > (int64_t)UINT32_MAX) return BD_E_RANGE;
+        if (!wide && (n > (int64_t(1) << 24) || 3 * nnz + 8 > (int64_t)UINT32_MAX)) return BD_E_RANGE;
     }
     for (int64_t i = 0; i < nnz; ++i)
         if (col_idx[i] < 0 || col_idx[i] >= n) return BD_E_GRAPH;
@@ -228,7 +231,8 @@ extern "C" int graph_load_csr(int64_t n, const int64_t* row_ptr, const int32_t* 
     g->d_min = dmin;
     g->d_max = dmax;
     g->bipartite = bip;
-    g->layout = (flags & BD_LAYOUT_COMPACT) ? ((flags & BD_RELABEL_DEGREE) ? 3 : 2) : (flags & BD_LAYOUT_FAT) ? 1 : 0;
+    g->layout = (flags & BD_LAYOUT_COMPACT) ? (wide ? 4 : (flags & BD_RELABEL_DEGREE) ? 3 : 2)
+                                            : (flags & BD_LAYOUT_FAT) ? 1 : 0;
     g->device = dev;
     g->dom = make_domain((uint32_t)n);
     g->deg.resize((size_t)n);
@@ -272,22 +276,27 @@ extern "C" int graph_load_csr(int64_t n, const int64_t* row_ptr, const int32_t* 
     std::vector<uint32_t> rp32, packed;
     if (g->layout >= 2) {
         // compact: 32-bit row offsets (storage order), 3-byte neighbour storage ids
-        // (little endian), 8 bytes of padding; with hubs first also the node entries
-        // {row offset, original id}, entry n = {nnz, 0}
+        // (little endian) with 8 bytes of padding -- 4-byte ids above 2^24 nodes;
+        // with hubs first also the node entries {row offset, original id}, entry
+        // n = {nnz, 0}
+        const bool packed_ids = g->layout != 4;
+        const bool hubs = g->layout >= 3;
         rp32.resize((size_t)n + 1);
         for (int64_t i = 0; i < n; ++i) rp32[(size_t)i] = nodetab[(size_t)i * 4];
         rp32[(size_t)n] = (uint32_t)nnz;
-        const size_t bytes = (size_t)(3 * nnz + 8);
-        packed.assign((bytes + 3) / 4, 0u);
-        uint8_t* b = reinterpret_cast<uint8_t*>(packed.data());
-        for (int64_t i = 0; i < nnz; ++i) {
-            const uint32_t v = (uint32_t)col_store[i];
-            b[3 * i + 0] = (uint8_t)v;
-            b[3 * i + 1] = (uint8_t)(v >> 8);
-            b[3 * i + 2] = (uint8_t)(v >> 16);
+        if (packed_ids) {
+            const size_t bytes = (size_t)(3 * nnz + 8);
+            packed.assign((bytes + 3) / 4, 0u);
+            uint8_t* b = reinterpret_cast<uint8_t*>(packed.data());
+            for (int64_t i = 0; i < nnz; ++i) {
+                const uint32_t v = (uint32_t)col_store[i];
+                b[3 * i + 0] = (uint8_t)v;
+                b[3 * i + 1] = (uint8_t)(v >> 8);
+                b[3 * i + 2] = (uint8_t)(v >> 16);
+            }
         }
         std::vector<uint32_t> node8;
-        if (g->layout == 3) {
+        if (hubs) {
             node8.resize(2 * ((size_t)n + 1));
             for (int64_t i = 0; i < n; ++i) {
                 node8[2 * (size_t)i] = nodetab[(size_t)i * 4];
@@ -297,16 +306,20 @@ extern "C" int graph_load_csr(int64_t n, const int64_t* row_ptr, const int32_t* 
             node8[2 * (size_t)n + 1] = 0u;
         }
         rc = g->rp32.alloc(rp32.size() * 4);
-        if (rc == BD_OK) rc = g->col24.alloc(packed.size() * 4);
-        if (rc == BD_OK && g->layout == 3) rc = g->node8.alloc(node8.size() * 4);
+        if (rc == BD_OK && packed_ids) rc = g->col24.alloc(packed.size() * 4);
+        if (rc == BD_OK && !packed_ids) rc = g->col.alloc((size_t)std::max<int64_t>(nnz, 1) * 4);
+        if (rc == BD_OK && hubs) rc = g->node8.alloc(node8.size() * 4);
         if (rc != BD_OK) {
             delete g;
             return rc;
         }
         if (hipMemcpyAsync(g->rp32.p, rp32.data(), rp32.size() * 4, hipMemcpyHostToDevice, st) != hipSuccess ||
-            hipMemcpyAsync(g->col24.p, packed.data(), packed.size() * 4, hipMemcpyHostToDevice, st) != hipSuccess ||
-            (g->layout == 3 && hipMemcpyAsync(g->node8.p, node8.data(), node8.size() * 4, hipMemcpyHostToDevice,
-                                              st) != hipSuccess)) {
+            (packed_ids && hipMemcpyAsync(g->col24.p, packed.data(), packed.size() * 4, hipMemcpyHostToDevice,
+                                          st) != hipSuccess) ||
+            (!packed_ids && hipMemcpyAsync(g->col.p, col_store, (size_t)nnz * 4, hipMemcpyHostToDevice,
+                                           st) != hipSuccess) ||
+            (hubs && hipMemcpyAsync(g->node8.p, node8.data(), node8.size() * 4, hipMemcpyHostToDevice,
+                                    st) != hipSuccess)) {
             delete g;
             return BD_E_HIP;
         }
@@ -945,8 +958,9 @@ extern "C" int bd_truncated_beta(bd_graph* g, int64_t nq, const int32_t* s, cons
     hipStream_t st = (hipStream_t)stream;
     const uint32_t n = (uint32_t)g->n;
     const uint32_t* rp = g->rp32.as<const uint32_t>();
-    const uint32_t* col = g->layout >= 2 ? nullptr : g->col.as<const uint32_t>();
-    const uint32_t* col24 = g->layout >= 2 ? g->col24.as<const uint32_t>() : nullptr;
+    const bool packed_ids = g->layout == 2 || g->layout == 3;
+    const uint32_t* col = packed_ids ? nullptr : g->col.as<const uint32_t>();
+    const uint32_t* col24 = packed_ids ? g->col24.as<const uint32_t>() : nullptr;
     for (int64_t q0 = 0; q0 < nq; q0 += 64) {
         const uint32_t Q = (uint32_t)std::min<int64_t>(64, nq - q0);
         const size_t bytes = (size_t)n * Q * 8;
@@ -987,8 +1001,9 @@ extern "C" int bd_graph_lambda(bd_graph* g, int32_t iters, uint64_t seed, void* 
     hipStream_t st = (hipStream_t)stream;
     const uint32_t n = (uint32_t)g->n;
     const uint32_t* rp = g->rp32.as<const uint32_t>();
-    const uint32_t* col = g->layout >= 2 ? nullptr : g->col.as<const uint32_t>();
-    const uint32_t* col24 = g->layout >= 2 ? g->col24.as<const uint32_t>() : nullptr;
+    const bool packed_ids = g->layout == 2 || g->layout == 3;
+    const uint32_t* col = packed_ids ? nullptr : g->col.as<const uint32_t>();
+    const uint32_t* col24 = packed_ids ? g->col24.as<const uint32_t>() : nullptr;
     // phi = sqrt(d) / ||sqrt(d)|| in storage order; x0 from a seeded LCG, made orthogonal to phi
     std::vector<double> phi(n), x(n), y(n);
     double nrm = 0.0;

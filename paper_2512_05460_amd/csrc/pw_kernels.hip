@@ -369,13 +369,14 @@ __device__ void run_chunk(const WalkArgs& A, const DevGraph& G, uint32_t ci,
 // Eight waves per SIMD where the kernel fits 64 VGPRs without spilling.
 template <int kLayout, int kUniform, int kShare>
 __global__ __launch_bounds__(kBlockThreads, kShare == 1 && (kUniform || kLayout == kLayoutCompact ||
-                                                            kLayout == kLayoutCompactHub) ? 8 : 1) void walk_kernel(
+                                                            kLayout == kLayoutCompactHub ||
+                                                            kLayout == kLayoutHub32) ? 8 : 1) void walk_kernel(
     WalkArgs A)
 {
     __shared__ unsigned long long acc[kMaxChunkProbes * 4];
     __shared__ double ys[kMaxG];
     __shared__ uint32_t next;
-    __shared__ uint2 hub_lds[kLayout == kLayoutCompactHub ? kHubNodes + 1 : 1];
+    __shared__ uint2 hub_lds[kLayout == kLayoutCompactHub || kLayout == kLayoutHub32 ? kHubNodes + 1 : 1];
     DevGraph G = make_graph(A.g);
     stage_hubs<kLayout>(G, hub_lds);
     if (!A.persistent) {
@@ -433,6 +434,7 @@ static const void* walk_fn(int layout, int uniform, int share)
     if (layout == kLayoutFat) return walk_fn_l<kLayoutFat>(uniform, share);
     if (layout == kLayoutCompact) return walk_fn_l<kLayoutCompact>(uniform, share);
     if (layout == kLayoutCompactHub) return walk_fn_l<kLayoutCompactHub>(uniform, share);
+    if (layout == kLayoutHub32) return walk_fn_l<kLayoutHub32>(uniform, share);
     return walk_fn_l<kLayoutCsr>(uniform, share);
 }
 
@@ -456,6 +458,9 @@ hipError_t launch_walk(const WalkArgs& a, int layout, int uniform, int share, ui
     } else if (layout == kLayoutCompactHub) {
         if (uniform) launch_l<kLayoutCompactHub, 1>(a, share, grid, st);
         else launch_l<kLayoutCompactHub, 0>(a, share, grid, st);
+    } else if (layout == kLayoutHub32) {
+        if (uniform) launch_l<kLayoutHub32, 1>(a, share, grid, st);
+        else launch_l<kLayoutHub32, 0>(a, share, grid, st);
     } else {
         if (uniform) launch_l<kLayoutCsr, 1>(a, share, grid, st);
         else launch_l<kLayoutCsr, 0>(a, share, grid, st);
@@ -551,6 +556,7 @@ hipError_t launch_trace(const GraphTables& g, int layout, uint32_t count, const 
     if (layout == kLayoutFat) PW_TRACE(1);
     else if (layout == kLayoutCompact) PW_TRACE(2);
     else if (layout == kLayoutCompactHub) PW_TRACE(3);
+    else if (layout == kLayoutHub32) PW_TRACE(4);
     else PW_TRACE(0);
 #undef PW_TRACE
     return hipGetLastError();
@@ -592,7 +598,7 @@ template <int kLayout, int kChains>
 __global__ __launch_bounds__(kBlockThreads) void gather_kernel(GraphTables gt, int32_t steps, uint32_t seed,
                                                                uint32_t* sink)
 {
-    __shared__ uint2 hub_lds[kLayout == kLayoutCompactHub ? kHubNodes + 1 : 1];
+    __shared__ uint2 hub_lds[kLayout == kLayoutCompactHub || kLayout == kLayoutHub32 ? kHubNodes + 1 : 1];
     DevGraph G = make_graph(gt);
     stage_hubs<kLayout>(G, hub_lds);
     const uint32_t gid = blockIdx.x * blockDim.x + threadIdx.x;
@@ -638,6 +644,7 @@ hipError_t launch_gather(const GraphTables& g, int layout, int chains, uint32_t 
     if (layout == kLayoutFat) PW_GATHER_C(1);
     else if (layout == kLayoutCompact) PW_GATHER_C(2);
     else if (layout == kLayoutCompactHub) PW_GATHER_C(3);
+    else if (layout == kLayoutHub32) PW_GATHER_C(4);
     else PW_GATHER_C(0);
 #undef PW_GATHER_C
 #undef PW_GATHER

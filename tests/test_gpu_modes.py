@@ -164,6 +164,28 @@ def test_served_admission_caps_and_split():
         srv.destroy()
 
 
+def test_served_walk_step_admission():
+    # walk-budget admission: a request above the cap is refused; requests under
+    # it are admitted one at a time when together they exceed it
+    g, dg = _graph("ba1k", B.BD_LAYOUT_COMPACT)
+    pol = B.policy("fixed", B=2, R=64)
+    per_query = 2 * 74 * 64 * 40                      # K = 74, R = 64, L = 40
+    srv = B.Server(dg, pol, max_steps=3 * per_query)
+    try:
+        with pytest.raises(B.ProbeWalkError) as ei:
+            srv.submit(np.arange(4), np.arange(4) + 50, 0.1, 40, SEED)
+        assert ei.value.code == B.BD_E_FULL
+        reqs = [queries.uniform_pairs(g.n, 3, 900 + j) for j in range(4)]
+        rids = [srv.submit(s, t, 0.1, 40, SEED, uid=np.arange(3) + 10 * j) for j, (s, t) in enumerate(reqs)]
+        for j, rid in enumerate(rids):
+            out, _ = srv.wait(rid)
+            s, t = reqs[j]
+            ref = B.bd_query_batch(dg, s, t, 0.1, 40, SEED, pol, uid=np.arange(3) + 10 * j)
+            assert np.array_equal(out["beta"], ref["beta"])
+    finally:
+        srv.destroy()
+
+
 def test_served_destroy_with_pending_work():
     g, dg = _graph("ba1k", B.BD_LAYOUT_COMPACT)
     srv = B.Server(dg, B.policy("fixed", B=4, R=256), max_queries=2)

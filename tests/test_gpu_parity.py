@@ -63,7 +63,8 @@ def test_device_info():
 
 @pytest.mark.parametrize("layout,code", [(B.BD_LAYOUT_CSR, 0), (B.BD_LAYOUT_FAT, 1),
                                          (B.BD_LAYOUT_FAT | B.BD_RELABEL_DEGREE, 1), (B.BD_LAYOUT_COMPACT, 2),
-                                         (B.BD_LAYOUT_COMPACT | B.BD_RELABEL_DEGREE, 3)])
+                                         (B.BD_LAYOUT_COMPACT | B.BD_RELABEL_DEGREE, 3),
+                                         (B.BD_LAYOUT_COMPACT | B.BD_RELABEL_DEGREE | B.BD_WIDE_IDS, 4)])
 def test_graph_info(ba1k, layout, code):
     gi = load(ba1k, layout).info()
     assert gi["n"] == ba1k.n and gi["nnz"] == ba1k.nnz
@@ -91,7 +92,8 @@ def test_probe_parity(name):
 
 
 LAYOUTS = [B.BD_LAYOUT_CSR, B.BD_LAYOUT_FAT, B.BD_LAYOUT_CSR | B.BD_RELABEL_DEGREE,
-           B.BD_LAYOUT_FAT | B.BD_RELABEL_DEGREE, B.BD_LAYOUT_COMPACT, B.BD_LAYOUT_COMPACT | B.BD_RELABEL_DEGREE]
+           B.BD_LAYOUT_FAT | B.BD_RELABEL_DEGREE, B.BD_LAYOUT_COMPACT, B.BD_LAYOUT_COMPACT | B.BD_RELABEL_DEGREE,
+           B.BD_LAYOUT_COMPACT | B.BD_RELABEL_DEGREE | B.BD_WIDE_IDS]
 
 
 @pytest.mark.parametrize("layout", LAYOUTS)

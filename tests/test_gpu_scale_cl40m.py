@@ -1,6 +1,7 @@
 """The scale workload at full size: Chung-Lu n=4*10^7 (mean degree 25,
 exponent 2.2, largest component: 39,944,860 nodes, 996,486,866 adjacency
-entries) in the CSR layout, hubs stored first.
+entries) in the compact layout with hubs first, which above 2^24 nodes keeps
+4-byte neighbour ids.
 
 Queries of the workload's set (eps = 0.05, L in {1000, 10000}) in one
 persistent launch and through the server; sampled queries are checked bit for
@@ -32,8 +33,8 @@ def _say(*a):
 def cl40m():
     _say("[cl40m] building the graph (native generator)")
     g = graphs.workload_graph("cl40m")
-    _say(f"[cl40m] n={g.n} nnz={g.nnz}; loading (CSR, hubs first)")
-    dg = B.graph_load_csr(g.n, g.row_ptr, g.col, B.BD_LAYOUT_CSR | B.BD_RELABEL_DEGREE)
+    _say(f"[cl40m] n={g.n} nnz={g.nnz}; loading (hubs first)")
+    dg = B.graph_load_csr(g.n, g.row_ptr, g.col, B.BD_LAYOUT_COMPACT | B.BD_RELABEL_DEGREE)
     _say("[cl40m] loaded")
     yield g, dg
     dg.free()
@@ -43,10 +44,10 @@ def cl40m():
 def test_cl40m_resident(cl40m):
     g, dg = cl40m
     info = dg.info()
-    assert info["n"] == g.n and info["nnz"] == g.nnz and info["d_min"] == 1 and info["layout"] == 0
+    assert info["n"] == g.n and info["nnz"] == g.nnz and info["d_min"] == 1 and info["layout"] == 4
     assert g.nnz > 9.9e8
-    # 16-byte node entries, 4-byte neighbour ids, 4-byte row offsets
-    assert 16 * g.n + 4 * g.nnz <= info["device_bytes"] <= 20 * g.n + 4 * g.nnz + (64 << 20)
+    # 8-byte node entries, 4-byte neighbour ids, 4-byte row offsets
+    assert 12 * g.n + 4 * g.nnz <= info["device_bytes"] <= 12 * g.n + 4 * g.nnz + (64 << 20)
     _say(f"[cl40m] device bytes {info['device_bytes']:,}")
 
 

@@ -21,7 +21,7 @@ pytestmark = pytest.mark.gpu
 
 SEED = graphs.PHILOX_SEED
 LAYOUTS = [B.BD_LAYOUT_COMPACT, B.BD_LAYOUT_CSR | B.BD_RELABEL_DEGREE, B.BD_LAYOUT_FAT,
-           B.BD_LAYOUT_COMPACT | B.BD_RELABEL_DEGREE]
+           B.BD_LAYOUT_COMPACT | B.BD_RELABEL_DEGREE, B.BD_LAYOUT_COMPACT | B.BD_RELABEL_DEGREE | B.BD_WIDE_IDS]
 
 _cache = {}
 
