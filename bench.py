@@ -37,6 +37,7 @@ BYTES_PER_STEP = 12   # algorithmic: next node id + its row offset and degree (4
 HBM_PEAK_GBS = 8000.0
 COUNTERS = os.path.join(ROOT, "profiles", "walk_kernel_cl100k_counters.txt")
 KERNEL_SOURCES = ["pw_kernels.hip", "pw_device.hpp", "pw_internal.hpp"]
+LAYOUT_NAMES = {0: "csr", 1: "fat", 2: "compact", 3: "compact, hubs first", 4: "hubs first, 4-byte ids"}
 
 
 def log(*a):
@@ -147,16 +148,18 @@ def small_queries(B, torch, stream):
 def grid_batched(B, torch, stream, plain_sample=512):
     """Mixed eps and L in one persistent launch: the 1,414 x 1,414 grid (5% of
     edges removed), 65,536 queries, eps over {0.02, 0.05, 0.1}, L over {500,
-    2000, 5000}, throughput walk counts; chunking from the autotuner, the
-    launches captured into a hipGraph and run from it. The plain mode (one
-    query per launch) runs the first `plain_sample` queries of the same set."""
+    2000, 5000}, throughput walk counts; tables in the layout the library
+    picks (fat at this size); chunking from the autotuner, the launches
+    captured into a hipGraph and run from it. The plain mode (one query per
+    launch) runs the first `plain_sample` queries of the same set."""
     from paper_2512_05460_amd.budgets import BUDGETS, budget_policy
     from synth import graphs, queries
 
     g = graphs.workload_graph("grid1414")
     s, t, eps, Ls = queries.workload_batch("grid1414", g.n)
     nq = s.size
-    dg = B.graph_load_csr(g.n, g.row_ptr, g.col, B.BD_LAYOUT_COMPACT)
+    dg = B.graph_load_csr(g.n, g.row_ptr, g.col, B.BD_LAYOUT_AUTO)
+    info = dg.info()
     pol = budget_policy("grid1414")
     seed = graphs.PHILOX_SEED
     plan = B.bd_plan(dg, s, t, eps, Ls, pol)
@@ -193,6 +196,7 @@ def grid_batched(B, torch, stream, plain_sample=512):
     return {
         "workload": ("1,414 x 1,414 grid, 5% of edges removed, connected (bipartite); 65,536 uniform pairs, "
                      "eps over {0.02, 0.05, 0.1}, L over {500, 2000, 5000}"),
+        "layout": LAYOUT_NAMES[info["layout"]], "device_bytes": info["device_bytes"],
         "policy": {"kind": "scaled", "c_B": c_B, "c_R": c_R, "calibration": how},
         "R_range": [int(plan["R"].min()), int(plan["R"].max())],
         "walk_steps": steps,
@@ -214,8 +218,8 @@ def grid_batched(B, torch, stream, plain_sample=512):
 
 def served_cl10m(B, torch, seconds_per_load=20.0):
     """Continuous batching under Poisson arrivals: Chung-Lu n=10^7 (mean degree
-    10, exponent 2.3, largest component, compact layout with hubs first
-    resident on the device); request batches of 2^U uniform pairs (U uniform
+    10, exponent 2.3, largest component, resident on the device in the layout
+    the library picks: fat at this size); request batches of 2^U uniform pairs (U uniform
     on 0..12, 1 to 4,096 pairs), eps per query from {0.02, 0.05, 0.1}, L=1000,
     throughput walk counts. Capacity comes from a burst of requests submitted
     at once; then Poisson arrivals at 50%, 80% and 95% of it, each for
@@ -227,7 +231,7 @@ def served_cl10m(B, torch, seconds_per_load=20.0):
 
     log("served: building Chung-Lu n=10^7")
     g = graphs.workload_graph("cl10m")
-    dg = B.graph_load_csr(g.n, g.row_ptr, g.col, B.BD_LAYOUT_COMPACT | B.BD_RELABEL_DEGREE)
+    dg = B.graph_load_csr(g.n, g.row_ptr, g.col, B.BD_LAYOUT_AUTO)
     pol = budget_policy("cl10m")
     seed = graphs.PHILOX_SEED
     base = graphs.GRAPH_SEED + 3 + graphs.QUERY_SEED_OFFSET + 0x10
@@ -250,7 +254,7 @@ def served_cl10m(B, torch, seconds_per_load=20.0):
     out = {"workload": ("Chung-Lu n=10,000,000 mean degree 10 exponent 2.3 LCC; Poisson arrivals of request "
                         "batches of 2^U uniform pairs, U uniform on 0..12; eps per query from {0.02, 0.05, 0.1}; "
                         "L=1000"),
-           "graph": {"n": g.n, "nnz": g.nnz, "layout": "compact, hubs first",
+           "graph": {"n": g.n, "nnz": g.nnz, "layout": LAYOUT_NAMES[dg.info()["layout"]],
                      "device_bytes": dg.info()["device_bytes"]},
            "policy": {"kind": "scaled", "c_B": BUDGETS["cl10m"][0], "c_R": BUDGETS["cl10m"][1],
                       "calibration": BUDGETS["cl10m"][2]},
@@ -332,10 +336,10 @@ def scale_cl40m(B, torch, stream, served_queries=65536):
     """The scale workload: Chung-Lu n=4*10^7 (mean degree 25, exponent 2.2,
     largest component, about 10^9 adjacency entries; native generator); the
     262,144 queries (eps = 0.05, L over {1000, 10000}) in one persistent launch
-    on the CSR layout and on the compact layout with hubs first (4-byte ids at
-    this size), then on the latter the first `served_queries` of them as
-    requests of 4,096 submitted together to the server; throughput walk
-    counts."""
+    on the CSR layout, the compact layout with hubs first (4-byte ids at this
+    size) and the layout the library picks (fat), then on the last the first
+    `served_queries` of them as requests of 4,096 submitted together to the
+    server; throughput walk counts."""
     from paper_2512_05460_amd.budgets import BUDGETS, budget_policy
     from synth import graphs, queries
 
@@ -348,11 +352,13 @@ def scale_cl40m(B, torch, stream, served_queries=65536):
     seed = graphs.PHILOX_SEED
     layouts = {}
     r = dg = None
-    # CSR (16-byte node entries) first, then the compact layout with hubs
-    # first (8-byte entries, 4-byte ids above 2^24 nodes, hubs in LDS), which
-    # also runs the served part
+    # CSR (16-byte node entries), the compact layout with hubs first (8-byte
+    # entries, 4-byte ids above 2^24 nodes, hubs in LDS), then the automatic
+    # choice (fat: one 16-byte entry per step), which also runs the served
+    # part; the first load validates the graph, the others reuse its arrays
     for name, flags in (("csr, hubs first", B.BD_LAYOUT_CSR | B.BD_RELABEL_DEGREE),
-                        ("compact, hubs first", B.BD_LAYOUT_COMPACT | B.BD_RELABEL_DEGREE)):
+                        ("compact, hubs first", B.BD_LAYOUT_COMPACT | B.BD_RELABEL_DEGREE | B.BD_SKIP_VALIDATION),
+                        ("automatic", B.BD_LAYOUT_AUTO | B.BD_SKIP_VALIDATION)):
         if dg is not None:
             dg.free()
         log(f"scale: n={g.n} nnz={g.nnz}; loading ({name})")
@@ -370,7 +376,8 @@ def scale_cl40m(B, torch, stream, served_queries=65536):
         dt = time.perf_counter() - t0
         assert np.all(r["status"] == 0)
         roof = max((B.bd_gather_roofline(dg, c, 1000) for c in (2, 4, 8)), key=lambda x: x["steps_per_s"])
-        layouts[name] = {"device_bytes": dg.info()["device_bytes"], "load_s": t_load,
+        layouts[name] = {"layout": LAYOUT_NAMES[dg.info()["layout"]],
+                         "device_bytes": dg.info()["device_bytes"], "load_s": t_load,
                          "batched_queries_per_s": s.size / dt, "batched_walk_steps_per_s": steps / dt,
                          "kernel_walk_steps_per_s": steps / (st["walk_kernel_ms"] / 1e3),
                          "gather_roofline_steps_per_s": roof["steps_per_s"],
@@ -391,7 +398,7 @@ def scale_cl40m(B, torch, stream, served_queries=65536):
     steps_m = float(plan["walk_steps"][:m].sum())
     dg.free()
     c_B, c_R, how = BUDGETS["cl40m"]
-    best = layouts["compact, hubs first"]
+    best = max(layouts.values(), key=lambda x: x["batched_queries_per_s"])
     return {
         "workload": ("Chung-Lu n=40,000,000 mean degree 25 exponent 2.2 LCC; 262,144 uniform pairs; eps=0.05; "
                      "L over {1000, 10000}"),
@@ -399,6 +406,7 @@ def scale_cl40m(B, torch, stream, served_queries=65536):
         "policy": {"kind": "scaled", "c_B": c_B, "c_R": c_R, "calibration": how},
         "walk_steps": steps,
         "layouts": layouts,
+        "best_layout": best["layout"], "served_layout": layouts["automatic"]["layout"],
         "batched_queries_per_s": best["batched_queries_per_s"],
         "batched_walk_steps_per_s": best["batched_walk_steps_per_s"],
         "served_queries": m, "served_queries_per_s": m / dts, "served_walk_steps_per_s": steps_m / dts,
@@ -412,8 +420,9 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--queries", type=int, default=32, help="queries per step")
-    ap.add_argument("--layout", choices=["hubs", "compact", "csr", "fat"], default="hubs",
-                    help="hubs: compact layout with nodes in descending-degree order and hub entries in LDS")
+    ap.add_argument("--layout", choices=["hubs", "compact", "csr", "fat", "auto"], default="hubs",
+                    help="hubs: compact layout with nodes in descending-degree order and hub entries in LDS; "
+                         "auto: the library's choice (the same at this size)")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--no-roofline", action="store_true")
@@ -449,7 +458,7 @@ def main():
     s, t = s_all[:nq], t_all[:nq]
     flags = {"hubs": B.BD_LAYOUT_COMPACT | B.BD_RELABEL_DEGREE, "compact": B.BD_LAYOUT_COMPACT,
              "csr": B.BD_LAYOUT_CSR | B.BD_RELABEL_DEGREE,
-             "fat": B.BD_LAYOUT_FAT | B.BD_RELABEL_DEGREE}[args.layout]
+             "fat": B.BD_LAYOUT_FAT | B.BD_RELABEL_DEGREE, "auto": B.BD_LAYOUT_AUTO}[args.layout]
     dg = B.graph_load_csr(g.n, g.row_ptr, g.col, flags)
     pol = budget_policy(WORKLOAD)
     seed = graphs.PHILOX_SEED

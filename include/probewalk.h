@@ -83,6 +83,12 @@ typedef struct bd_graph bd_graph;
                                    neighbour ids take 4 bytes (layout code 4) */
 #define BD_WIDE_IDS        16u  /* with BD_LAYOUT_COMPACT | BD_RELABEL_DEGREE: 4-byte
                                    neighbour ids (layout code 4) at any n */
+#define BD_LAYOUT_AUTO     32u  /* the library picks: BD_LAYOUT_COMPACT | BD_RELABEL_DEGREE
+                                   when those tables take at most 4 MiB (one XCD's L2),
+                                   else BD_LAYOUT_FAT (with BD_RELABEL_DEGREE only if
+                                   given). Not with BD_LAYOUT_FAT, BD_LAYOUT_COMPACT or
+                                   BD_WIDE_IDS (BD_E_INVALID). bd_graph_get_info reports
+                                   the choice */
 
 typedef struct {
     int64_t  n, nnz;
@@ -103,10 +109,11 @@ typedef struct {
  *            self-loops, no repeats, and the adjacency symmetric. The order of
  *            a row is part of the contract: the walk's neighbour index j
  *            selects col_idx[row_ptr[x] + j].
- *   flags    BD_LAYOUT_* | BD_SKIP_VALIDATION.
+ *   flags    BD_LAYOUT_* | BD_RELABEL_DEGREE | BD_WIDE_IDS | BD_SKIP_VALIDATION.
  *   out      receives the handle; release with graph_free.
  * Errors: BD_E_GRAPH if a check fails (disconnected, asymmetric, unsorted,
- * self-loop), BD_E_RANGE for sizes beyond the limits, BD_E_NOMEM, BD_E_HIP.
+ * self-loop), BD_E_RANGE for sizes beyond the limits, BD_E_INVALID for
+ * conflicting layout flags, BD_E_NOMEM, BD_E_HIP.
  */
 int  graph_load_csr(int64_t n, const int64_t* row_ptr, const int32_t* col_idx,
                     uint32_t flags, void* stream, bd_graph** out);

@@ -43,6 +43,7 @@ BD_SKIP_VALIDATION = 2
 BD_RELABEL_DEGREE = 4
 BD_LAYOUT_COMPACT = 8
 BD_WIDE_IDS = 16
+BD_LAYOUT_AUTO = 32
 
 BD_POLICY_PAPER = 0
 BD_POLICY_SCALED = 1

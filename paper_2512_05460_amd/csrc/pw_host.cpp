@@ -28,6 +28,10 @@ constexpr int64_t kMaxN = int64_t(1) << 30;
 constexpr int64_t kMaxNnz = (int64_t(1) << 31) - 1;
 constexpr int32_t kMaxDeg = (1 << 24) - 1;
 constexpr int32_t kMaxL = 16383;
+// BD_LAYOUT_AUTO: hubs-first compact tables up to this size stay in one
+// XCD's 4 MB L2, where two short requests per step beat one 16-byte request;
+// above it every step misses L2 and the fat layout's single request wins.
+constexpr int64_t kAutoCompactBytes = int64_t(4) << 20;
 
 #define HIP_TRY(expr)                                  \
     do {                                               \
@@ -203,6 +207,13 @@ extern "C" int graph_load_csr(int64_t n, const int64_t* row_ptr, const int32_t* 
         dmax = std::max<int32_t>(dmax, (int32_t)d);
     }
     if (dmin < 1) return BD_E_GRAPH;  // an isolated node: not connected
+    if (flags & BD_LAYOUT_AUTO) {
+        if (flags & (BD_LAYOUT_FAT | BD_LAYOUT_COMPACT | BD_WIDE_IDS)) return BD_E_INVALID;
+        const int64_t compact_bytes = 8 * (n + 1) + 3 * nnz + 8;
+        flags = (n <= (int64_t(1) << 24) && compact_bytes <= kAutoCompactBytes)
+                    ? (flags | BD_LAYOUT_COMPACT | BD_RELABEL_DEGREE)
+                    : (flags | BD_LAYOUT_FAT);
+    }
     // compact layouts: 3-byte ids up to 2^24 nodes; hubs first keeps 4-byte ids above that
     const bool wide = (flags & BD_LAYOUT_COMPACT) && (flags & BD_RELABEL_DEGREE) &&
                       (n > (int64_t(1) << 24) || (flags & BD_WIDE_IDS));

@@ -65,11 +65,13 @@ def test_graph_checks_reject_bad_input():
     assert _load(2, [0, 1, 2], [5, 0]) == binding.BD_E_GRAPH
     # sizes
     assert _load(1, [0, 0], []) == binding.BD_E_RANGE
-    # the compact layouts exclude the fat layout
+    # the compact layouts exclude the fat layout; the automatic choice excludes both
     g = graphs.complete_graph(4)
     h = ctypes.c_void_p()
     for bad in (binding.BD_LAYOUT_COMPACT | binding.BD_LAYOUT_FAT,
-                binding.BD_LAYOUT_COMPACT | binding.BD_LAYOUT_FAT | binding.BD_RELABEL_DEGREE):
+                binding.BD_LAYOUT_COMPACT | binding.BD_LAYOUT_FAT | binding.BD_RELABEL_DEGREE,
+                binding.BD_LAYOUT_AUTO | binding.BD_LAYOUT_FAT, binding.BD_LAYOUT_AUTO | binding.BD_LAYOUT_COMPACT,
+                binding.BD_LAYOUT_AUTO | binding.BD_WIDE_IDS):
         rc = binding.lib().graph_load_csr(4, g.row_ptr.ctypes.data_as(ctypes.c_void_p),
                                           g.col.ctypes.data_as(ctypes.c_void_p), bad, None, ctypes.byref(h))
         assert rc == binding.BD_E_INVALID

@@ -2,14 +2,14 @@
 
 65,536 queries with eps over {0.02, 0.05, 0.1} and L over {500, 2000, 5000}
 run in one persistent launch, with chunking from the autotuner, captured into a
-hipGraph and replayed. Walk counts are the throughput setting of
+hipGraph and replayed, on the layout the library picks (fat at this size). Walk counts are the throughput setting of
 paper_2512_05460_amd/budgets.py (scaled policy of Algorithm 1).
 
   * planner parity over all 65,536 queries;
   * sampled parity at full size: beta-hat of two queries of every (eps, L)
     pair equals the oracle's bit for bit (all sums are exact fixed point);
   * graph replays equal the eager persistent launch, any number of chunk
-    queues and the plain mode.
+    queues, the plain mode and the compact layout.
 """
 
 import sys
@@ -36,7 +36,7 @@ def _say(*a):
 def grid():
     g = graphs.workload_graph("grid1414")
     _say(f"[grid] n={g.n} nnz={g.nnz}")
-    dg = B.graph_load_csr(g.n, g.row_ptr, g.col, B.BD_LAYOUT_COMPACT)
+    dg = B.graph_load_csr(g.n, g.row_ptr, g.col, B.BD_LAYOUT_AUTO)
     yield g, dg
     dg.free()
 
@@ -52,7 +52,7 @@ def _oracle_plans(g, s, t, eps, L):
 def test_grid_info(grid):
     g, dg = grid
     info = dg.info()
-    assert info["bipartite"] == 1 and info["d_min"] == 1 and info["d_max"] == 4
+    assert info["bipartite"] == 1 and info["d_min"] == 1 and info["d_max"] == 4 and info["layout"] == 1
     assert g.n == 1414 * 1414 and g.nnz == 2 * (2 * 1414 * 1413 - round(0.05 * 2 * 1414 * 1413))
 
 
@@ -118,3 +118,9 @@ def test_grid_replay_equals_eager_and_plain(grid):
     plain = B.bd_query_batch(dg, s[sub], t[sub], eps[sub], L[sub], SEED, pol, B.exec_cfg("plain"),
                              uid=sub.astype(np.uint32))
     assert np.array_equal(plain["beta"], eager["beta"][sub])
+    dc = B.graph_load_csr(g.n, g.row_ptr, g.col, B.BD_LAYOUT_COMPACT | B.BD_SKIP_VALIDATION)
+    try:
+        r = B.bd_query_batch(dc, s, t, eps, L, SEED, pol, B.exec_cfg("batched", chunk_pairs=128))
+        assert np.array_equal(r["beta"], eager["beta"])
+    finally:
+        dc.free()

@@ -72,6 +72,16 @@ def test_graph_info(ba1k, layout, code):
     assert gi["layout"] == code and gi["bipartite"] == 0
 
 
+def test_auto_layout(ba1k):
+    # hubs-first compact tables within 4 MiB (one XCD's L2), else the fat layout
+    assert load(ba1k, B.BD_LAYOUT_AUTO).info()["layout"] == 3
+    assert load(graphs.workload_graph("cl100k"), B.BD_LAYOUT_AUTO).info()["layout"] == 3
+    grid = graphs.workload_graph("grid1414")
+    for flags in (B.BD_LAYOUT_AUTO, B.BD_LAYOUT_AUTO | B.BD_RELABEL_DEGREE):
+        gi = load(grid, flags | B.BD_SKIP_VALIDATION).info()
+        assert gi["layout"] == 1 and gi["device_bytes"] >= 16 * grid.nnz
+
+
 def test_bipartite_flag():
     gi = load(graphs.cycle_graph(6), B.BD_LAYOUT_CSR).info()
     assert gi["bipartite"] == 1

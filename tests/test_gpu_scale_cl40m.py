@@ -1,7 +1,8 @@
 """The scale workload at full size: Chung-Lu n=4*10^7 (mean degree 25,
 exponent 2.2, largest component: 39,944,860 nodes, 996,486,866 adjacency
 entries) in the compact layout with hubs first, which above 2^24 nodes keeps
-4-byte neighbour ids.
+4-byte neighbour ids, and in the layout the library picks (fat: 16-byte
+adjacency entries, 16 GB at this size).
 
 Queries of the workload's set (eps = 0.05, L in {1000, 10000}) in one
 persistent launch and through the server; sampled queries are checked bit for
@@ -81,3 +82,29 @@ def test_cl40m_batched_and_served_sampled_parity(cl40m):
             assert np.array_equal(out["beta"], res["beta"][64 * k:64 * k + 64])
     finally:
         srv.destroy()
+
+
+@pytest.mark.timeout(900)
+def test_cl40m_fat_equals_hubs_first(cl40m):
+    g, dg = cl40m
+    n = 4096
+    s, t, eps, L = queries.workload_batch("cl40m", g.n, n)
+    pol = budget_policy("cl40m")
+    ref = B.bd_query_batch(dg, s, t, eps, L, SEED, pol, B.exec_cfg("batched"))
+    _say("[cl40m] loading the automatic layout")
+    fat = B.graph_load_csr(g.n, g.row_ptr, g.col, B.BD_LAYOUT_AUTO | B.BD_SKIP_VALIDATION)
+    try:
+        info = fat.info()
+        assert info["layout"] == 1
+        assert 16 * g.n + 20 * g.nnz <= info["device_bytes"] <= 20 * g.n + 20 * g.nnz + (64 << 20)
+        res = B.bd_query_batch(fat, s, t, eps, L, SEED, pol, B.exec_cfg("batched"))
+        assert np.array_equal(res["beta"], ref["beta"])
+        srv = B.Server(fat, pol)
+        try:
+            rid = srv.submit(s[:512], t[:512], eps[:512], L[:512], SEED)
+            out, _ = srv.wait(rid)
+            assert np.array_equal(out["beta"], ref["beta"][:512])
+        finally:
+            srv.destroy()
+    finally:
+        fat.free()

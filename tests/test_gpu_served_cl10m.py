@@ -1,5 +1,7 @@
 """Served mode at full size: Chung-Lu n=10^7 (mean degree 10, exponent 2.3,
-largest component) resident on the device in the compact layout.
+largest component) resident on the device in the layout the library picks
+(fat: one 16-byte entry per walk step) and in the compact layout (3-byte ids
+near their 2^24 limit).
 
 Requests of mixed size (1 to 4,096 pairs, eps per query from {0.02, 0.05,
 0.1}, L=1000) are submitted while others run. Sampled queries are checked bit
@@ -35,25 +37,31 @@ def cl10m():
     _say("[cl10m] building the graph")
     g = graphs.workload_graph("cl10m")
     _say(f"[cl10m] n={g.n} nnz={g.nnz}; loading")
-    dg = B.graph_load_csr(g.n, g.row_ptr, g.col, B.BD_LAYOUT_COMPACT)
-    yield g, dg
-    dg.free()
+    dc = B.graph_load_csr(g.n, g.row_ptr, g.col, B.BD_LAYOUT_COMPACT)
+    da = B.graph_load_csr(g.n, g.row_ptr, g.col, B.BD_LAYOUT_AUTO | B.BD_SKIP_VALIDATION)
+    yield g, da, dc
+    da.free()
+    dc.free()
 
 
 @pytest.mark.timeout(600)
 def test_cl10m_resident(cl10m):
-    g, dg = cl10m
-    info = dg.info()
+    g, da, dc = cl10m
+    info = dc.info()
     assert info["n"] == g.n and info["nnz"] == g.nnz and info["d_min"] == 1
     assert info["layout"] == 2 and info["bipartite"] == 0
     # compact: 4 bytes per row offset, 3 per adjacency entry (+ padding)
     assert 4 * g.n + 3 * g.nnz <= info["device_bytes"] <= 4 * g.n + 3 * g.nnz + (1 << 20)
-    _say(f"[cl10m] device bytes {info['device_bytes']:,}")
+    fat = da.info()
+    assert fat["layout"] == 1 and fat["n"] == g.n and fat["nnz"] == g.nnz
+    # fat: 16-byte adjacency entries beside the CSR node table and ids
+    assert 16 * g.n + 20 * g.nnz <= fat["device_bytes"] <= 20 * g.n + 20 * g.nnz + (64 << 20)
+    _say(f"[cl10m] device bytes compact {info['device_bytes']:,}, fat {fat['device_bytes']:,}")
 
 
 @pytest.mark.timeout(900)
 def test_served_mix_equals_oracle_and_alone(cl10m):
-    g, dg = cl10m
+    g, dg, dc = cl10m
     pol = budget_policy("cl10m")
     c_B, c_R, _ = BUDGETS["cl10m"]
     op = OP.Policy("scaled", c_B=c_B, c_R=c_R)
@@ -90,12 +98,14 @@ def test_served_mix_equals_oracle_and_alone(cl10m):
                               uid=np.array([picks[j][1] for j in sel], dtype=np.uint32), threads=16)
     assert np.array_equal(got, ref), got - ref
     # alone: one-query requests with the same uid and seed, and the plain mode
+    # in both layouts
     for j, (ri, qi, _) in enumerate(picks[:6]):
         s, t, e = reqs[ri]
         rid = srv.submit(s[qi:qi + 1], t[qi:qi + 1], e[qi:qi + 1], L, seeds[ri], uid=[qi])
         o, _ = srv.wait(rid)
         assert o["beta"][0] == got[j]
-        p = B.bd_query_batch(dg, s[qi:qi + 1], t[qi:qi + 1], e[qi:qi + 1], L, seeds[ri], pol,
-                             B.exec_cfg("plain"), uid=[qi])
-        assert p["beta"][0] == got[j]
+        for d_ in (dg, dc):
+            p = B.bd_query_batch(d_, s[qi:qi + 1], t[qi:qi + 1], e[qi:qi + 1], L, seeds[ri], pol,
+                                 B.exec_cfg("plain"), uid=[qi])
+            assert p["beta"][0] == got[j]
     srv.destroy()
