@@ -332,14 +332,15 @@ def served_cl10m(B, torch, seconds_per_load=20.0):
     return out
 
 
-def scale_cl40m(B, torch, stream, served_queries=65536):
+def scale_cl40m(B, torch, stream, served_queries=65536, which=("csr", "hubs", "auto")):
     """The scale workload: Chung-Lu n=4*10^7 (mean degree 25, exponent 2.2,
     largest component, about 10^9 adjacency entries; native generator); the
     262,144 queries (eps = 0.05, L over {1000, 10000}) in one persistent launch
     on the CSR layout, the compact layout with hubs first (4-byte ids at this
     size) and the layout the library picks (fat), then on the last the first
     `served_queries` of them as requests of 4,096 submitted together to the
-    server; throughput walk counts."""
+    server; throughput walk counts. `which` selects among the three layouts
+    (the served part runs on the last one selected)."""
     from paper_2512_05460_amd.budgets import BUDGETS, budget_policy
     from synth import graphs, queries
 
@@ -356,11 +357,13 @@ def scale_cl40m(B, torch, stream, served_queries=65536):
     # entries, 4-byte ids above 2^24 nodes, hubs in LDS), then the automatic
     # choice (fat: one 16-byte entry per step), which also runs the served
     # part; the first load validates the graph, the others reuse its arrays
-    for name, flags in (("csr, hubs first", B.BD_LAYOUT_CSR | B.BD_RELABEL_DEGREE),
-                        ("compact, hubs first", B.BD_LAYOUT_COMPACT | B.BD_RELABEL_DEGREE | B.BD_SKIP_VALIDATION),
-                        ("automatic", B.BD_LAYOUT_AUTO | B.BD_SKIP_VALIDATION)):
+    cand = [("csr", "csr, hubs first", B.BD_LAYOUT_CSR | B.BD_RELABEL_DEGREE),
+            ("hubs", "compact, hubs first", B.BD_LAYOUT_COMPACT | B.BD_RELABEL_DEGREE),
+            ("auto", "automatic", B.BD_LAYOUT_AUTO)]
+    for key, name, flags in [c for c in cand if c[0] in which]:
         if dg is not None:
             dg.free()
+            flags |= B.BD_SKIP_VALIDATION
         log(f"scale: n={g.n} nnz={g.nnz}; loading ({name})")
         t0 = time.perf_counter()
         dg = B.graph_load_csr(g.n, g.row_ptr, g.col, flags)
@@ -383,6 +386,7 @@ def scale_cl40m(B, torch, stream, served_queries=65536):
                          "gather_roofline_steps_per_s": roof["steps_per_s"],
                          "gather_roofline_frac": steps / (st["walk_kernel_ms"] / 1e3) / roof["steps_per_s"]}
     m = served_queries
+    dg_layout = dg.info()["layout"]
     srv = B.Server(dg, pol)
     log(f"scale: served, {m} queries as requests of 4096")
     t0 = time.perf_counter()
@@ -406,7 +410,7 @@ def scale_cl40m(B, torch, stream, served_queries=65536):
         "policy": {"kind": "scaled", "c_B": c_B, "c_R": c_R, "calibration": how},
         "walk_steps": steps,
         "layouts": layouts,
-        "best_layout": best["layout"], "served_layout": layouts["automatic"]["layout"],
+        "best_layout": best["layout"], "served_layout": LAYOUT_NAMES[dg_layout],
         "batched_queries_per_s": best["batched_queries_per_s"],
         "batched_walk_steps_per_s": best["batched_walk_steps_per_s"],
         "served_queries": m, "served_queries_per_s": m / dts, "served_walk_steps_per_s": steps_m / dts,
@@ -430,6 +434,8 @@ def main():
     ap.add_argument("--no-grid", action="store_true")
     ap.add_argument("--no-sharing", action="store_true")
     ap.add_argument("--no-stabilize", action="store_true")
+    ap.add_argument("--scale-layouts", default="csr,hubs,auto",
+                    help="layouts of the scale report, from csr, hubs, auto")
     ap.add_argument("--scale", action="store_true",
                     help="also run the Chung-Lu n=4e7 workload (about 3 minutes more)")
     ap.add_argument("--no-served-cl10m", action="store_true")
@@ -573,7 +579,10 @@ def main():
     if not args.no_served_cl10m:
         extra["served_cl10m"] = served_cl10m(B, torch)
     if args.scale:
-        extra["scale_cl40m"] = scale_cl40m(B, torch, stream)
+        which = args.scale_layouts.split(",")
+        if not which or not set(which) <= {"csr", "hubs", "auto"}:
+            raise SystemExit(f"--scale-layouts takes csr, hubs, auto; got {args.scale_layouts}")
+        extra["scale_cl40m"] = scale_cl40m(B, torch, stream, which=which)
     roof = None
     if not args.no_roofline:
         log("gather roofline")
