@@ -36,6 +36,7 @@ L = 1000
 BYTES_PER_STEP = 12   # algorithmic: next node id + its row offset and degree (4 + 4 + 4 bytes)
 HBM_PEAK_GBS = 8000.0
 COUNTERS = os.path.join(ROOT, "profiles", "walk_kernel_cl100k_counters.txt")
+FAT_SCALE_COUNTERS = os.path.join(ROOT, "profiles", "walk_kernel_fat_cl40m_counters.txt")
 KERNEL_SOURCES = ["pw_kernels.hip", "pw_device.hpp", "pw_internal.hpp"]
 LAYOUT_NAMES = {0: "csr", 1: "fat", 2: "compact", 3: "compact, hubs first", 4: "hubs first, 4-byte ids"}
 
@@ -52,18 +53,27 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def counter_traffic():
-    """HBM bytes per walk-kernel launch from the committed rocprofv3 summary, or
-    None when the kernel sources changed since the counters were taken."""
-    if not os.path.exists(COUNTERS):
+def read_counters(path):
+    """key = value lines of a committed rocprofv3 summary, or (None, why) when
+    it is missing or the kernel sources changed since the counters were taken."""
+    if not os.path.exists(path):
         return None, "no counter summary"
     kv = {}
-    for ln in open(COUNTERS):
+    for ln in open(path):
         if "=" in ln and not ln.startswith("#"):
             k, v = ln.split("=", 1)
-            kv[k.strip()] = v.strip()
+            kv[k.strip()] = v.split("(")[0].strip()
     if kv.get("kernel_source_sha256_16") != kernel_source_hash():
         return None, "kernel changed since the counters were taken"
+    return kv, ""
+
+
+def counter_traffic():
+    """HBM bytes per walk step of the headline kernel from the committed
+    rocprofv3 summary, or None when the kernel sources changed since."""
+    kv, why = read_counters(COUNTERS)
+    if kv is None:
+        return None, why
     try:
         fetch = float(kv["fetch_kib_per_dispatch"]) * float(kv["fetch_scale"])
         write = float(kv["write_kib_per_dispatch"]) * float(kv["write_scale"])
@@ -403,6 +413,19 @@ def scale_cl40m(B, torch, stream, served_queries=65536, which=("csr", "hubs", "a
     dg.free()
     c_B, c_R, how = BUDGETS["cl40m"]
     best = max(layouts.values(), key=lambda x: x["batched_queries_per_s"])
+    # the fat layout's HBM roofline: bytes per step from the committed counters
+    # (one 128-byte line per step), at the walk-step rate measured here
+    if "automatic" in layouts and layouts["automatic"]["layout"] == "fat":
+        kv, why = read_counters(FAT_SCALE_COUNTERS)
+        a = layouts["automatic"]
+        if kv is None:
+            a["hbm_roofline"] = {"note": why}
+        else:
+            bps = float(kv["hbm_read_bytes_per_step"])
+            achieved = bps * a["kernel_walk_steps_per_s"] / 1e9
+            a["hbm_roofline"] = {"bound": "hbm", "bytes_per_step": bps, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                                 "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                                 "note": "HBM read bytes per step from TCC_EA0_RDREQ_* counters (128-byte requests)"}
     return {
         "workload": ("Chung-Lu n=40,000,000 mean degree 25 exponent 2.2 LCC; 262,144 uniform pairs; eps=0.05; "
                      "L over {1000, 10000}"),
