@@ -78,7 +78,7 @@ typedef struct bd_graph bd_graph;
                                    recomputed: the smallest footprint (n <= 2^24; not with
                                    BD_LAYOUT_FAT). With BD_RELABEL_DEGREE: 8-byte node
                                    entries {row offset, original id} in descending-degree
-                                   order, the 1024 highest-degree ones staged in LDS by
+                                   order, the 8192 highest-degree ones staged in LDS by
                                    every work group (layout code 3); above 2^24 nodes the
                                    neighbour ids take 4 bytes (layout code 4) */
 #define BD_WIDE_IDS        16u  /* with BD_LAYOUT_COMPACT | BD_RELABEL_DEGREE: 4-byte

@@ -174,7 +174,7 @@ __device__ __forceinline__ int probe_value(uint32_t x, const Probe& pr, const Do
 // (the highest-degree nodes, which the walks visit most) are staged in LDS.
 // Above 2^24 nodes the same layout keeps 4-byte neighbour storage ids.
 constexpr int kLayoutCsr = 0, kLayoutFat = 1, kLayoutCompact = 2, kLayoutCompactHub = 3, kLayoutHub32 = 4;
-constexpr uint32_t kHubNodes = 1024;
+constexpr uint32_t kHubNodes = 8192;
 
 struct DevGraph {
     const uint4* node;      // n entries (CSR and fat layouts)

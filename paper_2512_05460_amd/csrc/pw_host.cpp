@@ -522,7 +522,8 @@ int resident_wgs(const bd_graph* g, int uniform, int share = 1)
 }
 
 // How the probes of one query are cut into work-group chunks.
-//   plain:   one chunk holds whole probes (all R replicas), at least 256 pairs;
+//   plain:   one chunk holds whole probes (all R replicas), at least one pair
+//            per thread of the layout's work group (256, or 1,024 hubs first);
 //   batched / served: whole probes up to kSplitReplicas pairs per chunk, and a
 //   probe with R > kSplitReplicas is cut into replica parts (multiples of 64)
 //   so that no chunk runs much longer than the others.
@@ -550,13 +551,13 @@ struct Groups {
     uint32_t size(uint32_t gi) const { return std::min(M, B - (gi % per_block) * M); }
 };
 
-ChunkPlan chunk_plan(const bd_exec& ex, const QueryDesc& d)
+ChunkPlan chunk_plan(const bd_exec& ex, const QueryDesc& d, int layout)
 {
     ChunkPlan cp;
     const Groups grp(d);
     const uint32_t R = d.R;
     const uint32_t pairs = ex.chunk_pairs > 0 ? std::max<uint32_t>((uint32_t)ex.chunk_pairs, 64u)
-                           : ex.mode == BD_MODE_PLAIN ? (uint32_t)kBlockThreads : kSplitReplicas;
+                           : ex.mode == BD_MODE_PLAIN ? (uint32_t)block_threads(layout) : kSplitReplicas;
     if (ex.mode != BD_MODE_PLAIN && R >= kUniformMinR && R > pairs) {
         const uint32_t parts = (R + pairs - 1) / pairs;
         cp.part = ((R + parts - 1) / parts + 63u) & ~63u;
@@ -582,8 +583,8 @@ struct ChunkCursor {
     ChunkPlan plan;
     uint32_t next_g = 0, next_p = 0;
     ChunkCursor() = default;
-    ChunkCursor(uint32_t q_, const QueryDesc& d, const bd_exec& ex)
-        : q(q_), R(d.R), grp(d), plan(chunk_plan(ex, d))
+    ChunkCursor(uint32_t q_, const QueryDesc& d, const bd_exec& ex, int layout)
+        : q(q_), R(d.R), grp(d), plan(chunk_plan(ex, d, layout))
     {
     }
     bool done() const { return next_g >= grp.n; }
@@ -844,7 +845,7 @@ void build_batch(const bd_graph* g, int64_t nq, const int32_t* s, const int32_t*
         uint64_t nu = 0;
         for (const QueryDesc& d : b.qd) {
             if ((int64_t)d.R < umin) continue;
-            const ChunkPlan cp = chunk_plan(ex, d);
+            const ChunkPlan cp = chunk_plan(ex, d, g->layout);
             const uint32_t ng = Groups(d).n;
             nu += cp.part ? (uint64_t)ng * ((d.R + cp.part - 1) / cp.part) : (ng + cp.gc - 1) / cp.gc;
         }
@@ -863,7 +864,7 @@ void build_batch(const bd_graph* g, int64_t nq, const int32_t* s, const int32_t*
     b.chunk_begin.assign(b.qd.size(), 0);
     auto emit = [&](size_t q) {
         QueryDesc& d = b.qd[q];
-        ChunkCursor cur((uint32_t)q, d, ex);
+        ChunkCursor cur((uint32_t)q, d, ex, g->layout);
         if (cur.plan.part) {
             d.psum_base = b.split_probes;
             b.split_probes += d.K;
@@ -1278,7 +1279,8 @@ extern "C" int bd_gather_roofline(bd_graph* g, int32_t chains_per_lane, int32_t 
     hipStream_t st = (hipStream_t)stream;
     uint32_t grid = work_groups > 0 ? (uint32_t)work_groups : 4u * (uint32_t)resident_wgs(g, 1, 1);
     DevBuf sink;
-    int rc = sink.alloc((size_t)grid * kBlockThreads * 4);
+    const int wg = block_threads(g->layout);
+    int rc = sink.alloc((size_t)grid * wg * 4);
     if (rc != BD_OK) return rc;
     const int fat = g->layout == 1;
     // warm-up launch (caches, clocks), then the timed one
@@ -1294,7 +1296,7 @@ extern "C" int bd_gather_roofline(bd_graph* g, int32_t chains_per_lane, int32_t 
     HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    const double n = (double)grid * kBlockThreads * chains_per_lane * steps;
+    const double n = (double)grid * wg * chains_per_lane * steps;
     out->ms = ms;
     out->steps = (int64_t)n;
     out->steps_per_s = n / (ms * 1e-3);
@@ -1559,9 +1561,9 @@ int admit(bd_server* S)
         bool fits = true;
         for (size_t i = 0; i < need && fits; ++i) {
             const QueryDesc& d = r.desc[i];
-            if (chunk_plan(ex, d).part && !S->psum_alloc.alloc(d.K, &base[i])) {
+            if (chunk_plan(ex, d, S->g->layout).part && !S->psum_alloc.alloc(d.K, &base[i])) {
                 for (size_t j = 0; j < i; ++j)
-                    if (chunk_plan(ex, r.desc[j]).part) S->psum_alloc.release(base[j], r.desc[j].K);
+                    if (chunk_plan(ex, r.desc[j], S->g->layout).part) S->psum_alloc.release(base[j], r.desc[j].K);
                 fits = false;
             }
         }
@@ -1583,7 +1585,7 @@ int admit(bd_server* S)
             SlotState& ss = S->slot[sl];
             ss.req = id;
             ss.ridx = r.index[i];
-            ss.cur = ChunkCursor(sl, d, ex);
+            ss.cur = ChunkCursor(sl, d, ex, S->g->layout);
             ss.L = (uint32_t)d.L;
             ss.steps = (uint64_t)r.res[(size_t)ss.ridx].walk_steps;
             ss.uniform = d.R >= kUniformMinR;
@@ -1668,8 +1670,8 @@ void fill_slice(bd_server* S, Slice& sl)
         SlotState& ss = S->slot[q];
         sl.steps += ss.cur.chunk_steps(ss.L);
         const Chunk c = ss.cur.next();
-        const double cost = ((double)ss.L + 1.0) *
-                            (double)(((uint64_t)c.gc * c.pc + kBlockThreads - 1) / kBlockThreads);
+        const uint64_t wg = (uint64_t)block_threads(S->g->layout);
+        const double cost = ((double)ss.L + 1.0) * (double)(((uint64_t)c.gc * c.pc + wg - 1) / wg);
         sl.sum_cost += cost;
         if (cost > sl.max_cost) {
             sl.max_cost = cost;
@@ -1906,7 +1908,7 @@ extern "C" int bd_server_submit(bd_server* S, int64_t nq, const int32_t* s, cons
         r.index.push_back(i);
         r.steps += (uint64_t)pr.walk_steps;
         const bd_exec ex = server_exec(S);
-        if (chunk_plan(ex, d).part) r.split_probes += d.K;
+        if (chunk_plan(ex, d, S->g->layout).part) r.split_probes += d.K;
     }
     r.remaining = (int64_t)r.desc.size();
     if (r.desc.size() > S->slots || r.split_probes > S->arena) return BD_E_FULL;

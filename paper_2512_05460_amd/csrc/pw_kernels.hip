@@ -221,8 +221,9 @@ __device__ void run_chunk(const WalkArgs& A, const DevGraph& G, uint32_t ci,
 {
     const Chunk c = A.chunks[ci];
     const QueryDesc d = A.qd[c.q];
+    constexpr int kT = block_threads(kLayout);
     const int tid = threadIdx.x;
-    for (uint32_t j = tid; j < c.kc * 4u; j += kBlockThreads) acc[j] = 0ull;
+    for (uint32_t j = tid; j < c.kc * 4u; j += kT) acc[j] = 0ull;
     __syncthreads();
 
     const WalkState s0 = start_at<kLayout>(G, (uint32_t)d.s);
@@ -239,7 +240,7 @@ __device__ void run_chunk(const WalkArgs& A, const DevGraph& G, uint32_t ci,
         const uint32_t nb = (c.pc + 63u) >> 6;
         const uint32_t units = c.gc * nb;
         const uint32_t pend = c.p0 + c.pc;
-        for (uint32_t u = wave; u < units; u += kBlockThreads / 64) {
+        for (uint32_t u = wave; u < units; u += kT / 64) {
             const uint32_t gg = u / nb;
             const uint32_t p = c.p0 + (u - gg * nb) * 64u + lane;
             if (p < pend) {
@@ -273,7 +274,7 @@ __device__ void run_chunk(const WalkArgs& A, const DevGraph& G, uint32_t ci,
         // Any replica count: lanes stride over the chunk's (group, replica)
         // pairs, so one wave can cover several groups.
         const uint64_t total = (uint64_t)c.gc * c.pc;
-        for (uint64_t base = 0; base < total; base += kBlockThreads) {
+        for (uint64_t base = 0; base < total; base += kT) {
             const uint64_t w = base + (uint64_t)tid;
             if (w < total) {
                 const uint32_t gg = (uint32_t)(w / c.pc);
@@ -344,7 +345,7 @@ __device__ void run_chunk(const WalkArgs& A, const DevGraph& G, uint32_t ci,
         return;
     }
 
-    for (uint32_t j = tid; j < c.kc; j += kBlockThreads) {
+    for (uint32_t j = tid; j < c.kc; j += kT) {
         const i128 S1 = (i128)(((u128)acc[4 * j + 1] << 64) | (u128)acc[4 * j]);
         const u128 S2 = ((u128)acc[4 * j + 3] << 64) | (u128)acc[4 * j + 2];
         const double Q = probe_q(S1, S2, d.R);
@@ -368,7 +369,7 @@ __device__ void run_chunk(const WalkArgs& A, const DevGraph& G, uint32_t ci,
 // kUniform: every chunk of the launch has R >= kUniformMinR (see run_chunk).
 // Eight waves per SIMD where the kernel fits 64 VGPRs without spilling.
 template <int kLayout, int kUniform, int kShare>
-__global__ __launch_bounds__(kBlockThreads, kShare == 1 && (kUniform || kLayout == kLayoutCompact ||
+__global__ __launch_bounds__(block_threads(kLayout), kShare == 1 && (kUniform || kLayout == kLayoutCompact ||
                                                             kLayout == kLayoutCompactHub ||
                                                             kLayout == kLayoutHub32) ? 8 : 1) void walk_kernel(
     WalkArgs A)
@@ -441,9 +442,10 @@ static const void* walk_fn(int layout, int uniform, int share)
 template <int kLayout, int kUniform>
 static void launch_l(const WalkArgs& a, int share, uint32_t grid, hipStream_t st)
 {
-    if (share == 4) hipLaunchKernelGGL((walk_kernel<kLayout, kUniform, 4>), dim3(grid), dim3(kBlockThreads), 0, st, a);
-    else if (share == 2) hipLaunchKernelGGL((walk_kernel<kLayout, kUniform, 2>), dim3(grid), dim3(kBlockThreads), 0, st, a);
-    else hipLaunchKernelGGL((walk_kernel<kLayout, kUniform, 1>), dim3(grid), dim3(kBlockThreads), 0, st, a);
+    const dim3 block(block_threads(kLayout));
+    if (share == 4) hipLaunchKernelGGL((walk_kernel<kLayout, kUniform, 4>), dim3(grid), block, 0, st, a);
+    else if (share == 2) hipLaunchKernelGGL((walk_kernel<kLayout, kUniform, 2>), dim3(grid), block, 0, st, a);
+    else hipLaunchKernelGGL((walk_kernel<kLayout, kUniform, 1>), dim3(grid), block, 0, st, a);
 }
 
 hipError_t launch_walk(const WalkArgs& a, int layout, int uniform, int share, uint32_t grid, hipStream_t st)
@@ -471,7 +473,7 @@ hipError_t launch_walk(const WalkArgs& a, int layout, int uniform, int share, ui
 int walk_occupancy(int layout, int uniform, int share, int* wgs_per_cu)
 {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, walk_fn(layout, uniform, share), kBlockThreads, 0) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, walk_fn(layout, uniform, share), block_threads(layout), 0) !=
         hipSuccess)
         return -1;
     *wgs_per_cu = nb;
@@ -595,7 +597,7 @@ namespace pw {
 // transitions per second is the memory-side ceiling of the walk kernel on
 // this graph, layout and footprint.
 template <int kLayout, int kChains>
-__global__ __launch_bounds__(kBlockThreads) void gather_kernel(GraphTables gt, int32_t steps, uint32_t seed,
+__global__ __launch_bounds__(block_threads(kLayout)) void gather_kernel(GraphTables gt, int32_t steps, uint32_t seed,
                                                                uint32_t* sink)
 {
     __shared__ uint2 hub_lds[kLayout == kLayoutCompactHub || kLayout == kLayoutHub32 ? kHubNodes + 1 : 1];
@@ -633,7 +635,8 @@ __global__ __launch_bounds__(kBlockThreads) void gather_kernel(GraphTables gt, i
 hipError_t launch_gather(const GraphTables& g, int layout, int chains, uint32_t grid, int32_t steps, uint32_t seed,
                          uint32_t* sink, hipStream_t st)
 {
-#define PW_GATHER(F, C) hipLaunchKernelGGL((gather_kernel<F, C>), dim3(grid), dim3(kBlockThreads), 0, st, g, steps, seed, sink)
+#define PW_GATHER(F, C) \
+    hipLaunchKernelGGL((gather_kernel<F, C>), dim3(grid), dim3(block_threads(F)), 0, st, g, steps, seed, sink)
 #define PW_GATHER_C(F)                  \
     do {                                \
         if (chains == 1) PW_GATHER(F, 1); \
