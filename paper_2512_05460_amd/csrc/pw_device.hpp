@@ -170,11 +170,13 @@ __device__ __forceinline__ int probe_value(uint32_t x, const Probe& pr, const Do
 // rounded) at every step instead of stored.
 // Compact layout with hubs first: storage ids in descending-degree order, node
 // entries {row offset, original id} (8 bytes; entry n = {nnz, 0}), neighbour
-// storage ids packed in 3 bytes; the entries of the first kHubNodes storage ids
+// storage ids packed in 3 bytes; the entries of the first hub_nodes() storage ids
 // (the highest-degree nodes, which the walks visit most) are staged in LDS.
 // Above 2^24 nodes the same layout keeps 4-byte neighbour storage ids.
 constexpr int kLayoutCsr = 0, kLayoutFat = 1, kLayoutCompact = 2, kLayoutCompactHub = 3, kLayoutHub32 = 4;
-constexpr uint32_t kHubNodes = 8192;
+// hub entries staged per work group: 8,192 (64 KB) in 1,024-thread groups,
+// 1,024 in 256-thread ones
+constexpr uint32_t hub_nodes(int threads) { return threads >= 1024 ? 8192u : 1024u; }
 
 struct DevGraph {
     const uint4* node;      // n entries (CSR and fat layouts)
@@ -279,10 +281,10 @@ __device__ __forceinline__ void step(WalkState& w, uint32_t u, const DevGraph& G
 // Copy the hub entries of the compact layout with hubs first into LDS (every
 // thread of the block must call it); other layouts keep nhub = 0.
 template <int kLayout>
-__device__ __forceinline__ void stage_hubs(DevGraph& G, uint2* lds)
+__device__ __forceinline__ void stage_hubs(DevGraph& G, uint2* lds, uint32_t capacity)
 {
     if constexpr (kLayout == kLayoutCompactHub || kLayout == kLayoutHub32) {
-        const uint32_t nh = min(kHubNodes, G.dom.n);
+        const uint32_t nh = min(capacity, G.dom.n);
         for (uint32_t i = threadIdx.x; i <= nh; i += blockDim.x) lds[i] = G.node8[i];
         __syncthreads();
         G.hub = lds;

@@ -557,7 +557,8 @@ ChunkPlan chunk_plan(const bd_exec& ex, const QueryDesc& d, int layout)
     const Groups grp(d);
     const uint32_t R = d.R;
     const uint32_t pairs = ex.chunk_pairs > 0 ? std::max<uint32_t>((uint32_t)ex.chunk_pairs, 64u)
-                           : ex.mode == BD_MODE_PLAIN ? (uint32_t)block_threads(layout) : kSplitReplicas;
+                           : ex.mode == BD_MODE_PLAIN ? (uint32_t)block_threads(layout, share_class(d.share))
+                                                      : kSplitReplicas;
     if (ex.mode != BD_MODE_PLAIN && R >= kUniformMinR && R > pairs) {
         const uint32_t parts = (R + pairs - 1) / pairs;
         cp.part = ((R + parts - 1) / parts + 63u) & ~63u;
@@ -1279,7 +1280,7 @@ extern "C" int bd_gather_roofline(bd_graph* g, int32_t chains_per_lane, int32_t 
     hipStream_t st = (hipStream_t)stream;
     uint32_t grid = work_groups > 0 ? (uint32_t)work_groups : 4u * (uint32_t)resident_wgs(g, 1, 1);
     DevBuf sink;
-    const int wg = block_threads(g->layout);
+    const int wg = block_threads(g->layout, 1);
     int rc = sink.alloc((size_t)grid * wg * 4);
     if (rc != BD_OK) return rc;
     const int fat = g->layout == 1;
@@ -1670,7 +1671,7 @@ void fill_slice(bd_server* S, Slice& sl)
         SlotState& ss = S->slot[q];
         sl.steps += ss.cur.chunk_steps(ss.L);
         const Chunk c = ss.cur.next();
-        const uint64_t wg = (uint64_t)block_threads(S->g->layout);
+        const uint64_t wg = (uint64_t)block_threads(S->g->layout, share_class(policy_share(S->pol)));
         const double cost = ((double)ss.L + 1.0) * (double)(((uint64_t)c.gc * c.pc + wg - 1) / wg);
         sl.sum_cost += cost;
         if (cost > sl.max_cost) {

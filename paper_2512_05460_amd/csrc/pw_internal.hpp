@@ -90,13 +90,15 @@ constexpr uint32_t kMaxShare = 4;
 inline int share_class(uint32_t M) { return M <= 1 ? 1 : M <= 2 ? 2 : 4; }
 
 constexpr int kBlockThreads = 256;
-// Work-group size of the walk and gather kernels per layout code. The
-// hubs-first layouts (codes 3 and 4) stage the node entries of the 8,192
-// highest-degree nodes (64 KB) in LDS once per 1,024-thread work group: two
-// groups per CU keep 8 waves per SIMD within the 160 KB of LDS, and the staged
-// nodes take 42% of the steps on a Chung-Lu n=1e5 graph (1,024 nodes in each
-// 256-thread group would take 18%).
-constexpr int block_threads(int layout) { return layout == 3 || layout == 4 ? 1024 : kBlockThreads; }
+// Work-group size of the walk and gather kernels per layout code and walk
+// sharing class. With one probe per walk the hubs-first layouts (codes 3 and
+// 4) stage the node entries of the 8,192 highest-degree nodes (64 KB) in LDS
+// once per 1,024-thread work group: two groups per CU keep 8 waves per SIMD
+// within the 160 KB of LDS, and the staged nodes take 42% of the steps on a
+// Chung-Lu n=1e5 graph (1,024 nodes per 256-thread group take 18%). The
+// sharing kernels run 4-5 waves per SIMD, one such group per CU, and keep
+// 256-thread groups with 1,024 staged nodes.
+constexpr int block_threads(int layout, int share) { return (layout == 3 || layout == 4) && share <= 1 ? 1024 : kBlockThreads; }
 constexpr uint32_t kMaxQueues = 8;      // one chunk queue per XCD
 constexpr int kMaxChunkProbes = 256;
 constexpr int kMaxG = 128;

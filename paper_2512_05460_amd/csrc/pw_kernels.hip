@@ -221,7 +221,7 @@ __device__ void run_chunk(const WalkArgs& A, const DevGraph& G, uint32_t ci,
 {
     const Chunk c = A.chunks[ci];
     const QueryDesc d = A.qd[c.q];
-    constexpr int kT = block_threads(kLayout);
+    constexpr int kT = block_threads(kLayout, kShare);
     const int tid = threadIdx.x;
     for (uint32_t j = tid; j < c.kc * 4u; j += kT) acc[j] = 0ull;
     __syncthreads();
@@ -369,7 +369,7 @@ __device__ void run_chunk(const WalkArgs& A, const DevGraph& G, uint32_t ci,
 // kUniform: every chunk of the launch has R >= kUniformMinR (see run_chunk).
 // Eight waves per SIMD where the kernel fits 64 VGPRs without spilling.
 template <int kLayout, int kUniform, int kShare>
-__global__ __launch_bounds__(block_threads(kLayout), kShare == 1 && (kUniform || kLayout == kLayoutCompact ||
+__global__ __launch_bounds__(block_threads(kLayout, kShare), kShare == 1 && (kUniform || kLayout == kLayoutCompact ||
                                                             kLayout == kLayoutCompactHub ||
                                                             kLayout == kLayoutHub32) ? 8 : 1) void walk_kernel(
     WalkArgs A)
@@ -377,9 +377,10 @@ __global__ __launch_bounds__(block_threads(kLayout), kShare == 1 && (kUniform ||
     __shared__ unsigned long long acc[kMaxChunkProbes * 4];
     __shared__ double ys[kMaxG];
     __shared__ uint32_t next;
-    __shared__ uint2 hub_lds[kLayout == kLayoutCompactHub || kLayout == kLayoutHub32 ? kHubNodes + 1 : 1];
+    constexpr uint32_t kHubs = hub_nodes(block_threads(kLayout, kShare));
+    __shared__ uint2 hub_lds[kLayout == kLayoutCompactHub || kLayout == kLayoutHub32 ? kHubs + 1 : 1];
     DevGraph G = make_graph(A.g);
-    stage_hubs<kLayout>(G, hub_lds);
+    stage_hubs<kLayout>(G, hub_lds, kHubs);
     if (!A.persistent) {
         if (blockIdx.x < A.nchunks) run_chunk<kLayout, kUniform, kShare>(A, G, blockIdx.x, acc, ys);
         return;
@@ -442,10 +443,12 @@ static const void* walk_fn(int layout, int uniform, int share)
 template <int kLayout, int kUniform>
 static void launch_l(const WalkArgs& a, int share, uint32_t grid, hipStream_t st)
 {
-    const dim3 block(block_threads(kLayout));
-    if (share == 4) hipLaunchKernelGGL((walk_kernel<kLayout, kUniform, 4>), dim3(grid), block, 0, st, a);
-    else if (share == 2) hipLaunchKernelGGL((walk_kernel<kLayout, kUniform, 2>), dim3(grid), block, 0, st, a);
-    else hipLaunchKernelGGL((walk_kernel<kLayout, kUniform, 1>), dim3(grid), block, 0, st, a);
+    if (share == 4)
+        hipLaunchKernelGGL((walk_kernel<kLayout, kUniform, 4>), dim3(grid), dim3(block_threads(kLayout, 4)), 0, st, a);
+    else if (share == 2)
+        hipLaunchKernelGGL((walk_kernel<kLayout, kUniform, 2>), dim3(grid), dim3(block_threads(kLayout, 2)), 0, st, a);
+    else
+        hipLaunchKernelGGL((walk_kernel<kLayout, kUniform, 1>), dim3(grid), dim3(block_threads(kLayout, 1)), 0, st, a);
 }
 
 hipError_t launch_walk(const WalkArgs& a, int layout, int uniform, int share, uint32_t grid, hipStream_t st)
@@ -473,7 +476,8 @@ hipError_t launch_walk(const WalkArgs& a, int layout, int uniform, int share, ui
 int walk_occupancy(int layout, int uniform, int share, int* wgs_per_cu)
 {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, walk_fn(layout, uniform, share), block_threads(layout), 0) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, walk_fn(layout, uniform, share),
+                                                     block_threads(layout, share), 0) !=
         hipSuccess)
         return -1;
     *wgs_per_cu = nb;
@@ -597,12 +601,13 @@ namespace pw {
 // transitions per second is the memory-side ceiling of the walk kernel on
 // this graph, layout and footprint.
 template <int kLayout, int kChains>
-__global__ __launch_bounds__(block_threads(kLayout)) void gather_kernel(GraphTables gt, int32_t steps, uint32_t seed,
+__global__ __launch_bounds__(block_threads(kLayout, 1)) void gather_kernel(GraphTables gt, int32_t steps, uint32_t seed,
                                                                uint32_t* sink)
 {
-    __shared__ uint2 hub_lds[kLayout == kLayoutCompactHub || kLayout == kLayoutHub32 ? kHubNodes + 1 : 1];
+    constexpr uint32_t kHubs = hub_nodes(block_threads(kLayout, 1));
+    __shared__ uint2 hub_lds[kLayout == kLayoutCompactHub || kLayout == kLayoutHub32 ? kHubs + 1 : 1];
     DevGraph G = make_graph(gt);
-    stage_hubs<kLayout>(G, hub_lds);
+    stage_hubs<kLayout>(G, hub_lds, kHubs);
     const uint32_t gid = blockIdx.x * blockDim.x + threadIdx.x;
     WalkState w[kChains];
     uint32_t rng[kChains];
@@ -636,7 +641,7 @@ hipError_t launch_gather(const GraphTables& g, int layout, int chains, uint32_t 
                          uint32_t* sink, hipStream_t st)
 {
 #define PW_GATHER(F, C) \
-    hipLaunchKernelGGL((gather_kernel<F, C>), dim3(grid), dim3(block_threads(F)), 0, st, g, steps, seed, sink)
+    hipLaunchKernelGGL((gather_kernel<F, C>), dim3(grid), dim3(block_threads(F, 1)), 0, st, g, steps, seed, sink)
 #define PW_GATHER_C(F)                  \
     do {                                \
         if (chains == 1) PW_GATHER(F, 1); \
