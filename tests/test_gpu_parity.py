@@ -160,6 +160,14 @@ PROBE_CASES = [
     ("ba1k", 10, 900, 200, 3, 300, B.BD_LAYOUT_COMPACT, 0),
     ("cl100k", 5, 77, 1000, 1, 70, B.BD_LAYOUT_COMPACT, 0),
     ("P2", 0, 1, 5, 2, 3, B.BD_LAYOUT_COMPACT, 0),
+    # hubs first: 1,024-thread work groups with 8,192 staged node entries; on
+    # cl100k steps go to staged and unstaged nodes, on ba1k every node is staged;
+    # R = 40 runs the general kernel, R = 70 and 300 the wave-uniform one
+    ("cl100k", 5, 77, 1000, 1, 70, B.BD_LAYOUT_COMPACT | B.BD_RELABEL_DEGREE, 0),
+    ("cl100k", 5, 77, 1000, 2, 40, B.BD_LAYOUT_COMPACT | B.BD_RELABEL_DEGREE, 0),
+    ("cl100k", 5, 77, 1000, 1, 70, B.BD_LAYOUT_COMPACT | B.BD_RELABEL_DEGREE | B.BD_WIDE_IDS, 0),
+    ("ba1k", 10, 900, 200, 3, 300, B.BD_LAYOUT_COMPACT | B.BD_RELABEL_DEGREE, 0),
+    ("G37", 2, 30, 40, 3, 100, B.BD_LAYOUT_COMPACT | B.BD_RELABEL_DEGREE, 7),
 ]
 
 
