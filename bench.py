@@ -20,6 +20,7 @@ from __future__ import annotations
 
 import argparse
 import hashlib
+import re
 import json
 import os
 import sys
@@ -46,10 +47,14 @@ def log(*a):
 
 
 def kernel_source_hash() -> str:
+    """sha256[:16] of the device sources with comments and blank lines removed:
+    it changes when the compiled kernels can, not when a comment does."""
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_2512_05460_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2512_05460_amd", "csrc", f), encoding="utf-8") as fh:
+            src = re.sub(r"/\*.*?\*/", "", fh.read(), flags=re.S)
+        lines = (re.sub(r"//.*", "", ln).rstrip() for ln in src.splitlines())
+        h.update("\n".join(ln for ln in lines if ln).encode())
     return h.hexdigest()[:16]
 
 

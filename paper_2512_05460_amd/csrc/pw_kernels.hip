@@ -2,7 +2,8 @@
 //
 // One work group runs one chunk: probes [k0, k0+kc) of one query with all R
 // replicas each (Algorithm 1: the probe loop, the replica loop and the walk
-// loop). Its 256 lanes stride over the kc*R (probe, replica) pairs; each lane
+// loop). Its lanes (256, or 1,024 on the hubs-first layouts with one probe
+// per walk) stride over the kc*R (probe, replica) pairs; each lane
 // runs the s-walk and the t-walk of its pair interleaved, so two independent
 // dependent-gather chains are in flight per lane. Per-probe sums S1, S2 are
 // exact 128-bit integers accumulated in LDS; at the end of the chunk each
@@ -11,8 +12,8 @@
 // query's last probe forms the G block means and their median.
 //
 // The same chunk routine serves one-query-per-launch (grid = chunks) and
-// persistent launches (grid = resident capacity, chunks claimed from an
-// atomic cursor until none are left, so every wave exits).
+// persistent launches (grid = resident capacity, chunks claimed from per-XCD
+// atomic cursors until none are left, so every wave exits).
 #include "pw_device.hpp"
 #include "pw_internal.hpp"
 
