@@ -168,7 +168,8 @@ typedef struct {
     int32_t  use_graph;      /* BATCHED: replay a captured hipGraph of the launch (work buffers
                                 are reused; the graph is rebuilt when the batch shape changes) */
     int32_t  chunk_pairs;    /* (probe, replica) pairs per chunk, also the replica-part size of
-                                a split probe (BATCHED); 0 = 256 (PLAIN) / 4096 (BATCHED) */
+                                a split probe (BATCHED); 0 = one per work-group thread (PLAIN:
+                                256, or 1024 on the hubs-first layouts) / 4096 (BATCHED) */
     int32_t  queues;         /* BATCHED: chunk queues of the persistent launch, 1..8. A query's
                                 chunks stay in one queue and a work group takes chunks from the
                                 queue of the XCD it runs on before the others, so they share
