@@ -88,6 +88,21 @@ def counter_traffic():
     return (fetch + write) * 1024.0 / steps, "bytes per walk step, FETCH_SIZE and WRITE_SIZE scaled by a copy kernel"
 
 
+def l2_requests(kernel_sps):
+    """The resource that binds the L2-resident headline kernel: L2 requests per
+    walk step from the committed counters, at the walk-step rate measured here."""
+    kv, why = read_counters(COUNTERS)
+    if kv is None:
+        return {"note": why}
+    try:
+        rps = float(kv["l2_requests_per_step"])
+        hit = float(kv["l2_hit_rate"])
+    except (KeyError, ValueError):
+        return {"note": "incomplete counter summary"}
+    return {"requests_per_step": rps, "hit_rate": hit, "requests_per_s": rps * kernel_sps,
+            "note": "random L2 requests per walk step (TCC_REQ); the tables are L2-resident"}
+
+
 def cpu_baseline(g, s, t, plans, seed, target_s=20.0):
     """The oracle on a bounded sample: each of `threads` queries runs its first
     few probes at the full R and L; queries/s is the measured step rate divided
@@ -677,6 +692,7 @@ def main():
             "kernel_walk_steps_per_s": kernel_sps,
             "bytes_per_step": BYTES_PER_STEP,
             "gather_roofline": roof,
+            "l2": l2_requests(kernel_sps),
         },
         "cpu_baseline": cpu,
         "paper_context": ("per-query times of the same estimator in the paper (Table 3): one thread of an "
