@@ -487,8 +487,8 @@ def main():
                     help="also run a device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU: queries shard across GPUs with nothing exchanged but "
-              "a few block sums per query, and this build runs and reports one GPU's share.",
+        print("bench.py runs on one GPU only (--gpus 1): queries shard across GPUs with nothing "
+              "exchanged but a few block sums per query, so it reports one GPU's share.",
               file=sys.stderr)
         sys.exit(2)
 

@@ -3,7 +3,7 @@
 L = 500, 2000 and 5000.
 
 The grid is bipartite, so the series does not converge to beta and beta^(L)
-is the reference the estimator is judged against at a fixed L. Calls only the
+is the reference the estimator is measured against at a fixed L. Calls only the
 oracle (oracle.exact.beta_truncated_multi: L binary64 sparse products) and the
 seeded generators; about 20 minutes on one core.
 

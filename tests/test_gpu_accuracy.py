@@ -94,7 +94,7 @@ def test_accuracy_cl100k_walk_sharing():
 
 @pytest.mark.timeout(600)
 def test_accuracy_grid_truncated():
-    # The bipartite grid: judged against beta^(L) (the series does not converge
+    # The bipartite grid: measured against beta^(L) (the series does not converge
     # to beta), 32 golden pairs x eps in {.02, .05, .1} x L in {500, 2000, 5000}
     g = graphs.workload_graph("grid1414")
     ref = np.loadtxt(GRID_GOLDEN, comments="#")
