@@ -36,6 +36,7 @@ EPS = 0.05
 L = 1000
 BYTES_PER_STEP = 12   # algorithmic: next node id + its row offset and degree (4 + 4 + 4 bytes)
 HBM_PEAK_GBS = 8000.0
+L2_PEAK_REQ_PER_S = 8 * 16 * 2.4e9   # one request per L2 channel per clock, 16 channels per XCD
 COUNTERS = os.path.join(ROOT, "profiles", "walk_kernel_cl100k_counters.txt")
 FAT_SCALE_COUNTERS = os.path.join(ROOT, "profiles", "walk_kernel_fat_cl40m_counters.txt")
 KERNEL_SOURCES = ["pw_kernels.hip", "pw_device.hpp", "pw_internal.hpp"]
@@ -99,8 +100,11 @@ def l2_requests(kernel_sps):
         hit = float(kv["l2_hit_rate"])
     except (KeyError, ValueError):
         return {"note": "incomplete counter summary"}
-    return {"requests_per_step": rps, "hit_rate": hit, "requests_per_s": rps * kernel_sps,
-            "note": "random L2 requests per walk step (TCC_REQ); the tables are L2-resident"}
+    achieved = rps * kernel_sps
+    return {"requests_per_step": rps, "hit_rate": hit, "requests_per_s": achieved,
+            "peak_requests_per_s": L2_PEAK_REQ_PER_S, "frac": achieved / L2_PEAK_REQ_PER_S,
+            "note": ("random L2 requests per walk step (TCC_REQ); the tables are L2-resident; peak = one "
+                     "request per L2 channel per clock: 8 XCDs x 16 channels x 2.4 GHz")}
 
 
 def cpu_baseline(g, s, t, plans, seed, target_s=20.0):
