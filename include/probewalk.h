@@ -84,8 +84,8 @@ typedef struct bd_graph bd_graph;
 #define BD_WIDE_IDS        16u  /* with BD_LAYOUT_COMPACT | BD_RELABEL_DEGREE: 4-byte
                                    neighbour ids (layout code 4) at any n */
 #define BD_LAYOUT_AUTO     32u  /* the library picks: BD_LAYOUT_COMPACT | BD_RELABEL_DEGREE
-                                   when those tables take at most 4 MiB (one XCD's L2),
-                                   else BD_LAYOUT_FAT (with BD_RELABEL_DEGREE only if
+                                   when those tables take at most 12 MiB (measured
+                                   crossover), else BD_LAYOUT_FAT (with BD_RELABEL_DEGREE only if
                                    given). Not with BD_LAYOUT_FAT, BD_LAYOUT_COMPACT or
                                    BD_WIDE_IDS (BD_E_INVALID). bd_graph_get_info reports
                                    the choice */

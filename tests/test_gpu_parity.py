@@ -73,7 +73,7 @@ def test_graph_info(ba1k, layout, code):
 
 
 def test_auto_layout(ba1k):
-    # hubs-first compact tables within 4 MiB (one XCD's L2), else the fat layout
+    # hubs-first compact tables within 12 MiB, else the fat layout
     assert load(ba1k, B.BD_LAYOUT_AUTO).info()["layout"] == 3
     assert load(graphs.workload_graph("cl100k"), B.BD_LAYOUT_AUTO).info()["layout"] == 3
     grid = graphs.workload_graph("grid1414")
