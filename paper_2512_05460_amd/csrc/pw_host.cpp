@@ -32,7 +32,8 @@ constexpr int32_t kMaxL = 16383;
 // short requests per step, mostly L2 hits with 42% of the node reads from
 // LDS, beat the fat layout's one 16-byte request into a 4.5x larger table;
 // beyond it the misses dominate and fat wins. Measured on Chung-Lu graphs of
-// mean degree 10: at 8 MiB hubs first ran 1.40x fat, at 16 MiB 0.89x.
+// mean degree 10: with 7.2 MiB of tables hubs first ran 1.40x fat, with
+// 14.4 MiB 0.89x.
 constexpr int64_t kAutoCompactBytes = int64_t(12) << 20;
 
 #define HIP_TRY(expr)                                  \
