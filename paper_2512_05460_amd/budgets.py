@@ -27,7 +27,7 @@ BUDGETS = {
     "grid1414": (0.0064, 128.0 / 2 ** 28, "throughput setting, not calibrated"),
     # The same grid at one L at a time, calibrated against the truncated
     # distance beta^(L) of 32 pairs (tests/golden) at eps in {.02,.05,.1}:
-    # c_R = 16/(L+1)^2 gives R = 38..68 at every L (the (L+1)^2 of Algorithm 1
+    # c_R = 16/(L+1)^2 gives R = 37..68 at every L (the (L+1)^2 of Algorithm 1
     # overstates the grid's walk variance, which grows about like L log L while
     # beta^(L) grows like L), and B = 256 at eps = 0.05. Within eps: 99.0%
     # (L=500), 100% (L=2000), 96.9% (L=5000) of 96 queries; half the

@@ -1,0 +1,57 @@
+"""The walk-count budgets of paper_2512_05460_amd/budgets.py: the policies it
+hands to the library carry its constants, and the block and replica counts
+its comments state follow from them under the planner of Algorithm 1 (the
+oracle's copy)."""
+
+import os
+
+import numpy as np
+import pytest
+
+from oracle import planner as OP
+from paper_2512_05460_amd import binding as B
+from paper_2512_05460_amd.budgets import BUDGETS, SHARED_BUDGETS, budget_policy
+
+
+@pytest.mark.parametrize("key", sorted(BUDGETS))
+def test_policy_carries_the_constants(key):
+    c_B, c_R, how = BUDGETS[key]
+    p = budget_policy(key)
+    assert p.kind == B.BD_POLICY_SCALED and p.c_B == c_B and p.c_R == c_R and p.delta == 0.01
+    assert p.share <= 1
+    assert how.startswith("calibrated") or how.startswith("throughput")
+
+
+def test_shared_policy():
+    M, c_B, c_R, _ = SHARED_BUDGETS["cl100k"]
+    p = budget_policy("cl100k", shared=True)
+    assert (p.share, p.c_B, p.c_R) == (M, c_B, c_R) and M == 4
+
+
+def _B(key, eps):
+    c_B, c_R, _ = BUDGETS[key]
+    return OP.plan(eps, 1000, 1, 1, 1, OP.Policy("scaled", c_B=c_B, c_R=c_R))[0]
+
+
+def test_stated_block_sizes():
+    # G = 37 blocks at delta = 0.01; B per eps as the comments state
+    assert OP.plan(0.05, 1000, 1, 1, 1, OP.Policy("scaled", c_B=0.64, c_R=1.0))[1] == 37
+    assert _B("cl100k", 0.05) == 256
+    assert [_B("cl10m", e) for e in (0.02, 0.05, 0.1)] == [100, 16, 4]
+    assert [_B("grid1414", e) for e in (0.02, 0.05, 0.1)] == [16, 3, 1]
+    assert _B("cl40m", 0.05) == 1
+    assert _B("grid1414@2000", 0.05) == 256
+    M, c_B, _, _ = SHARED_BUDGETS["cl100k"]
+    assert OP.plan(0.05, 1000, 1, 1, 1, OP.Policy("scaled", c_B=c_B, c_R=1.0))[0] == 384
+
+
+@pytest.mark.parametrize("L", [500, 2000, 5000])
+def test_grid_replicas_per_L(L):
+    # c_R = 16/(L+1)^2 on the grid (d_min 1): R from 37 to 68 for the endpoint
+    # degrees of the 32 calibration pairs (tests/golden), whatever L
+    ref = np.loadtxt(os.path.join(os.path.dirname(__file__), "golden", "grid1414_truncated_reference.txt"),
+                     comments="#")
+    c_B, c_R, _ = BUDGETS[f"grid1414@{L}"]
+    Rs = [OP.plan(e, L, int(ds), int(dt), 1, OP.Policy("scaled", c_B=c_B, c_R=c_R))[3]
+          for e in (0.02, 0.05, 0.1) for ds, dt in ref[:, 3:5]]
+    assert min(Rs) == 37 and max(Rs) == 68
