@@ -55,3 +55,18 @@ def test_grid_replicas_per_L(L):
     Rs = [OP.plan(e, L, int(ds), int(dt), 1, OP.Policy("scaled", c_B=c_B, c_R=c_R))[3]
           for e in (0.02, 0.05, 0.1) for ds, dt in ref[:, 3:5]]
     assert min(Rs) == 37 and max(Rs) == 68
+
+
+@pytest.mark.parametrize("key,count,B_,R_median", [("ba1k", 256, 96, 176), ("cl100k", 128, 256, 934)])
+def test_calibrated_budgets_on_their_pairs(key, count, B_, R_median):
+    # the calibration sets: B and the median R over the reference pairs
+    from synth import graphs, queries
+
+    g = graphs.workload_graph(key)
+    s, t, eps, L = queries.workload_batch(key, g.n, count)
+    c_B, c_R, _ = BUDGETS[key]
+    pol = OP.Policy("scaled", c_B=c_B, c_R=c_R)
+    plans = [OP.plan(float(eps[i]), int(L[i]), int(g.deg[s[i]]), int(g.deg[t[i]]), g.d_min, pol)
+             for i in range(count)]
+    assert {p[0] for p in plans} == {B_}
+    assert np.median([p[3] for p in plans]) == R_median
