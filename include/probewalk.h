@@ -79,8 +79,9 @@ typedef struct bd_graph bd_graph;
                                    BD_LAYOUT_FAT). With BD_RELABEL_DEGREE: 8-byte node
                                    entries {row offset, original id} in descending-degree
                                    order, the 8192 highest-degree ones staged in LDS by
-                                   every work group (layout code 3); above 2^24 nodes the
-                                   neighbour ids take 4 bytes (layout code 4) */
+                                   every work group (1024 in the walk-sharing kernels)
+                                   (layout code 3); above 2^24 nodes the neighbour ids
+                                   take 4 bytes (layout code 4) */
 #define BD_WIDE_IDS        16u  /* with BD_LAYOUT_COMPACT | BD_RELABEL_DEGREE: 4-byte
                                    neighbour ids (layout code 4) at any n */
 #define BD_LAYOUT_AUTO     32u  /* the library picks: BD_LAYOUT_COMPACT | BD_RELABEL_DEGREE
