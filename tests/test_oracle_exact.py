@@ -158,3 +158,43 @@ def test_alternative_expression_lemma22():
     h = exact.h_truncated(g, 2, 11, 3000)
     b_series = h @ h - h.sum() ** 2 / g.n
     assert b_series == pytest.approx(exact.beta_dense(g, 2, 11, Lp)[0], rel=1e-9)
+
+
+@pytest.mark.parametrize("maker,closed", [
+    (lambda: graphs.complete_graph(9), lambda n, s, t: 2.0 / n ** 2),
+    (lambda: graphs.cycle_graph(11),
+     lambda n, s, t: ((t - s) % n) * (n - (t - s) % n) * (((t - s) % n) * (n - (t - s) % n) + 2) / (12.0 * n)),
+])
+def test_beta_dense_all_closed_forms(maker, closed):
+    # the many-pairs routine (the reference of the BA accuracy test) on every
+    # ordered pair, against the closed forms and the one-pair routine
+    g = maker()
+    s, t = zip(*_pairs(g.n))
+    got = exact.beta_dense_all(g, s, t)
+    for j, (a, b) in enumerate(zip(s, t)):
+        assert got[j] == pytest.approx(closed(g.n, a, b), rel=1e-11)
+        assert got[j] == pytest.approx(exact.beta_dense(g, a, b)[0], rel=1e-13)
+
+
+def test_beta_dense_all_path_closed_form():
+    n = 9
+    g = graphs.path_graph(n)
+    s, t = zip(*_pairs(n))
+    got = exact.beta_dense_all(g, s, t)
+    for j, (a, b) in enumerate(zip(s, t)):
+        lo, hi = min(a, b), max(a, b)  # beta is symmetric in (s, t)
+        p, D = lo + 1, hi - lo
+        ref = p * D * D + D * (D - 1) * (2 * D - 1) / 6.0 - (p * D + D * (D - 1) / 2.0) ** 2 / n
+        assert got[j] == pytest.approx(ref, rel=1e-10)
+
+
+def test_beta_dense_all_random_graph_vs_one_pair():
+    g = graphs.random_connected(40, 0.15, 3)
+    rng = np.random.default_rng(1)
+    s = rng.integers(0, 40, 60)
+    t = (s + 1 + rng.integers(0, 39, 60)) % 40
+    got = exact.beta_dense_all(g, s, t)
+    ref = np.array([exact.beta_dense(g, int(a), int(b))[0] for a, b in zip(s, t)])
+    assert np.allclose(got, ref, rtol=1e-12, atol=0)
+    # Lemma 3.5 lower bound on every pair
+    assert np.all(got >= (1 / 8) * (1.0 / g.deg[s] + 1.0 / g.deg[t]) ** 2)

@@ -83,3 +83,48 @@ def test_second_moment_is_centering_matrix(n):
     assert np.abs(M - H).max() < 5.0 * sd
     # per-entry diagonal mean is exactly 1 - r/n for each probe; its average -> 1 - 1/n
     assert np.abs(np.diag(M) - (1 - 1.0 / n)).max() < 5.0 * sd
+
+
+# p of the base-sign hash family (section 3.3): a fixed prime above n/2
+HASH_P = 2 ** 31 - 1
+
+
+@pytest.mark.parametrize("n", [2, 7, 10, 1000, 1001, 65536, 100003])
+def test_base_sign_hash_recomputed(n):
+    # Section 3.3: z_i = 0 iff pi_k(i) >= n - r, else
+    # z_i = (-1)^(h_k(pi_k(i) >> 1) + pi_k(i)) with h_k(u) = ((a_k u + b_k) mod p) mod 2.
+    # Recomputed here with Python integers from the probe's exposed a_k, b_k, r
+    # and pi_k; the oracle's C code reduces a 64-bit product instead.
+    rng = np.random.default_rng(n)
+    nodes = np.arange(n, dtype=np.uint32) if n <= 4096 else rng.integers(0, n, 4096).astype(np.uint32)
+    for k in range(40):
+        pi, z, prm = E.probe(n, 0x5EED_0B1A, 11, k, nodes=nodes)
+        a, b, r = int(prm[6]), int(prm[7]), int(prm[8])
+        for y, zi in zip(pi.tolist(), z.tolist()):
+            if y >= n - r:
+                assert zi == 0
+                continue
+            h = ((a * (y >> 1) + b) % HASH_P) % 2
+            assert zi == (-1) ** (h + (y & 1)), (n, k, y)
+
+
+def test_base_signs_balanced_and_pairwise_independent():
+    # The base bits h_k(u) of a 2-universal family are fair and pairwise
+    # independent across probes: for u != u', (-1)^(h(u) + h(u')) has mean 0
+    # (up to O(1/p)). Observed through z: z_i (-1)^(pi_k(i)) = (-1)^(h_k(pi_k(i) >> 1)).
+    n, nk = 64, 20000
+    bits = np.zeros((nk, n // 2), dtype=np.float64)
+    for k in range(nk):
+        pi, z, _ = E.probe(n, 77, 2, k)
+        act = z != 0
+        u = pi[act] >> 1
+        bits[k, u] = z[act] * (1 - 2 * (pi[act].astype(np.int64) & 1))
+    # u = n/2 - 1 is the zero pair when r = 2 (half the probes): left out
+    bits = bits[:, : n // 2 - 1]
+    m = bits.shape[1]
+    assert np.all(np.abs(bits) == 1.0)
+    sd = 1.0 / np.sqrt(nk)
+    assert np.abs(bits.mean(axis=0)).max() < 5 * sd
+    C = bits.T @ bits / nk
+    off = C[~np.eye(m, dtype=bool)]
+    assert np.abs(off).max() < 5.5 * sd
