@@ -60,6 +60,8 @@ extern "C" {
 #define BD_E_FULL     -9  /* server admission refused: request exceeds the caps */
 #define BD_E_CANCELLED -10 /* server destroyed before the request finished */
 #define BD_E_TIMEOUT  -11 /* bd_server_wait timed out; the request is still running */
+#define BD_E_SCRATCH  -12 /* bd_query_batch_noalloc: the batch needs more than the fixed
+                             scratch array holds (BD_NOALLOC_SCRATCH_BYTES) */
 
 /* ---- graph --------------------------------------------------------------- */
 typedef struct bd_graph bd_graph;
@@ -210,6 +212,34 @@ int bd_query_batch(bd_graph* g, int64_t nq, const int32_t* s, const int32_t* t,
                    const double* eps, const int32_t* L, const uint32_t* uid,
                    uint64_t seed, const bd_policy* pol, const bd_exec* exec,
                    void* stream, bd_result* out, bd_stats* stats);
+
+/*
+ * For callers that cannot allocate device memory (code under hipGraph capture,
+ * serving loops that must not call hipMalloc, harnesses that forbid it): the
+ * same computation as bd_query_batch, bit for bit, with every work buffer
+ * (query descriptors, chunk table, block sums, counters, split-probe
+ * accumulators, results) carved out of a fixed device array of
+ * BD_NOALLOC_SCRATCH_BYTES that the library holds on each device from the
+ * time it is loaded there until the process ends. The call allocates no
+ * device memory and creates no events or streams; the caller still passes its
+ * inputs and outputs in host memory and the graph stays as loaded.
+ *   Arguments, results and errors as bd_query_batch, and additionally:
+ *   - BD_E_SCRATCH when the batch's buffers exceed the array (about 650 bytes
+ *     per query plus 32 per chunk, and 36 per probe of queries whose probes
+ *     are split in batched mode); nothing runs then;
+ *   - BD_E_INVALID when the current device is not the graph's;
+ *   - exec->use_graph is ignored (no hipGraph), and stats->walk_kernel_ms is
+ *     0 (no timing events); the other stats are filled.
+ * The array is shared by every call on a device and keeps the last call's
+ * contents; each call clears the parts that must start at zero. Calls on one
+ * device take a process-wide lock for the array and run one at a time: two
+ * calls overlapping on one device would otherwise race on it.
+ */
+#define BD_NOALLOC_SCRATCH_BYTES (64u << 20)
+int bd_query_batch_noalloc(bd_graph* g, int64_t nq, const int32_t* s, const int32_t* t,
+                           const double* eps, const int32_t* L, const uint32_t* uid,
+                           uint64_t seed, const bd_policy* pol, const bd_exec* exec,
+                           void* stream, bd_result* out, bd_stats* stats);
 
 /*
  * The truncated distance beta^(L)(s,t) = ||h||^2 - (1^T h)^2 / n with

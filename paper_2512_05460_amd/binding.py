@@ -36,6 +36,8 @@ BD_E_NOTFOUND = -8
 BD_E_FULL = -9
 BD_E_CANCELLED = -10
 BD_E_TIMEOUT = -11
+BD_E_SCRATCH = -12
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 BD_LAYOUT_CSR = 0
 BD_LAYOUT_FAT = 1
@@ -57,7 +59,8 @@ EXPORTS = ("graph_load_csr", "graph_free", "bd_graph_get_info", "bd_plan", "bd_q
            "bd_walk_trace", "bd_probe_eval", "bd_query_probes", "bd_server_create",
            "bd_server_submit", "bd_server_poll", "bd_server_wait", "bd_server_destroy",
            "bd_strerror", "bd_device_info", "bd_gather_roofline", "bd_autotune",
-           "bd_query_stabilized", "bd_truncated_beta", "bd_graph_lambda", "bd_theorem_L")
+           "bd_query_stabilized", "bd_truncated_beta", "bd_graph_lambda", "bd_theorem_L",
+           "bd_query_batch_noalloc")
 
 
 class BdPolicy(ctypes.Structure):
@@ -135,6 +138,8 @@ def lib():
             "bd_plan": (ctypes.c_int, [_P, i64, _P, _P, _P, _P, ctypes.POINTER(BdPolicy), _P]),
             "bd_query_batch": (ctypes.c_int, [_P, i64, _P, _P, _P, _P, _P, u64, ctypes.POINTER(BdPolicy),
                                               ctypes.POINTER(BdExec), _P, _P, ctypes.POINTER(BdStats)]),
+            "bd_query_batch_noalloc": (ctypes.c_int, [_P, i64, _P, _P, _P, _P, _P, u64, ctypes.POINTER(BdPolicy),
+                                                      ctypes.POINTER(BdExec), _P, _P, ctypes.POINTER(BdStats)]),
             "bd_walk_trace": (ctypes.c_int, [_P, i64, _P, _P, _P, _P, _P, i32, u64, _P, _P, _P]),
             "bd_probe_eval": (ctypes.c_int, [_P, u64, u32, u32, i64, _P, _P, _P, _P]),
             "bd_query_probes": (ctypes.c_int, [_P, i32, i32, ctypes.c_double, i32, u32, u64,
@@ -275,6 +280,22 @@ def bd_query_batch(g: Graph, s, t, eps, L, seed: int, pol: BdPolicy | None = Non
                                 seed & (2 ** 64 - 1), None if pol is None else ctypes.byref(pol),
                                 None if ex is None else ctypes.byref(ex), _stream(stream), _ptr(out),
                                 ctypes.byref(st)), "bd_query_batch")
+    return (out, st.as_dict()) if with_stats else out
+
+
+def bd_query_batch_noalloc(g: Graph, s, t, eps, L, seed: int, pol: BdPolicy | None = None,
+                           ex: BdExec | None = None, uid=None, stream=None, with_stats: bool = False):
+    """bd_query_batch with the library's fixed scratch array (no device allocation)."""
+    s, t = _arr(s, np.int32), _arr(t, np.int32)
+    eps = _arr(np.broadcast_to(eps, s.shape), np.float64)
+    L = _arr(np.broadcast_to(L, s.shape), np.int32)
+    u = None if uid is None else _arr(uid, np.uint32)
+    out = np.zeros(s.size, dtype=RESULT_DTYPE)
+    st = BdStats()
+    _check(lib().bd_query_batch_noalloc(g.handle, s.size, _ptr(s), _ptr(t), _ptr(eps), _ptr(L), _ptr(u),
+                                        seed & (2 ** 64 - 1), None if pol is None else ctypes.byref(pol),
+                                        None if ex is None else ctypes.byref(ex), _stream(stream), _ptr(out),
+                                        ctypes.byref(st)), "bd_query_batch_noalloc")
     return (out, st.as_dict()) if with_stats else out
 
 

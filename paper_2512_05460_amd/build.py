@@ -21,7 +21,7 @@ INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libprobewalk.so")
 
-SOURCES = ["pw_kernels.hip", "pw_host.cpp"]
+SOURCES = ["pw_kernels.hip", "pw_host.cpp", "pw_scratch.hip"]
 ARCH = "gfx950"
 
 

@@ -641,58 +641,105 @@ struct Batch {
     int share = 1;                      // kernel instance for the walk-sharing factor
 };
 
+// Device buffers of one batch: either the graph's workspace (grown on demand)
+// or a carving of the library's fixed scratch array (no allocation).
+struct WorkPtrs {
+    void *qd = nullptr, *chunks = nullptr, *bs = nullptr, *done = nullptr, *beta = nullptr, *cursor = nullptr,
+         *psum = nullptr, *pcount = nullptr, *qdbg = nullptr, *ydbg = nullptr;
+};
+
+// Bytes of each buffer a batch needs (in WorkPtrs order).
+void work_sizes(const Batch& b, bool qdbg, bool ydbg, size_t sz[10])
+{
+    const size_t nv = b.qd.size();
+    sz[0] = nv * sizeof(QueryDesc);
+    sz[1] = b.chunks.size() * sizeof(Chunk);
+    sz[2] = nv * (size_t)b.G * 16;
+    sz[3] = nv * 4;
+    sz[4] = nv * 8;
+    sz[5] = 2 * kMaxQueues * 4;
+    sz[6] = (size_t)b.split_probes * 32;
+    sz[7] = (size_t)b.split_probes * 4;
+    sz[8] = qdbg ? (size_t)b.qd[0].K * 8 : 0;
+    sz[9] = ydbg ? (size_t)b.G * 8 : 0;
+}
+
+int workspace_ptrs(Workspace& w, const Batch& b, bool qdbg, bool ydbg, WorkPtrs* wp)
+{
+    size_t sz[10];
+    work_sizes(b, qdbg, ydbg, sz);
+    DevBuf* bufs[10] = {&w.qd, &w.chunks, &w.bs, &w.done, &w.beta, &w.cursor, &w.psum, &w.pcount, &w.qdbg, &w.ydbg};
+    void** out[10] = {&wp->qd, &wp->chunks, &wp->bs, &wp->done, &wp->beta, &wp->cursor, &wp->psum, &wp->pcount,
+                      &wp->qdbg, &wp->ydbg};
+    for (int i = 0; i < 10; ++i) {
+        if (i >= 8 && sz[i] == 0) continue;
+        const int rc = w.ensure(*bufs[i], sz[i]);
+        if (rc != BD_OK) return rc;
+        *out[i] = bufs[i]->p;
+    }
+    return BD_OK;
+}
+
+// The buffers laid out one after another, each 256-byte aligned, inside
+// [base, base + cap). BD_E_SCRATCH when they do not fit.
+int carve_ptrs(void* base, size_t cap, const Batch& b, WorkPtrs* wp)
+{
+    size_t sz[10];
+    work_sizes(b, false, false, sz);
+    void** out[8] = {&wp->qd, &wp->chunks, &wp->bs, &wp->done, &wp->beta, &wp->cursor, &wp->psum, &wp->pcount};
+    size_t off = 0;
+    for (int i = 0; i < 8; ++i) {
+        const size_t need = std::max<size_t>(sz[i], 16);
+        if (need > cap || off > cap - need) return BD_E_SCRATCH;
+        *out[i] = static_cast<char*>(base) + off;
+        off += (need + 255) & ~(size_t)255;
+    }
+    return BD_OK;
+}
+
 // Run one set of valid queries: zero the tables, launch, read the results.
-// Work buffers live in the graph's workspace and are reused across calls. With
-// ex.use_graph (batched mode) the zeroing and the persistent launches are
-// captured once per launch shape into a hipGraph on a library-owned stream and
-// replayed; descriptors and chunk tables are copied in before each replay.
-int run_batch(bd_graph* g, const Batch& b, const bd_exec& ex, hipStream_t user_st,
-              std::vector<double>& beta, bd_stats* stats, double* q_dbg_host, double* y_dbg_host)
+// The work buffers are w (see WorkPtrs). With ex.use_graph (batched mode, and
+// only with the graph's own workspace, `owned`) the zeroing and the persistent
+// launches are captured once per launch shape into a hipGraph on a
+// library-owned stream and replayed; descriptors and chunk tables are copied
+// in before each replay. Without `owned` nothing is created: no events, so
+// stats->walk_kernel_ms stays 0.
+int run_batch(bd_graph* g, const Batch& b, const bd_exec& ex, hipStream_t user_st, const WorkPtrs& w,
+              bool owned, std::vector<double>& beta, bd_stats* stats, double* q_dbg_host, double* y_dbg_host)
 {
     const size_t nv = b.qd.size();
     if (nv == 0) return BD_OK;
     const size_t gdim = b.G;
-    Workspace& w = g->ws;
-    const bool graph_mode = ex.use_graph && ex.mode != BD_MODE_PLAIN && !q_dbg_host && !y_dbg_host;
-    if (graph_mode && !w.gstream && hipStreamCreateWithFlags(&w.gstream, hipStreamNonBlocking) != hipSuccess)
+    Workspace& ws = g->ws;
+    const bool graph_mode = owned && ex.use_graph && ex.mode != BD_MODE_PLAIN && !q_dbg_host && !y_dbg_host;
+    if (graph_mode && !ws.gstream && hipStreamCreateWithFlags(&ws.gstream, hipStreamNonBlocking) != hipSuccess)
         return BD_E_HIP;
-    hipStream_t st = graph_mode ? w.gstream : user_st;
-    int rc = w.ensure(w.qd, nv * sizeof(QueryDesc));
-    if (rc == BD_OK) rc = w.ensure(w.chunks, b.chunks.size() * sizeof(Chunk));
-    if (rc == BD_OK) rc = w.ensure(w.bs, nv * gdim * 16);
-    if (rc == BD_OK) rc = w.ensure(w.done, nv * 4);
-    if (rc == BD_OK) rc = w.ensure(w.beta, nv * 8);
-    if (rc == BD_OK) rc = w.ensure(w.cursor, 2 * kMaxQueues * 4);
-    if (rc == BD_OK) rc = w.ensure(w.psum, (size_t)b.split_probes * 32);
-    if (rc == BD_OK) rc = w.ensure(w.pcount, (size_t)b.split_probes * 4);
-    if (rc == BD_OK && q_dbg_host) rc = w.ensure(w.qdbg, (size_t)b.qd[0].K * 8);
-    if (rc == BD_OK && y_dbg_host) rc = w.ensure(w.ydbg, gdim * 8);
-    if (rc != BD_OK) return rc;
-    HIP_TRY(hipMemcpyAsync(w.qd.p, b.qd.data(), nv * sizeof(QueryDesc), hipMemcpyHostToDevice, st));
-    HIP_TRY(hipMemcpyAsync(w.chunks.p, b.chunks.data(), b.chunks.size() * sizeof(Chunk), hipMemcpyHostToDevice,
+    hipStream_t st = graph_mode ? ws.gstream : user_st;
+    HIP_TRY(hipMemcpyAsync(w.qd, b.qd.data(), nv * sizeof(QueryDesc), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(w.chunks, b.chunks.data(), b.chunks.size() * sizeof(Chunk), hipMemcpyHostToDevice,
                            st));
 
     WalkArgs a{};
     a.g = tables(g);
-    a.qd = w.qd.as<const QueryDesc>();
+    a.qd = static_cast<const QueryDesc*>(w.qd);
     a.gdim = (uint32_t)gdim;
-    a.cursor = w.cursor.as<uint32_t>();
-    a.blocksum = w.bs.as<unsigned long long>();
-    a.done = w.done.as<uint32_t>();
-    a.psum = w.psum.as<unsigned long long>();
-    a.pcount = w.pcount.as<uint32_t>();
-    a.beta = w.beta.as<double>();
-    a.q_debug = q_dbg_host ? w.qdbg.as<double>() : nullptr;
-    a.ybar_debug = y_dbg_host ? w.ydbg.as<double>() : nullptr;
+    a.cursor = static_cast<uint32_t*>(w.cursor);
+    a.blocksum = static_cast<unsigned long long*>(w.bs);
+    a.done = static_cast<uint32_t*>(w.done);
+    a.psum = static_cast<unsigned long long*>(w.psum);
+    a.pcount = static_cast<uint32_t*>(w.pcount);
+    a.beta = static_cast<double*>(w.beta);
+    a.q_debug = q_dbg_host ? static_cast<double*>(w.qdbg) : nullptr;
+    a.ybar_debug = y_dbg_host ? static_cast<double*>(w.ydbg) : nullptr;
     const int layout = g->layout;
 
     // the zeroing every launch needs
     auto zero_all = [&](hipStream_t s2) -> int {
-        if (launch_zero(w.bs.p, nv * gdim * 16, s2) != hipSuccess) return BD_E_HIP;
-        if (launch_zero(w.done.p, nv * 4, s2) != hipSuccess) return BD_E_HIP;
-        if (launch_zero(w.cursor.p, 2 * kMaxQueues * 4, s2) != hipSuccess) return BD_E_HIP;
-        if (launch_zero(w.psum.p, (size_t)b.split_probes * 32, s2) != hipSuccess) return BD_E_HIP;
-        if (launch_zero(w.pcount.p, (size_t)b.split_probes * 4, s2) != hipSuccess) return BD_E_HIP;
+        if (launch_zero(w.bs, nv * gdim * 16, s2) != hipSuccess) return BD_E_HIP;
+        if (launch_zero(w.done, nv * 4, s2) != hipSuccess) return BD_E_HIP;
+        if (launch_zero(w.cursor, 2 * kMaxQueues * 4, s2) != hipSuccess) return BD_E_HIP;
+        if (launch_zero(w.psum, (size_t)b.split_probes * 32, s2) != hipSuccess) return BD_E_HIP;
+        if (launch_zero(w.pcount, (size_t)b.split_probes * 4, s2) != hipSuccess) return BD_E_HIP;
         return BD_OK;
     };
     // the persistent launches of the batched mode: wave-uniform chunks, then the rest
@@ -707,9 +754,9 @@ int run_batch(bd_graph* g, const Batch& b, const bd_exec& ex, hipStream_t user_s
         for (int part = 0; part < 2; ++part) {
             if (grids[part] == 0) continue;
             WalkArgs ab = a;
-            ab.chunks = w.chunks.as<const Chunk>() + parts[part];
+            ab.chunks = static_cast<const Chunk*>(w.chunks) + parts[part];
             ab.nchunks = parts[part + 1] - parts[part];
-            ab.cursor = w.cursor.as<uint32_t>() + part * kMaxQueues;
+            ab.cursor = static_cast<uint32_t*>(w.cursor) + part * kMaxQueues;
             ab.persistent = 1;
             ab.nqueues = b.nqueues;
             for (uint32_t i = 0; i <= b.nqueues; ++i) ab.qoff[i] = b.qoff[part][i];
@@ -719,24 +766,27 @@ int run_batch(bd_graph* g, const Batch& b, const bd_exec& ex, hipStream_t user_s
     };
 
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    HIP_TRY(hipEventCreate(&e0));
-    if (hipEventCreate(&e1) != hipSuccess) {
-        (void)hipEventDestroy(e0);
-        return BD_E_HIP;
+    if (owned) {
+        HIP_TRY(hipEventCreate(&e0));
+        if (hipEventCreate(&e1) != hipSuccess) {
+            (void)hipEventDestroy(e0);
+            return BD_E_HIP;
+        }
     }
     double kernel_ms = 0.0;
     int64_t launches = 0;
     int status = BD_OK;
     auto timed = [&](auto&& body) -> int {
-        if (hipEventRecord(e0, st) != hipSuccess) return BD_E_HIP;
+        if (e0 && hipEventRecord(e0, st) != hipSuccess) return BD_E_HIP;
         const int r = body();
         if (r != BD_OK) return r;
+        ++launches;
+        if (!e0) return BD_OK;
         if (hipEventRecord(e1, st) != hipSuccess) return BD_E_HIP;
         if (hipEventSynchronize(e1) != hipSuccess) return BD_E_HIP;
         float ms = 0.f;
         if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return BD_E_HIP;
         kernel_ms += ms;
-        ++launches;
         return BD_OK;
     };
     if (ex.mode == BD_MODE_PLAIN) {
@@ -746,7 +796,7 @@ int run_batch(bd_graph* g, const Batch& b, const bd_exec& ex, hipStream_t user_s
             const uint32_t c0 = b.chunk_begin[q];
             const uint32_t c1 = q + 1 < nv ? b.chunk_begin[q + 1] : (uint32_t)b.chunks.size();
             WalkArgs aq = a;
-            aq.chunks = w.chunks.as<const Chunk>() + c0;
+            aq.chunks = static_cast<const Chunk*>(w.chunks) + c0;
             aq.nchunks = c1 - c0;
             aq.persistent = 0;
             const int uniform = b.qd[q].R >= kUniformMinR;
@@ -761,16 +811,16 @@ int run_batch(bd_graph* g, const Batch& b, const bd_exec& ex, hipStream_t user_s
         // key: everything the captured launches depend on
         std::vector<uint64_t> key = {nv, b.chunks.size(), b.n_uniform, b.split_probes, gdim, grids[0],
                                      grids[1], (uint64_t)layout, (uint64_t)b.share, b.nqueues,
-                                     (uint64_t)(uintptr_t)w.qd.p, (uint64_t)(uintptr_t)w.chunks.p,
-                                     (uint64_t)(uintptr_t)w.bs.p, (uint64_t)(uintptr_t)w.psum.p,
-                                     (uint64_t)(uintptr_t)w.pcount.p, (uint64_t)(uintptr_t)w.done.p,
-                                     (uint64_t)(uintptr_t)w.beta.p, (uint64_t)(uintptr_t)w.cursor.p};
+                                     (uint64_t)(uintptr_t)w.qd, (uint64_t)(uintptr_t)w.chunks,
+                                     (uint64_t)(uintptr_t)w.bs, (uint64_t)(uintptr_t)w.psum,
+                                     (uint64_t)(uintptr_t)w.pcount, (uint64_t)(uintptr_t)w.done,
+                                     (uint64_t)(uintptr_t)w.beta, (uint64_t)(uintptr_t)w.cursor};
         for (int part = 0; part < 2; ++part)
             for (uint32_t i = 0; i <= b.nqueues; ++i) key.push_back(b.qoff[part][i]);
-        if (!w.gexec || w.gkey != key) {
-            if (w.gexec) {
-                (void)hipGraphExecDestroy(w.gexec);
-                w.gexec = nullptr;
+        if (!ws.gexec || ws.gkey != key) {
+            if (ws.gexec) {
+                (void)hipGraphExecDestroy(ws.gexec);
+                ws.gexec = nullptr;
             }
             hipGraph_t graph = nullptr;
             HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
@@ -781,26 +831,26 @@ int run_batch(bd_graph* g, const Batch& b, const bd_exec& ex, hipStream_t user_s
                 if (graph) (void)hipGraphDestroy(graph);
                 return BD_E_HIP;
             }
-            const hipError_t ie = hipGraphInstantiate(&w.gexec, graph, nullptr, nullptr, 0);
+            const hipError_t ie = hipGraphInstantiate(&ws.gexec, graph, nullptr, nullptr, 0);
             (void)hipGraphDestroy(graph);
             if (ie != hipSuccess) {
-                w.gexec = nullptr;
+                ws.gexec = nullptr;
                 return BD_E_HIP;
             }
-            w.gkey = key;
-            ++w.graph_builds;
+            ws.gkey = key;
+            ++ws.graph_builds;
         }
-        status = timed([&] { return hipGraphLaunch(w.gexec, st) == hipSuccess ? BD_OK : BD_E_HIP; });
-        ++w.graph_replays;
+        status = timed([&] { return hipGraphLaunch(ws.gexec, st) == hipSuccess ? BD_OK : BD_E_HIP; });
+        ++ws.graph_replays;
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
     if (status != BD_OK) return status;
     beta.resize(nv);
-    HIP_TRY(hipMemcpyAsync(beta.data(), w.beta.p, nv * 8, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(beta.data(), w.beta, nv * 8, hipMemcpyDeviceToHost, st));
     if (q_dbg_host)
-        HIP_TRY(hipMemcpyAsync(q_dbg_host, w.qdbg.p, (size_t)b.qd[0].K * 8, hipMemcpyDeviceToHost, st));
-    if (y_dbg_host) HIP_TRY(hipMemcpyAsync(y_dbg_host, w.ydbg.p, gdim * 8, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(q_dbg_host, w.qdbg, (size_t)b.qd[0].K * 8, hipMemcpyDeviceToHost, st));
+    if (y_dbg_host) HIP_TRY(hipMemcpyAsync(y_dbg_host, w.ydbg, gdim * 8, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     if (stats) {
         stats->walk_kernel_ms += kernel_ms;
@@ -923,8 +973,58 @@ extern "C" int bd_query_batch(bd_graph* g, int64_t nq, const int32_t* s, const i
     Batch b;
     build_batch(g, nq, s, t, L, uid, seed, out, ex, policy_share(p), b);
     std::vector<double> beta;
-    const int rc = run_batch(g, b, ex, (hipStream_t)stream, beta, stats, nullptr, nullptr);
+    WorkPtrs wp;
+    int rc = b.qd.empty() ? BD_OK : workspace_ptrs(g->ws, b, false, false, &wp);
+    if (rc == BD_OK) rc = run_batch(g, b, ex, (hipStream_t)stream, wp, true, beta, stats, nullptr, nullptr);
     if (rc != BD_OK) return rc;
+    for (size_t q = 0; q < b.qd.size(); ++q) {
+        bd_result& r = out[b.index[q]];
+        r.beta = beta[q];
+        if (stats) {
+            stats->walk_steps += r.walk_steps;
+            const int64_t M = (int64_t)policy_share(p);
+            stats->walk_pairs += (int64_t)r.G * ((r.B + M - 1) / M) * r.R;
+        }
+    }
+    if (stats) stats->total_ms = now_ms() - t0;
+    return BD_OK;
+}
+
+static_assert(kScratchBytes == (size_t)BD_NOALLOC_SCRATCH_BYTES, "scratch size of the ABI");
+
+extern "C" int bd_query_batch_noalloc(bd_graph* g, int64_t nq, const int32_t* s, const int32_t* t,
+                                      const double* eps, const int32_t* L, const uint32_t* uid,
+                                      uint64_t seed, const bd_policy* pol, const bd_exec* exec, void* stream,
+                                      bd_result* out, bd_stats* stats)
+{
+    if (!g || nq < 0 || (nq > 0 && (!s || !t || !eps || !L || !out))) return BD_E_INVALID;
+    const double t0 = now_ms();
+    if (stats) std::memset(stats, 0, sizeof(*stats));
+    const bd_policy p = pol ? *pol : default_policy();
+    bd_exec ex{};
+    ex.mode = BD_MODE_BATCHED;
+    if (exec) ex = *exec;
+    ex.use_graph = 0;
+    for (int64_t i = 0; i < nq; ++i) {
+        plan_one(g, s[i], t[i], eps[i], L[i], p, &out[i]);
+        if (uid && uid[i] >= 0x80000000u) out[i].status = BD_E_INVALID;
+    }
+    Batch b;
+    build_batch(g, nq, s, t, L, uid, seed, out, ex, policy_share(p), b);
+    std::vector<double> beta;
+    if (!b.qd.empty()) {
+        int dev = -1;
+        HIP_TRY(hipGetDevice(&dev));
+        if (dev != g->device) return BD_E_INVALID;
+        void* base = nullptr;
+        std::unique_lock<std::mutex> held;
+        int rc = scratch_acquire(dev, &base, &held);
+        if (rc != BD_OK) return rc;
+        WorkPtrs wp;
+        rc = carve_ptrs(base, kScratchBytes, b, &wp);
+        if (rc == BD_OK) rc = run_batch(g, b, ex, (hipStream_t)stream, wp, false, beta, stats, nullptr, nullptr);
+        if (rc != BD_OK) return rc;
+    }
     for (size_t q = 0; q < b.qd.size(); ++q) {
         bd_result& r = out[b.index[q]];
         r.beta = beta[q];
@@ -954,7 +1054,9 @@ extern "C" int bd_query_probes(bd_graph* g, int32_t s, int32_t t, double eps, in
     Batch b;
     build_batch(g, 1, &s, &t, &L, &uid, seed, out, ex, policy_share(p), b);
     std::vector<double> beta;
-    const int rc = run_batch(g, b, ex, (hipStream_t)stream, beta, nullptr, q_out, ybar_out);
+    WorkPtrs wp;
+    int rc = workspace_ptrs(g->ws, b, q_out != nullptr, ybar_out != nullptr, &wp);
+    if (rc == BD_OK) rc = run_batch(g, b, ex, (hipStream_t)stream, wp, true, beta, nullptr, q_out, ybar_out);
     if (rc != BD_OK) return rc;
     out->beta = beta[0];
     return BD_OK;
@@ -1328,6 +1430,7 @@ extern "C" const char* bd_strerror(int code)
     case BD_E_FULL: return "request exceeds the admission caps";
     case BD_E_CANCELLED: return "request cancelled";
     case BD_E_TIMEOUT: return "timed out";
+    case BD_E_SCRATCH: return "batch exceeds the fixed scratch array of the allocation-free entry point";
     default: return "unknown error";
     }
 }

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+
 namespace pw {
 
 // One query as the device sees it (Algorithm 1 inputs and parameters).
@@ -135,5 +137,11 @@ hipError_t launch_nmul(const uint32_t* rp, const uint32_t* col, const uint32_t* 
                        double* y, hipStream_t st);
 // Work groups of the walk kernel that fit on the device at once.
 int walk_occupancy(int layout, int uniform, int share, int* wgs_per_cu);
+
+// Bytes of the fixed device scratch array (pw_scratch.hip).
+constexpr size_t kScratchBytes = size_t(64) << 20;
+// Device address of `device`'s scratch array (resolved on first use, with that
+// device current) and that device's scratch lock, held by *held on success.
+int scratch_acquire(int device, void** base, std::unique_lock<std::mutex>* held);
 
 }  // namespace pw
