@@ -16,9 +16,15 @@
  *     the duration of the call only; the library keeps no reference to them.
  *   - "stream" is a hipStream_t passed as void* (NULL = the null stream). The
  *     calls enqueue work on it and synchronise it before they return, except
- *     where stated. The library owns the device memory it allocates (graph
- *     tables, per-call work buffers) and frees it in graph_free /
- *     bd_server_destroy.
+ *     where stated.
+ *   - Device memory. The library holds the device memory of the graph tables,
+ *     the per-graph work buffers (grown on demand) and the server arenas, and
+ *     frees it in graph_free / bd_server_destroy. It takes that memory from
+ *     the allocator installed with bd_set_allocator (for example PyTorch's
+ *     caching allocator), else from hipMalloc; each buffer is returned to the
+ *     allocator it came from. Inputs are never retained: graph_load_csr
+ *     copies the caller's CSR (host arrays, or device arrays with
+ *     BD_DEVICE_PTRS) into tables of its own.
  *   - Random streams depend only on (seed, uid, k, p, side, step): a query's
  *     result is bit-identical whatever batch, mode, chunking or server
  *     traffic it runs in.
@@ -86,6 +92,11 @@ typedef struct bd_graph bd_graph;
                                    take 4 bytes (layout code 4) */
 #define BD_WIDE_IDS        16u  /* with BD_LAYOUT_COMPACT | BD_RELABEL_DEGREE: 4-byte
                                    neighbour ids (layout code 4) at any n */
+#define BD_DEVICE_PTRS     64u  /* row_ptr and col_idx are device pointers on the current
+                                   device (e.g. the data of PyTorch tensors) instead of host
+                                   arrays; they are read once, on `stream`, and not kept.
+                                   BD_E_INVALID if either is not device memory of the
+                                   current device */
 #define BD_LAYOUT_AUTO     32u  /* the library picks: BD_LAYOUT_COMPACT | BD_RELABEL_DEGREE
                                    when those tables take at most 12 MiB (measured
                                    crossover), else BD_LAYOUT_FAT (with BD_RELABEL_DEGREE only if
@@ -107,12 +118,15 @@ typedef struct {
  * Load a graph (section 2.1: connected, undirected, simple) and keep it
  * resident on the current device.
  *   n        number of nodes.
- *   row_ptr  host, n+1 int64 offsets, row_ptr[0] = 0, nondecreasing.
- *   col_idx  host, row_ptr[n] int32 neighbour ids; each row ascending, no
- *            self-loops, no repeats, and the adjacency symmetric. The order of
+ *   row_ptr  n+1 int64 offsets (host, or device with BD_DEVICE_PTRS),
+ *            row_ptr[0] = 0, nondecreasing.
+ *   col_idx  row_ptr[n] int32 neighbour ids (host, or device with
+ *            BD_DEVICE_PTRS); each row ascending, no self-loops, no repeats,
+ *            and the adjacency symmetric. The order of
  *            a row is part of the contract: the walk's neighbour index j
  *            selects col_idx[row_ptr[x] + j].
- *   flags    BD_LAYOUT_* | BD_RELABEL_DEGREE | BD_WIDE_IDS | BD_SKIP_VALIDATION.
+ *   flags    BD_LAYOUT_* | BD_RELABEL_DEGREE | BD_WIDE_IDS | BD_SKIP_VALIDATION |
+ *            BD_DEVICE_PTRS.
  *   out      receives the handle; release with graph_free.
  * Errors: BD_E_GRAPH if a check fails (disconnected, asymmetric, unsorted,
  * self-loop), BD_E_RANGE for sizes beyond the limits, BD_E_INVALID for
@@ -120,6 +134,31 @@ typedef struct {
  */
 int  graph_load_csr(int64_t n, const int64_t* row_ptr, const int32_t* col_idx,
                     uint32_t flags, void* stream, bd_graph** out);
+
+/*
+ * Device allocator of the library's buffers. alloc returns `bytes` of device
+ * memory of the current device (NULL on failure, reported as BD_E_NOMEM);
+ * free returns a pointer alloc gave, with its size. `stream` is passed as
+ * NULL: the library synchronises its own work on a buffer before freeing it.
+ * ctx is passed back unchanged. Both functions may be called from any thread
+ * that calls into the library (not from the server's scheduler thread, which
+ * allocates nothing).
+ */
+typedef struct {
+    void* ctx;
+    void* (*alloc)(void* ctx, size_t bytes, void* stream);
+    void  (*free)(void* ctx, void* ptr, size_t bytes, void* stream);
+} bd_allocator;
+
+/*
+ * Install the allocator for every device buffer allocated from now on (graph
+ * tables, work buffers, server arenas, temporaries of the validation and
+ * reference entry points); NULL restores hipMalloc/hipFree. Buffers already
+ * allocated keep the allocator they came from, which must stay usable until
+ * they are freed. BD_E_INVALID if a is not NULL and a function is missing.
+ */
+int  bd_set_allocator(const bd_allocator* a);
+
 void graph_free(bd_graph* g);
 int  bd_graph_get_info(const bd_graph* g, bd_graph_info* info);
 

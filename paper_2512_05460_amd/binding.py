@@ -12,12 +12,21 @@ PyTorch ships its own HIP runtime under the same SONAME as the system one.
 ``lib()`` imports torch before loading ``libprobewalk.so`` so that the
 library binds to the runtime torch already loaded: one HIP runtime per
 process, in which torch's streams and our calls live together.
+
+Device memory: ``lib()`` installs PyTorch's caching allocator as the library's
+allocator (``bd_set_allocator``), so graph tables, work buffers and server
+arenas come from torch's pool and show in ``torch.cuda.memory_allocated()``.
+``use_torch_allocator(False)`` switches back to the library's own hipMalloc for
+buffers allocated afterwards. Objects still alive at interpreter exit are freed
+by an exit hook while torch is still usable.
 """
 
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import weakref
 
 import numpy as np
 
@@ -46,6 +55,7 @@ BD_RELABEL_DEGREE = 4
 BD_LAYOUT_COMPACT = 8
 BD_WIDE_IDS = 16
 BD_LAYOUT_AUTO = 32
+BD_DEVICE_PTRS = 64
 
 BD_POLICY_PAPER = 0
 BD_POLICY_SCALED = 1
@@ -60,7 +70,7 @@ EXPORTS = ("graph_load_csr", "graph_free", "bd_graph_get_info", "bd_plan", "bd_q
            "bd_server_submit", "bd_server_poll", "bd_server_wait", "bd_server_destroy",
            "bd_strerror", "bd_device_info", "bd_gather_roofline", "bd_autotune",
            "bd_query_stabilized", "bd_truncated_beta", "bd_graph_lambda", "bd_theorem_L",
-           "bd_query_batch_noalloc")
+           "bd_query_batch_noalloc", "bd_set_allocator")
 
 
 class BdPolicy(ctypes.Structure):
@@ -104,6 +114,14 @@ class BdServerCfg(ctypes.Structure):
     _fields_ = [("policy", BdPolicy), ("max_queries_inflight", ctypes.c_int64),
                 ("max_steps_inflight", ctypes.c_uint64), ("chunk_probes", ctypes.c_int32),
                 ("slice_ms", ctypes.c_double)]
+
+
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+
+
+class BdAllocator(ctypes.Structure):
+    _fields_ = [("ctx", ctypes.c_void_p), ("alloc", _ALLOC_FN), ("free", _FREE_FN)]
 
 
 RESULT_DTYPE = np.dtype([("beta", "f8"), ("K", "i8"), ("R", "i8"), ("B", "i4"), ("G", "i4"),
@@ -162,12 +180,53 @@ def lib():
             "bd_autotune": (ctypes.c_int, [_P, i64, _P, _P, _P, _P, u64, ctypes.POINTER(BdPolicy), u32, _P,
                                            ctypes.POINTER(BdExec), _P, ctypes.POINTER(i32)]),
         }
+        sig["bd_set_allocator"] = (ctypes.c_int, [ctypes.POINTER(BdAllocator)])
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
             fn.restype = res
             fn.argtypes = args
         _lib = L
+        use_torch_allocator(True)
+        # registered after torch's import, so it runs before torch's own exit hooks
+        atexit.register(_free_live_objects)
     return _lib
+
+
+# --- device memory from PyTorch's caching allocator ------------------------------
+def _torch_alloc(ctx, nbytes, stream):
+    import torch
+    try:
+        return torch.cuda.caching_allocator_alloc(int(nbytes), device=torch.cuda.current_device(),
+                                                  stream=stream if stream else None)
+    except Exception:  # reported to the library as a failed allocation (BD_E_NOMEM)
+        return None
+
+
+def _torch_free(ctx, ptr, nbytes, stream):
+    import torch
+    torch.cuda.caching_allocator_delete(ptr)
+
+
+_TORCH_ALLOCATOR = BdAllocator(None, _ALLOC_FN(_torch_alloc), _FREE_FN(_torch_free))
+_live = weakref.WeakSet()  # graphs and servers, freed at exit while torch still works
+_torch_alloc_on = False
+
+
+def use_torch_allocator(enable: bool = True):
+    """Take the library's device buffers allocated from now on from PyTorch's
+    caching allocator (True) or from the library's own hipMalloc (False)."""
+    global _torch_alloc_on
+    L = _lib if _lib is not None else lib()
+    _check(L.bd_set_allocator(ctypes.byref(_TORCH_ALLOCATOR) if enable else None), "bd_set_allocator")
+    _torch_alloc_on = enable
+
+
+def _free_live_objects():
+    for obj in [o for o in list(_live) if isinstance(o, Server)] + [o for o in list(_live) if isinstance(o, Graph)]:
+        try:
+            obj.free() if isinstance(obj, Graph) else obj.destroy()
+        except Exception:
+            pass
 
 
 def strerror(code: int) -> str:
@@ -215,6 +274,7 @@ class Graph:
 
     def __init__(self, handle):
         self._h = handle
+        _live.add(self)
 
     @property
     def handle(self):
@@ -245,6 +305,23 @@ def graph_load_csr(n: int, row_ptr, col_idx, flags: int = BD_LAYOUT_CSR, stream=
     h = _P()
     _check(lib().graph_load_csr(n, _ptr(rp), _ptr(col), flags, _stream(stream), ctypes.byref(h)),
            "graph_load_csr")
+    return Graph(h)
+
+
+def graph_load_csr_device(n: int, row_ptr, col_idx, flags: int = BD_LAYOUT_CSR, stream=None) -> Graph:
+    """graph_load_csr with BD_DEVICE_PTRS: row_ptr (int64, n+1) and col_idx
+    (int32) are torch tensors on the current device."""
+    import torch
+    if row_ptr.dtype != torch.int64 or col_idx.dtype != torch.int32:
+        raise TypeError("row_ptr must be int64 and col_idx int32")
+    if not (row_ptr.is_cuda and col_idx.is_cuda):
+        raise ValueError("row_ptr and col_idx must be device tensors")
+    rp, col = row_ptr.contiguous(), col_idx.contiguous()
+    if rp.numel() != n + 1:
+        raise ValueError("row_ptr must have n+1 entries")
+    h = _P()
+    _check(lib().graph_load_csr(n, rp.data_ptr(), col.data_ptr(), flags | BD_DEVICE_PTRS, _stream(stream),
+                                ctypes.byref(h)), "graph_load_csr")
     return Graph(h)
 
 
@@ -350,6 +427,7 @@ class Server:
         _check(lib().bd_server_create(g.handle, ctypes.byref(cfg), ctypes.byref(h)), "bd_server_create")
         self._h = h
         self._sizes = {}
+        _live.add(self)
 
     def submit(self, s, t, eps, L, seed: int, uid=None) -> int:
         s, t = _arr(s, np.int32), _arr(t, np.int32)

@@ -42,17 +42,33 @@ constexpr int64_t kAutoCompactBytes = int64_t(12) << 20;
         if (e_ != hipSuccess) return BD_E_HIP;         \
     } while (0)
 
-// Device allocation owned by the library.
+// The process-wide device allocator (bd_set_allocator): hipMalloc/hipFree
+// unless the caller installed its own.
+std::mutex g_alloc_mu;
+bd_allocator g_alloc{};
+
+bd_allocator current_allocator()
+{
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    return g_alloc;
+}
+
+// Device allocation owned by the library, released through the allocator it
+// came from.
 struct DevBuf {
     void* p = nullptr;
     size_t bytes = 0;
+    bd_allocator al{};
     DevBuf() = default;
     DevBuf(const DevBuf&) = delete;
     DevBuf& operator=(const DevBuf&) = delete;
     ~DevBuf() { release(); }
     void release()
     {
-        if (p) (void)hipFree(p);
+        if (p) {
+            if (al.free) al.free(al.ctx, p, bytes, nullptr);
+            else (void)hipFree(p);
+        }
         p = nullptr;
         bytes = 0;
     }
@@ -60,7 +76,12 @@ struct DevBuf {
     {
         release();
         if (b == 0) b = 16;
-        if (hipMalloc(&p, b) != hipSuccess) {
+        b = (b + 255) & ~(size_t)255;
+        al = current_allocator();
+        if (al.alloc) {
+            p = al.alloc(al.ctx, b, nullptr);
+            if (!p) return BD_E_NOMEM;
+        } else if (hipMalloc(&p, b) != hipSuccess) {
             p = nullptr;
             (void)hipGetLastError();
             return BD_E_NOMEM;
@@ -190,7 +211,43 @@ int validate(int64_t n, const int64_t* rp, const int32_t* col, int32_t* bip)
     return BD_OK;
 }
 
+// The caller's arrays when they live in device memory (BD_DEVICE_PTRS): checked
+// to be device allocations of the current device, then read once into host
+// copies for validation and layout building.
+int fetch_device_csr(int64_t n, const int64_t* row_ptr, const int32_t* col_idx, hipStream_t st,
+                     std::vector<int64_t>& rp, std::vector<int32_t>& col)
+{
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    for (const void* ptr : {(const void*)row_ptr, (const void*)col_idx}) {
+        hipPointerAttribute_t at{};
+        if (hipPointerGetAttributes(&at, ptr) != hipSuccess) {
+            (void)hipGetLastError();
+            return BD_E_INVALID;
+        }
+        if (at.type != hipMemoryTypeDevice || at.device != dev) return BD_E_INVALID;
+    }
+    rp.resize((size_t)n + 1);
+    HIP_TRY(hipMemcpyAsync(rp.data(), row_ptr, rp.size() * 8, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    const int64_t nnz = rp[(size_t)n];
+    if (rp[0] != 0 || nnz < 0) return BD_E_GRAPH;
+    if (nnz > kMaxNnz) return BD_E_RANGE;
+    col.resize((size_t)std::max<int64_t>(nnz, 1));
+    if (nnz) HIP_TRY(hipMemcpyAsync(col.data(), col_idx, (size_t)nnz * 4, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return BD_OK;
+}
+
 }  // namespace
+
+extern "C" int bd_set_allocator(const bd_allocator* a)
+{
+    if (a && (!a->alloc || !a->free)) return BD_E_INVALID;
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    g_alloc = a ? *a : bd_allocator{};
+    return BD_OK;
+}
 
 extern "C" int graph_load_csr(int64_t n, const int64_t* row_ptr, const int32_t* col_idx,
                               uint32_t flags, void* stream, bd_graph** out)
@@ -198,6 +255,15 @@ extern "C" int graph_load_csr(int64_t n, const int64_t* row_ptr, const int32_t* 
     if (!out || !row_ptr || !col_idx) return BD_E_INVALID;
     *out = nullptr;
     if (n < 2 || n > kMaxN) return BD_E_RANGE;
+    std::vector<int64_t> rp_host;
+    std::vector<int32_t> col_host;
+    if (flags & BD_DEVICE_PTRS) {
+        const int rc = fetch_device_csr(n, row_ptr, col_idx, (hipStream_t)stream, rp_host, col_host);
+        if (rc != BD_OK) return rc;
+        row_ptr = rp_host.data();
+        col_idx = col_host.data();
+        flags &= ~BD_DEVICE_PTRS;
+    }
     if (row_ptr[0] != 0) return BD_E_GRAPH;
     const int64_t nnz = row_ptr[n];
     if (nnz < 0 || nnz > kMaxNnz) return BD_E_RANGE;
