@@ -312,6 +312,8 @@ def grid_minus_edges(side: int, frac: float, seed: int) -> Csr:
 GRAPH_SEED = 0x5EED0000
 QUERY_SEED_OFFSET = 0x100
 PHILOX_SEED = 0x0B1A5ED5EED
+# Philox key of the walk-count calibration runs; no test or benchmark uses it
+CALIBRATION_SEED = 0x0CA11B7A7E5E
 
 # The five workload graphs. Key -> (builder, description).
 WORKLOADS = {

@@ -1,0 +1,27 @@
+"""Host logic of the walk-count calibration (paper_2512_05460_amd/calibrate.py):
+the estimate for a smaller B formed from the per-probe values of a run at a
+larger B equals the oracle's own estimate at that smaller B, bit for bit
+(Q_k depends on k and R, not on B), for odd and even G."""
+
+import numpy as np
+import pytest
+
+from oracle import estimator as E
+from oracle import planner as OP
+from paper_2512_05460_amd.calibrate import median_of_means
+from synth import graphs
+
+
+@pytest.mark.parametrize("delta", [0.01, 0.3])  # G = 37 (odd) and G = 10 (even)
+def test_smaller_B_from_larger_run(delta):
+    g = graphs.barabasi_albert(200, 3, 11)
+    s, t, L, seed = 3, 150, 12, 0x77
+    big = OP.Policy("fixed", B_fixed=12, R_fixed=20, delta=delta)
+    plan = OP.plan(0.1, L, 1, 1, 1, big)
+    beta, q, y = E.estimate(g, [s], [t], L, [plan], seed, uid=[5], want_q=True)
+    G = plan[1]
+    assert median_of_means(q, 12, G) == beta[0]
+    for b in (1, 2, 5, 7):
+        small = OP.plan(0.1, L, 1, 1, 1, OP.Policy("fixed", B_fixed=b, R_fixed=20, delta=delta))
+        ref = E.estimate(g, [s], [t], L, [small], seed, uid=[5])[0]
+        assert median_of_means(q, b, G) == ref
