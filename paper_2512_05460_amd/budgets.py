@@ -37,12 +37,23 @@ BUDGETS = {
     "grid1414@5000": (0.64, 16.0 / 5001 ** 2, "calibrated: 96.9% of 96 queries within eps (calibration seed)"),
     # Chung-Lu n=1e7 (served requests of 1-4,096 pairs), eps in {.02,.05,.1},
     # L=1000: B = 100/16/4 and R median 3 (up to ~1,800 for hub pairs), a
-    # throughput setting for the serving measurement, not calibrated.
+    # throughput setting for the serving measurement, not calibrated: about
+    # 1/150 of the calibrated walk count below.
     "cl10m": (0.04, 128.0 / 2 ** 28, "throughput setting, not calibrated"),
+    # The same graph at L = 1000, calibrated against binary64 CG distances of
+    # 64 pairs (tests/golden) at eps = 0.05 (calibration seed, one run per c_R
+    # with every B of the ladder from its per-probe values): B = 384 at
+    # R median 717 (max 36,201) put all 64 within eps (B = 256: 93.8%; c_R/2
+    # with B = 512: 95.3%); 6.6e10 walk steps per query on average.
+    "cl10m@1000": (0.96, 128.0 / 2 ** 20, "calibrated: 100% of 64 pairs within eps (calibration seed)"),
     # Chung-Lu n=4e7 (1e9 adjacency entries), eps=0.05, L in {1000, 10000}:
     # B = 1 (K = 37) and R = 2 for most pairs (up to ~6,000 for hub pairs), a
     # throughput setting for the full 262,144-query set, not calibrated.
     "cl40m": (0.0025, 128.0 / 2 ** 37, "throughput setting, not calibrated"),
+    # The same graph at L = 1000, calibrated as cl10m@1000 on its 64 reference
+    # pairs: B = 256 at R median 516 (max 6,995) put 98.4% within eps (B = 192:
+    # 92.2%; c_R/2 with B = 512: 92.2%); 2.0e10 walk steps per query on average.
+    "cl40m@1000": (0.64, 128.0 / 2 ** 22, "calibrated: 98.4% of 64 pairs within eps (calibration seed)"),
 }
 
 

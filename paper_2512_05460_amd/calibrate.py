@@ -99,6 +99,17 @@ def calibrate(dg, s, t, beta_ref, eps: float, L, seed: int, c_B_ladder, c_R_ladd
     return best, table
 
 
+def load_reference(path: str) -> dict:
+    """The columns of a reference file by name: its "# index s t ..." comment
+    line names the whitespace-separated columns of the data rows."""
+    with open(path) as f:
+        names = [ln for ln in f if ln.startswith("# index")][0][1:].split()
+    data = np.loadtxt(path, comments="#", ndmin=2)
+    if data.shape[1] != len(names):
+        raise ValueError(f"{path}: {len(names)} column names for {data.shape[1]} columns")
+    return {name: data[:, i] for i, name in enumerate(names)}
+
+
 def main(argv=None):
     from synth import graphs  # seeded workload inputs
 
@@ -120,27 +131,24 @@ def main(argv=None):
     def log(*x):
         print(*x, flush=True)
 
-    ref = np.loadtxt(a.ref, comments="#", ndmin=2)
-    with open(a.ref) as f:
-        header = [ln for ln in f if ln.startswith("# index")][0].split()[1:]
-    col = {name: i - 1 for i, name in enumerate(header)}
-    has_L = "L" in col
-    sel = np.ones(ref.shape[0], dtype=bool)
+    ref = load_reference(a.ref)
+    sel = np.ones(ref["index"].size, dtype=bool)
     if a.only_L:
-        sel &= ref[:, col["L"]] == a.only_L
+        sel &= ref["L"] == a.only_L
     idx = np.flatnonzero(sel)
     if a.pairs:
         idx = idx[:a.pairs]
-    s = ref[idx, col["s"]].astype(np.int32)
-    t = ref[idx, col["t"]].astype(np.int32)
-    beta = ref[idx, col["beta_cg"]]
-    L = np.full(idx.size, a.L, dtype=np.int32) if a.L or not has_L else ref[idx, col["L"]].astype(np.int32)
-    uid = ref[idx, col["index"]].astype(np.int64)
+    s = ref["s"][idx].astype(np.int32)
+    t = ref["t"][idx].astype(np.int32)
+    beta = ref["beta_cg"][idx]
+    L = np.full(idx.size, a.L, dtype=np.int32) if a.L or "L" not in ref else ref["L"][idx].astype(np.int32)
+    uid = ref["index"][idx].astype(np.int64)
     t0 = time.time()
     g = graphs.workload_graph(a.workload)
     dg = B.graph_load_csr(g.n, g.row_ptr, g.col, a.layout)
     log(f"{a.workload}: {idx.size} pairs, eps={a.eps}, L {sorted(set(L.tolist()))}, seed {a.seed:#x} "
-        f"(graph {time.time() - t0:.1f} s)")
+        f"(graph {time.time() - t0:.1f} s); first pairs (s, t, beta): "
+        f"{[(int(x), int(y), float(z)) for x, y, z in zip(s[:3], t[:3], beta[:3])]}")
     best, table = calibrate(dg, s, t, beta, a.eps, L, a.seed, a.c_B, a.c_R, a.target, uid=uid, log=log)
     log(json.dumps({"best": best}))
     if a.json:

@@ -40,6 +40,7 @@ def test_stated_block_sizes():
     assert [_B("cl10m", e) for e in (0.02, 0.05, 0.1)] == [100, 16, 4]
     assert [_B("grid1414", e) for e in (0.02, 0.05, 0.1)] == [16, 3, 1]
     assert _B("cl40m", 0.05) == 1
+    assert _B("cl10m@1000", 0.05) == 384 and _B("cl40m@1000", 0.05) == 256
     assert _B("grid1414@2000", 0.05) == 256
     M, c_B, _, _ = SHARED_BUDGETS["cl100k"]
     assert OP.plan(0.05, 1000, 1, 1, 1, OP.Policy("scaled", c_B=c_B, c_R=1.0))[0] == 384
@@ -70,3 +71,17 @@ def test_calibrated_budgets_on_their_pairs(key, count, B_, R_median):
              for i in range(count)]
     assert {p[0] for p in plans} == {B_}
     assert np.median([p[3] for p in plans]) == R_median
+
+
+@pytest.mark.parametrize("key,B_,R_median,R_max", [("cl10m", 384, 716.5, 36201), ("cl40m", 256, 515.5, 6995)])
+def test_large_graph_budgets_on_their_reference_pairs(key, B_, R_median, R_max):
+    # the 64 CG reference pairs of the two large graphs (d_min = 1), L = 1000
+    from paper_2512_05460_amd.calibrate import load_reference
+
+    ref = load_reference(os.path.join(os.path.dirname(__file__), "golden", f"{key}_cg_reference.txt"))
+    c_B, c_R, _ = BUDGETS[f"{key}@1000"]
+    pol = OP.Policy("scaled", c_B=c_B, c_R=c_R)
+    plans = [OP.plan(0.05, 1000, int(a), int(b), 1, pol) for a, b in zip(ref["d_s"], ref["d_t"])]
+    assert {p[0] for p in plans} == {B_}
+    R = [p[3] for p in plans]
+    assert np.median(R) == R_median and max(R) == R_max

@@ -25,3 +25,20 @@ def test_smaller_B_from_larger_run(delta):
         small = OP.plan(0.1, L, 1, 1, 1, OP.Policy("fixed", B_fixed=b, R_fixed=20, delta=delta))
         ref = E.estimate(g, [s], [t], L, [small], seed, uid=[5])[0]
         assert median_of_means(q, b, G) == ref
+
+
+def test_reference_columns_by_name():
+    import os
+
+    from paper_2512_05460_amd.calibrate import load_reference
+    here = os.path.join(os.path.dirname(__file__), "golden")
+    for key in ("cl10m", "cl40m", "cl100k"):
+        ref = load_reference(os.path.join(here, f"{key}_cg_reference.txt"))
+        assert np.array_equal(ref["index"], np.arange(ref["index"].size))
+        assert np.all(ref["s"] != ref["t"]) and np.all(ref["d_s"] >= 1)
+        assert np.all((ref["beta_cg"] > 0) & (ref["beta_cg"] < 10))
+        assert np.allclose(ref["beta_2nd"], ref["beta_cg"], rtol=1e-10)
+        # Lemma 3.5: beta >= (1/8)(1/d_s + 1/d_t)^2
+        assert np.all(ref["beta_cg"] >= (1.0 / ref["d_s"] + 1.0 / ref["d_t"]) ** 2 / 8)
+    ref = load_reference(os.path.join(here, "cl40m_cg_reference.txt"))
+    assert set(np.unique(ref["L"])) == {1000.0, 10000.0}

@@ -139,3 +139,42 @@ def test_gather_roofline_runs():
     r = B.bd_gather_roofline(dg, 4, 500)
     _say(f"[roofline] {r}")
     assert r["steps"] > 0 and r["steps_per_s"] > 1e9
+
+
+def _large_accuracy(key, L_values, budget_key):
+    # the 64 reference pairs of tests/golden (binary64 CG in plain torch, two
+    # solves; truncation gap at L = 1000 below 4e-14), eps = 0.05, test seed
+    from paper_2512_05460_amd.calibrate import load_reference
+    ref = load_reference(os.path.join(os.path.dirname(__file__), "golden", f"{key}_cg_reference.txt"))
+    assert np.allclose(ref["beta_2nd"], ref["beta_cg"], rtol=1e-10)
+    g = graphs.workload_graph(key)
+    s = ref["s"].astype(np.int32)
+    t = ref["t"].astype(np.int32)
+    assert np.array_equal(ref["d_s"], g.deg[s]) and np.array_equal(ref["d_t"], g.deg[t])
+    dg = B.graph_load_csr(g.n, g.row_ptr, g.col, B.BD_LAYOUT_AUTO)
+    hits, total = 0, 0
+    for L in L_values:
+        pol = budget_policy(f"{budget_key}@{L}")
+        res, st = B.bd_query_batch(dg, s, t, 0.05, L, SEED, pol, B.exec_cfg("batched"),
+                                   uid=ref["index"].astype(np.uint32), with_stats=True)
+        assert np.all(res["status"] == 0)
+        err = np.abs(res["beta"] - ref["beta_cg"]) / ref["beta_cg"]
+        ok = err <= 0.05
+        _say(f"[{key}] L={L}: within eps {ok.mean():.3f}, median rel err {np.median(err):.4f}, "
+             f"R median {int(np.median(res['R']))}, {st['walk_steps']:.3e} steps in {st['walk_kernel_ms']:.0f} ms")
+        hits += int(ok.sum())
+        total += ok.size
+    dg.free()
+    return hits, total
+
+
+@pytest.mark.timeout(900)
+def test_accuracy_cl10m():
+    hits, total = _large_accuracy("cl10m", (1000,), "cl10m")
+    assert hits >= 0.95 * total
+
+
+@pytest.mark.timeout(900)
+def test_accuracy_cl40m():
+    hits, total = _large_accuracy("cl40m", (1000,), "cl40m")
+    assert hits >= 0.95 * total
