@@ -65,7 +65,8 @@ extern "C" {
 #define BD_E_NOTFOUND -8  /* unknown server request id */
 #define BD_E_FULL     -9  /* server admission refused: request exceeds the caps */
 #define BD_E_CANCELLED -10 /* server destroyed before the request finished */
-#define BD_E_TIMEOUT  -11 /* bd_server_wait timed out; the request is still running */
+#define BD_E_TIMEOUT  -11 /* bd_server_wait timed out (the request is still running); per
+                             query: abandoned at the bd_exec deadline */
 #define BD_E_SCRATCH  -12 /* bd_query_batch_noalloc: the batch needs more than the fixed
                              scratch array holds (BD_NOALLOC_SCRATCH_BYTES) */
 
@@ -92,6 +93,23 @@ typedef struct bd_graph bd_graph;
                                    take 4 bytes (layout code 4) */
 #define BD_WIDE_IDS        16u  /* with BD_LAYOUT_COMPACT | BD_RELABEL_DEGREE: 4-byte
                                    neighbour ids (layout code 4) at any n */
+#define BD_PROBE_STORAGE_IDS 128u /* with BD_LAYOUT_COMPACT | BD_RELABEL_DEGREE (n <= 2^24; not
+                                   with BD_WIDE_IDS): the probe is evaluated on the storage id,
+                                   the node's rank in descending degree (ties by id), instead
+                                   of the caller's id. Algorithm 1 on the relabelled graph:
+                                   rows keep the caller's neighbour order, so the walks are
+                                   the same, and a uniformly random probe composed with a
+                                   fixed relabelling is again one, but the bits of every
+                                   result follow the relabelled ids. Node entries shrink to
+                                   the 4-byte row offset and the 16,384 highest-degree ones
+                                   are staged in LDS (layout code 5). bd_walk_trace still
+                                   reports caller ids */
+#define BD_NONTEMPORAL    256u  /* with BD_LAYOUT_FAT: read the adjacency entries with
+                                   non-temporal loads at any size (same results) */
+#define BD_TEMPORAL       512u  /* with BD_LAYOUT_FAT: ordinary loads at any size. Without
+                                   either flag the fat layout uses non-temporal loads when
+                                   its tables take at least 4 GiB (16x the Infinity Cache:
+                                   measured +9.5% at 20.7 GB, -3.5% at 2.2 GB) */
 #define BD_DEVICE_PTRS     64u  /* row_ptr and col_idx are device pointers on the current
                                    device (e.g. the data of PyTorch tensors) instead of host
                                    arrays; they are read once, on `stream`, and not kept.
@@ -110,8 +128,11 @@ typedef struct {
     int32_t  bipartite;      /* 1 if the graph is bipartite (section 2.1 assumes not;
                                 the estimator still targets beta^(L)) */
     int32_t  layout;         /* 0 CSR, 1 fat, 2 compact, 3 compact with hubs first,
-                                4 hubs first with 4-byte neighbour ids */
+                                4 hubs first with 4-byte neighbour ids, 5 hubs first with
+                                the probe on storage ids */
     int64_t  device_bytes;   /* device memory held by the graph tables */
+    int32_t  nontemporal;    /* 1 if the fat layout reads its entries with non-temporal loads */
+    int32_t  reserved;
 } bd_graph_info;
 
 /*
@@ -126,7 +147,7 @@ typedef struct {
  *            a row is part of the contract: the walk's neighbour index j
  *            selects col_idx[row_ptr[x] + j].
  *   flags    BD_LAYOUT_* | BD_RELABEL_DEGREE | BD_WIDE_IDS | BD_SKIP_VALIDATION |
- *            BD_DEVICE_PTRS.
+ *            BD_DEVICE_PTRS | BD_PROBE_STORAGE_IDS | BD_NONTEMPORAL | BD_TEMPORAL.
  *   out      receives the handle; release with graph_free.
  * Errors: BD_E_GRAPH if a check fails (disconnected, asymmetric, unsorted,
  * self-loop), BD_E_RANGE for sizes beyond the limits, BD_E_INVALID for
@@ -223,6 +244,13 @@ typedef struct {
                                 kernel for all when the wave-uniform chunks could not fill
                                 the device; < 0 = general kernel only. Results do not
                                 depend on it. */
+    double   deadline_ms;    /* > 0: a watchdog on the calling thread raises an abort flag
+                                once the call has run this long; the walk kernels read it
+                                before each chunk and take no further chunk, and queries
+                                that had not finished get status BD_E_TIMEOUT (beta 0); the
+                                finished ones keep their results, bit-identical to an
+                                unbounded call. Ignored by bd_query_batch_noalloc.
+                                0 = no deadline. */
 } bd_exec;
 
 typedef struct {
@@ -285,7 +313,10 @@ int bd_query_batch_noalloc(bd_graph* g, int64_t nq, const int32_t* s, const int3
  * h = sum_{i=0..L} P^i D^{-1} b_st (Lemma 2.3), in binary64 on the device by
  * L sparse products (the paper's PUSH series; a deterministic reference for
  * the estimator, which is unbiased for beta^(L) by Lemma 3.3).
- *   beta_L  host, nq doubles.  Up to 64 queries share one pass.
+ *   beta_L  host, nq doubles.
+ * Up to 64 queries share one pass: three n x Q binary64 blocks (the series
+ * term, the next term, the running sum), fewer queries per pass when those
+ * would take more than half of the free device memory.
  */
 int bd_truncated_beta(bd_graph* g, int64_t nq, const int32_t* s, const int32_t* t, int32_t L,
                       void* stream, double* beta_L);
@@ -295,6 +326,8 @@ int bd_truncated_beta(bd_graph* g, int64_t nq, const int32_t* s, const int32_t* 
  * (section 2.1), estimated by `iters` power iterations on D^{-1/2} A D^{-1/2}
  * (same spectrum) with the stationary direction projected out; the estimate
  * is ||N x|| for the unit iterate x, which converges to lambda from below.
+ * The iteration runs on the device (four n-vectors of binary64, the start
+ * vector a counter-based function of seed); only the estimate is copied back.
  */
 int bd_graph_lambda(bd_graph* g, int32_t iters, uint64_t seed, void* stream, double* lambda);
 
@@ -417,6 +450,17 @@ int  bd_server_poll(bd_server* srv, uint64_t request_id, bd_result* out, int* do
 /* Block until the request finishes (timeout_ms <= 0: no timeout). */
 int  bd_server_wait(bd_server* srv, uint64_t request_id, double timeout_ms, bd_result* out,
                     double* latency_ms);
+/*
+ * Cancel a request (failure handling of a serving loop: a client gone, a
+ * deadline missed). A request still queued for admission is finished at once;
+ * an admitted one gets no further chunk: the chunks already launched run to
+ * their end (each is bounded work), then the slots of its unfinished queries
+ * are cleared and freed for other requests. Its queries that finished before
+ * keep their results; the others get status BD_E_CANCELLED (beta 0). Poll or
+ * wait for the request as usual to collect it. BD_OK also when it had already
+ * finished or been cancelled; BD_E_NOTFOUND for an unknown (or collected) id.
+ */
+int  bd_server_cancel(bd_server* srv, uint64_t request_id);
 void bd_server_destroy(bd_server* srv);
 
 /* ---- misc ------------------------------------------------------------------ */

@@ -56,6 +56,9 @@ BD_LAYOUT_COMPACT = 8
 BD_WIDE_IDS = 16
 BD_LAYOUT_AUTO = 32
 BD_DEVICE_PTRS = 64
+BD_PROBE_STORAGE_IDS = 128
+BD_NONTEMPORAL = 256
+BD_TEMPORAL = 512
 
 BD_POLICY_PAPER = 0
 BD_POLICY_SCALED = 1
@@ -70,7 +73,7 @@ EXPORTS = ("graph_load_csr", "graph_free", "bd_graph_get_info", "bd_plan", "bd_q
            "bd_server_submit", "bd_server_poll", "bd_server_wait", "bd_server_destroy",
            "bd_strerror", "bd_device_info", "bd_gather_roofline", "bd_autotune",
            "bd_query_stabilized", "bd_truncated_beta", "bd_graph_lambda", "bd_theorem_L",
-           "bd_query_batch_noalloc", "bd_set_allocator")
+           "bd_query_batch_noalloc", "bd_set_allocator", "bd_server_cancel")
 
 
 class BdPolicy(ctypes.Structure):
@@ -83,7 +86,7 @@ class BdExec(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_uint32), ("chunk_probes", ctypes.c_int32),
                 ("grid_wgs", ctypes.c_int32), ("use_graph", ctypes.c_int32),
                 ("chunk_pairs", ctypes.c_int32), ("queues", ctypes.c_int32),
-                ("uniform_min_r", ctypes.c_int32)]
+                ("uniform_min_r", ctypes.c_int32), ("deadline_ms", ctypes.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -101,7 +104,7 @@ class BdStats(ctypes.Structure):
 class BdGraphInfo(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("d_min", ctypes.c_int32),
                 ("d_max", ctypes.c_int32), ("bipartite", ctypes.c_int32), ("layout", ctypes.c_int32),
-                ("device_bytes", ctypes.c_int64)]
+                ("device_bytes", ctypes.c_int64), ("nontemporal", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class BdRoofline(ctypes.Structure):
@@ -169,6 +172,7 @@ def lib():
                                               ctypes.POINTER(ctypes.c_double)]),
             "bd_server_wait": (ctypes.c_int, [_P, u64, ctypes.c_double, _P, ctypes.POINTER(ctypes.c_double)]),
             "bd_server_destroy": (None, [_P]),
+            "bd_server_cancel": (ctypes.c_int, [_P, u64]),
             "bd_strerror": (ctypes.c_char_p, [ctypes.c_int]),
             "bd_device_info": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_size_t]),
             "bd_gather_roofline": (ctypes.c_int, [_P, i32, i32, i32, _P, ctypes.POINTER(BdRoofline)]),
@@ -264,9 +268,10 @@ def policy(kind="paper", c_B=448.0, c_R=128.0, delta=0.01, B=0, R=0, max_steps=0
 
 
 def exec_cfg(mode="batched", chunk_probes=0, grid_wgs=0, use_graph=False, chunk_pairs=0, queues=0,
-             uniform_min_r=0) -> BdExec:
+             uniform_min_r=0, deadline_ms=0.0) -> BdExec:
     m = {"plain": BD_MODE_PLAIN, "batched": BD_MODE_BATCHED}[mode]
-    return BdExec(m, chunk_probes, grid_wgs, 1 if use_graph else 0, chunk_pairs, queues, uniform_min_r)
+    return BdExec(m, chunk_probes, grid_wgs, 1 if use_graph else 0, chunk_pairs, queues, uniform_min_r,
+                  deadline_ms)
 
 
 class Graph:
@@ -459,6 +464,10 @@ class Server:
                "bd_server_wait")
         del self._sizes[rid]
         return out, lat.value
+
+    def cancel(self, rid: int):
+        """bd_server_cancel: collect the request with poll/wait afterwards."""
+        _check(lib().bd_server_cancel(self._h, rid), "bd_server_cancel")
 
     def destroy(self):
         if self._h is not None:

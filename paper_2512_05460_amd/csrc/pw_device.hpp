@@ -173,10 +173,34 @@ __device__ __forceinline__ int probe_value(uint32_t x, const Probe& pr, const Do
 // storage ids packed in 3 bytes; the entries of the first hub_nodes() storage ids
 // (the highest-degree nodes, which the walks visit most) are staged in LDS.
 // Above 2^24 nodes the same layout keeps 4-byte neighbour storage ids.
-constexpr int kLayoutCsr = 0, kLayoutFat = 1, kLayoutCompact = 2, kLayoutCompactHub = 3, kLayoutHub32 = 4;
-// hub entries staged per work group: 8,192 (64 KB) in 1,024-thread groups,
-// 1,024 in 256-thread ones
-constexpr uint32_t hub_nodes(int threads) { return threads >= 1024 ? 8192u : 1024u; }
+// Hubs first with the probe on storage ids: the same storage order, but the
+// probe is evaluated on the storage id itself (the node's rank in descending
+// degree), so a node entry is its 4-byte row offset alone (rp[x], rp[x + 1]:
+// one 8-byte load) and twice as many hubs fit in the same LDS.
+constexpr int kLayoutCsr = 0, kLayoutFat = 1, kLayoutCompact = 2, kLayoutCompactHub = 3, kLayoutHub32 = 4,
+              kLayoutHubId = 5;
+// The fat layout read with non-temporal loads (the same tables and results):
+// for tables far larger than the Infinity Cache, where every step misses it
+// anyway and keeping the entries out of the caches' replacement order leaves
+// them to the node entries of the walks' start nodes.
+constexpr int kLayoutFatNT = 6;
+constexpr bool hub_layout(int layout)
+{
+    return layout == kLayoutCompactHub || layout == kLayoutHub32 || layout == kLayoutHubId;
+}
+// hub entries staged per work group (64 KB in 1,024-thread groups, 8 KB in
+// 256-thread ones): 8,192 / 1,024 node entries of 8 bytes, or 16,384 / 2,048
+// row offsets of 4 bytes with the probe on storage ids
+constexpr uint32_t hub_nodes(int threads, int layout)
+{
+    return (threads >= 1024 ? 8192u : 1024u) * (layout == kLayoutHubId ? 2u : 1u);
+}
+// 32-bit words of the LDS hub copy (entries 0 .. hub_nodes, inclusive)
+constexpr uint32_t hub_words(int threads, int layout)
+{
+    return !hub_layout(layout) ? 2u : layout == kLayoutHubId ? hub_nodes(threads, layout) + 1u
+                                                            : 2u * (hub_nodes(threads, layout) + 1u);
+}
 
 struct DevGraph {
     const uint4* node;      // n entries (CSR and fat layouts)
@@ -186,6 +210,7 @@ struct DevGraph {
     const uint32_t* col24;  // 3 nnz bytes + padding, read as aligned words (compact layouts)
     const uint2* node8;     // n + 1 entries {row offset, original id} (compact layout, hubs first)
     const uint2* hub;       // LDS copy of node8[0 .. nhub] (nhub = 0: none)
+    const uint32_t* hub4;   // LDS copy of rp[0 .. nhub] (probe on storage ids)
     uint32_t nhub;
     Domain dom;
 };
@@ -229,6 +254,24 @@ __device__ __forceinline__ void hub_row(const DevGraph& G, uint32_t x, WalkState
     w.inv = __fdiv_rn(1.0f, (float)w.deg);
 }
 
+// Node x with the probe on its storage id: rp[x], rp[x + 1] from LDS for the
+// staged hubs, else one 8-byte global load.
+__device__ __forceinline__ void hubid_row(const DevGraph& G, uint32_t x, WalkState& w)
+{
+    uint32_t b, e;
+    if (x < G.nhub) {
+        b = G.hub4[x];
+        e = G.hub4[x + 1];
+    } else {
+        b = G.rp[x];
+        e = G.rp[x + 1];
+    }
+    w.x = x;
+    w.off = b;
+    w.deg = e - b;
+    w.inv = __fdiv_rn(1.0f, (float)w.deg);
+}
+
 // Walk state at internal id x (the start of a walk).
 template <int kLayout>
 __device__ __forceinline__ WalkState start_at(const DevGraph& G, uint32_t x)
@@ -243,6 +286,11 @@ __device__ __forceinline__ WalkState start_at(const DevGraph& G, uint32_t x)
         hub_row(G, x, w);
         return w;
     }
+    if (kLayout == kLayoutHubId) {
+        WalkState w;
+        hubid_row(G, x, w);
+        return w;
+    }
     return start_state(G.node[x]);
 }
 
@@ -252,13 +300,20 @@ __device__ __forceinline__ void step(WalkState& w, uint32_t u, const DevGraph& G
 {
     const uint32_t j = __umulhi(u, w.deg);
     const uint32_t pos = w.off + j;
-    if (kLayout == kLayoutFat) {
-        const uint4 e = G.adj[pos];
+    if (kLayout == kLayoutFat || kLayout == kLayoutFatNT) {
+        uint4 e;
+        if (kLayout == kLayoutFatNT) {
+            typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+            const u32x4 v = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(G.adj) + pos);
+            e = make_uint4(v.x, v.y, v.z, v.w);
+        } else {
+            e = G.adj[pos];
+        }
         w.x = e.x;
         w.off = e.y;
         w.deg = e.z;
         w.inv = __uint_as_float(e.w);
-    } else if (kLayout == kLayoutCompact || kLayout == kLayoutCompactHub) {
+    } else if (kLayout == kLayoutCompact || kLayout == kLayoutCompactHub || kLayout == kLayoutHubId) {
         // the 3 bytes at byte offset 3*pos lie in the aligned 8 bytes at word (3*pos)/4
         const uint32_t o = pos * 3u;
         const uint32_t wi = o >> 2;
@@ -266,6 +321,7 @@ __device__ __forceinline__ void step(WalkState& w, uint32_t u, const DevGraph& G
         const uint32_t hi = G.col24[wi + 1];
         const uint32_t x = __builtin_amdgcn_alignbit(hi, lo, (o & 3u) * 8u) & 0xFFFFFFu;
         if (kLayout == kLayoutCompact) compact_row(G, x, w);
+        else if (kLayout == kLayoutHubId) hubid_row(G, x, w);
         else hub_row(G, x, w);
     } else if (kLayout == kLayoutHub32) {
         hub_row(G, G.col[pos], w);
@@ -281,13 +337,20 @@ __device__ __forceinline__ void step(WalkState& w, uint32_t u, const DevGraph& G
 // Copy the hub entries of the compact layout with hubs first into LDS (every
 // thread of the block must call it); other layouts keep nhub = 0.
 template <int kLayout>
-__device__ __forceinline__ void stage_hubs(DevGraph& G, uint2* lds, uint32_t capacity)
+__device__ __forceinline__ void stage_hubs(DevGraph& G, uint32_t* lds, uint32_t capacity)
 {
     if constexpr (kLayout == kLayoutCompactHub || kLayout == kLayoutHub32) {
         const uint32_t nh = min(capacity, G.dom.n);
-        for (uint32_t i = threadIdx.x; i <= nh; i += blockDim.x) lds[i] = G.node8[i];
+        uint2* l2 = reinterpret_cast<uint2*>(lds);
+        for (uint32_t i = threadIdx.x; i <= nh; i += blockDim.x) l2[i] = G.node8[i];
         __syncthreads();
-        G.hub = lds;
+        G.hub = l2;
+        G.nhub = nh;
+    } else if constexpr (kLayout == kLayoutHubId) {
+        const uint32_t nh = min(capacity, G.dom.n);
+        for (uint32_t i = threadIdx.x; i <= nh; i += blockDim.x) lds[i] = G.rp[i];
+        __syncthreads();
+        G.hub4 = lds;
         G.nhub = nh;
     }
 }

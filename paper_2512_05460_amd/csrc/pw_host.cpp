@@ -35,6 +35,11 @@ constexpr int32_t kMaxL = 16383;
 // mean degree 10: with 7.2 MiB of tables hubs first ran 1.40x fat, with
 // 14.4 MiB 0.89x.
 constexpr int64_t kAutoCompactBytes = int64_t(12) << 20;
+// The fat layout switches to non-temporal loads of its adjacency entries when
+// its tables exceed 16 times the 256 MB Infinity Cache: measured +9.5% walk
+// steps/s with 20.7 GB of tables (Chung-Lu n=4e7), -3.5% with 2.2 GB (n=1e7)
+// and -46% with 192 MB (the grid, whose locality lives in the caches).
+constexpr int64_t kFatNontemporalBytes = int64_t(4) << 30;
 
 #define HIP_TRY(expr)                                  \
     do {                                               \
@@ -109,15 +114,38 @@ struct Workspace {
     hipGraphExec_t gexec = nullptr;
     std::vector<uint64_t> gkey;
     int64_t graph_builds = 0, graph_replays = 0;
+    // the watchdog's abort flag: host memory mapped for the device
+    uint32_t* abort_host = nullptr;
+    uint32_t* abort_dev = nullptr;
     int ensure(DevBuf& b, size_t bytes)
     {
         if (b.p && b.bytes >= bytes) return BD_OK;
         return b.alloc(std::max(bytes, 2 * b.bytes));
     }
+    int ensure_abort_flag()
+    {
+        if (abort_host) return BD_OK;
+        void* h = nullptr;
+        if (hipHostMalloc(&h, 64, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
+            (void)hipGetLastError();
+            return BD_E_NOMEM;
+        }
+        void* d = nullptr;
+        if (hipHostGetDevicePointer(&d, h, 0) != hipSuccess) {
+            (void)hipGetLastError();
+            (void)hipHostFree(h);
+            return BD_E_HIP;
+        }
+        abort_host = static_cast<uint32_t*>(h);
+        abort_dev = static_cast<uint32_t*>(d);
+        __atomic_store_n(abort_host, 0u, __ATOMIC_SEQ_CST);
+        return BD_OK;
+    }
     ~Workspace()
     {
         if (gexec) (void)hipGraphExecDestroy(gexec);
         if (gstream) (void)hipStreamDestroy(gstream);
+        if (abort_host) (void)hipHostFree(abort_host);
     }
 };
 
@@ -125,10 +153,12 @@ struct bd_graph {
     int64_t n = 0, nnz = 0;
     int32_t d_min = 0, d_max = 0;
     int32_t bipartite = 0;
-    int32_t layout = 0;  // 0 CSR, 1 fat, 2 compact (kLayout* of the kernels)
+    int32_t layout = 0;  // 0 CSR, 1 fat, 2 compact, ... (kLayout* of the kernels)
+    int32_t kernel_layout = 0;  // the kernels' layout code: layout, or 6 for fat with non-temporal loads
     int device = 0;
     std::vector<int32_t> deg;        // host copy for the planner, by caller id
     std::vector<uint32_t> internal;  // caller id -> storage id (empty: identity)
+    std::vector<uint32_t> external;  // storage id -> caller id where walks see storage ids (layout 5)
     DevBuf node, col, adj, rp32, col24, node8;
     DomainParams dom{};
     int64_t device_bytes = 0;
@@ -277,15 +307,22 @@ extern "C" int graph_load_csr(int64_t n, const int64_t* row_ptr, const int32_t* 
     }
     if (dmin < 1) return BD_E_GRAPH;  // an isolated node: not connected
     if (flags & BD_LAYOUT_AUTO) {
-        if (flags & (BD_LAYOUT_FAT | BD_LAYOUT_COMPACT | BD_WIDE_IDS)) return BD_E_INVALID;
+        if (flags & (BD_LAYOUT_FAT | BD_LAYOUT_COMPACT | BD_WIDE_IDS | BD_PROBE_STORAGE_IDS)) return BD_E_INVALID;
         const int64_t compact_bytes = 8 * (n + 1) + 3 * nnz + 8;
         flags = (n <= (int64_t(1) << 24) && compact_bytes <= kAutoCompactBytes)
                     ? (flags | BD_LAYOUT_COMPACT | BD_RELABEL_DEGREE)
                     : (flags | BD_LAYOUT_FAT);
     }
     // compact layouts: 3-byte ids up to 2^24 nodes; hubs first keeps 4-byte ids above that
-    const bool wide = (flags & BD_LAYOUT_COMPACT) && (flags & BD_RELABEL_DEGREE) &&
+    const bool storage_probe = (flags & BD_PROBE_STORAGE_IDS) != 0;
+    if (storage_probe && ((flags & (BD_LAYOUT_COMPACT | BD_RELABEL_DEGREE)) != (BD_LAYOUT_COMPACT | BD_RELABEL_DEGREE) ||
+                          (flags & BD_WIDE_IDS)))
+        return BD_E_INVALID;
+    if (storage_probe && n > (int64_t(1) << 24)) return BD_E_RANGE;
+    const bool wide = (flags & BD_LAYOUT_COMPACT) && (flags & BD_RELABEL_DEGREE) && !storage_probe &&
                       (n > (int64_t(1) << 24) || (flags & BD_WIDE_IDS));
+    if ((flags & BD_NONTEMPORAL) && (flags & BD_TEMPORAL)) return BD_E_INVALID;
+    if ((flags & (BD_NONTEMPORAL | BD_TEMPORAL)) && !(flags & BD_LAYOUT_FAT)) return BD_E_INVALID;
     if (flags & BD_LAYOUT_COMPACT) {
         if (flags & BD_LAYOUT_FAT) return BD_E_INVALID;
         if (!wide && (n > (int64_t(1) << 24) || 3 * nnz + 8 > (int64_t)UINT32_MAX)) return BD_E_RANGE;
@@ -311,8 +348,16 @@ extern "C" int graph_load_csr(int64_t n, const int64_t* row_ptr, const int32_t* 
     g->d_min = dmin;
     g->d_max = dmax;
     g->bipartite = bip;
-    g->layout = (flags & BD_LAYOUT_COMPACT) ? (wide ? 4 : (flags & BD_RELABEL_DEGREE) ? 3 : 2)
+    g->layout = (flags & BD_LAYOUT_COMPACT) ? (storage_probe ? 5 : wide ? 4 : (flags & BD_RELABEL_DEGREE) ? 3 : 2)
                                             : (flags & BD_LAYOUT_FAT) ? 1 : 0;
+    g->kernel_layout = g->layout;
+    if (g->layout == 1) {
+        const int64_t fat_bytes = 16 * nnz + 16 * n;
+        const bool nt = (flags & BD_NONTEMPORAL) ? true
+                        : (flags & BD_TEMPORAL)  ? false
+                                                 : fat_bytes >= kFatNontemporalBytes;
+        if (nt) g->kernel_layout = 6;
+    }
     g->device = dev;
     g->dom = make_domain((uint32_t)n);
     g->deg.resize((size_t)n);
@@ -328,6 +373,7 @@ extern "C" int graph_load_csr(int64_t n, const int64_t* row_ptr, const int32_t* 
                          [&](uint32_t a, uint32_t b) { return g->deg[a] > g->deg[b]; });
         g->internal.resize((size_t)n);
         for (int64_t i = 0; i < n; ++i) g->internal[order[(size_t)i]] = (uint32_t)i;
+        if (storage_probe) g->external = order;  // walks report storage ids: map them back
         relabelled.resize((size_t)nnz);
         int64_t pos = 0;
         for (int64_t i = 0; i < n; ++i) {
@@ -360,7 +406,7 @@ extern "C" int graph_load_csr(int64_t n, const int64_t* row_ptr, const int32_t* 
         // with hubs first also the node entries {row offset, original id}, entry
         // n = {nnz, 0}
         const bool packed_ids = g->layout != 4;
-        const bool hubs = g->layout >= 3;
+        const bool hubs = g->layout == 3 || g->layout == 4;  // 8-byte node entries (layout 5 reads rp32)
         rp32.resize((size_t)n + 1);
         for (int64_t i = 0; i < n; ++i) rp32[(size_t)i] = nodetab[(size_t)i * 4];
         rp32[(size_t)n] = (uint32_t)nnz;
@@ -456,6 +502,7 @@ extern "C" int bd_graph_get_info(const bd_graph* g, bd_graph_info* info)
     info->d_max = g->d_max;
     info->bipartite = g->bipartite;
     info->layout = g->layout;
+    info->nontemporal = g->kernel_layout == 6 ? 1 : 0;
     info->device_bytes = g->device_bytes;
     return BD_OK;
 }
@@ -584,7 +631,7 @@ GraphTables tables(const bd_graph* g)
 int resident_wgs(const bd_graph* g, int uniform, int share = 1)
 {
     int per_cu = 0;
-    if (walk_occupancy(g->layout, uniform, share, &per_cu) != 0 || per_cu < 1) per_cu = 1;
+    if (walk_occupancy(g->kernel_layout, uniform, share, &per_cu) != 0 || per_cu < 1) per_cu = 1;
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, g->device) != hipSuccess) return per_cu * 256;
     return per_cu * prop.multiProcessorCount;
@@ -770,11 +817,31 @@ int carve_ptrs(void* base, size_t cap, const Batch& b, WorkPtrs* wp)
 // library-owned stream and replayed; descriptors and chunk tables are copied
 // in before each replay. Without `owned` nothing is created: no events, so
 // stats->walk_kernel_ms stays 0.
+// With ex.deadline_ms > 0 (and `owned`) a watchdog on the calling thread waits
+// for the launches by polling; once the deadline has passed it raises the
+// abort flag, the work groups take no further chunk, and the queries whose
+// probe count did not reach K are marked in *incomplete.
 int run_batch(bd_graph* g, const Batch& b, const bd_exec& ex, hipStream_t user_st, const WorkPtrs& w,
-              bool owned, std::vector<double>& beta, bd_stats* stats, double* q_dbg_host, double* y_dbg_host)
+              bool owned, std::vector<double>& beta, bd_stats* stats, double* q_dbg_host, double* y_dbg_host,
+              std::vector<uint8_t>* incomplete = nullptr)
 {
     const size_t nv = b.qd.size();
     if (nv == 0) return BD_OK;
+    const double t_call = now_ms();
+    const bool watch = owned && ex.deadline_ms > 0.0;
+    if (watch) {
+        const int rc = g->ws.ensure_abort_flag();
+        if (rc != BD_OK) return rc;
+        __atomic_store_n(g->ws.abort_host, 0u, __ATOMIC_SEQ_CST);
+    }
+    bool fired = false;
+    auto past_deadline = [&]() {
+        if (watch && !fired && now_ms() - t_call > ex.deadline_ms) {
+            __atomic_store_n(g->ws.abort_host, 1u, __ATOMIC_SEQ_CST);
+            fired = true;
+        }
+        return fired;
+    };
     const size_t gdim = b.G;
     Workspace& ws = g->ws;
     const bool graph_mode = owned && ex.use_graph && ex.mode != BD_MODE_PLAIN && !q_dbg_host && !y_dbg_host;
@@ -797,7 +864,8 @@ int run_batch(bd_graph* g, const Batch& b, const bd_exec& ex, hipStream_t user_s
     a.beta = static_cast<double*>(w.beta);
     a.q_debug = q_dbg_host ? static_cast<double*>(w.qdbg) : nullptr;
     a.ybar_debug = y_dbg_host ? static_cast<double*>(w.ydbg) : nullptr;
-    const int layout = g->layout;
+    a.abort_flag = watch ? g->ws.abort_dev : nullptr;
+    const int layout = g->kernel_layout;
 
     // the zeroing every launch needs
     auto zero_all = [&](hipStream_t s2) -> int {
@@ -849,7 +917,20 @@ int run_batch(bd_graph* g, const Batch& b, const bd_exec& ex, hipStream_t user_s
         ++launches;
         if (!e0) return BD_OK;
         if (hipEventRecord(e1, st) != hipSuccess) return BD_E_HIP;
-        if (hipEventSynchronize(e1) != hipSuccess) return BD_E_HIP;
+        if (watch) {
+            // poll, raising the abort flag once the deadline has passed; a
+            // raised flag ends the launch within one chunk per work group
+            for (;;) {
+                const hipError_t q = hipEventQuery(e1);
+                if (q == hipSuccess) break;
+                if (q != hipErrorNotReady) return BD_E_HIP;
+                past_deadline();
+                std::this_thread::sleep_for(std::chrono::microseconds(200));
+            }
+            (void)hipGetLastError();  // the not-ready answers are no error
+        } else if (hipEventSynchronize(e1) != hipSuccess) {
+            return BD_E_HIP;
+        }
         float ms = 0.f;
         if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return BD_E_HIP;
         kernel_ms += ms;
@@ -859,6 +940,7 @@ int run_batch(bd_graph* g, const Batch& b, const bd_exec& ex, hipStream_t user_s
         status = zero_all(st);
         // one query per launch, one work group per chunk
         for (size_t q = 0; q < nv && status == BD_OK; ++q) {
+            if (past_deadline()) break;  // the remaining queries are not launched
             const uint32_t c0 = b.chunk_begin[q];
             const uint32_t c1 = q + 1 < nv ? b.chunk_begin[q + 1] : (uint32_t)b.chunks.size();
             WalkArgs aq = a;
@@ -883,6 +965,7 @@ int run_batch(bd_graph* g, const Batch& b, const bd_exec& ex, hipStream_t user_s
                                      (uint64_t)(uintptr_t)w.beta, (uint64_t)(uintptr_t)w.cursor};
         for (int part = 0; part < 2; ++part)
             for (uint32_t i = 0; i <= b.nqueues; ++i) key.push_back(b.qoff[part][i]);
+        key.push_back((uint64_t)(uintptr_t)a.abort_flag);
         if (!ws.gexec || ws.gkey != key) {
             if (ws.gexec) {
                 (void)hipGraphExecDestroy(ws.gexec);
@@ -917,7 +1000,18 @@ int run_batch(bd_graph* g, const Batch& b, const bd_exec& ex, hipStream_t user_s
     if (q_dbg_host)
         HIP_TRY(hipMemcpyAsync(q_dbg_host, w.qdbg, (size_t)b.qd[0].K * 8, hipMemcpyDeviceToHost, st));
     if (y_dbg_host) HIP_TRY(hipMemcpyAsync(y_dbg_host, w.ydbg, gdim * 8, hipMemcpyDeviceToHost, st));
+    std::vector<uint32_t> done_count;
+    if (fired) {
+        // which queries the aborted launches finished: those whose probe count reached K
+        done_count.resize(nv);
+        HIP_TRY(hipMemcpyAsync(done_count.data(), w.done, nv * 4, hipMemcpyDeviceToHost, st));
+    }
     HIP_TRY(hipStreamSynchronize(st));
+    if (watch) __atomic_store_n(g->ws.abort_host, 0u, __ATOMIC_SEQ_CST);
+    if (incomplete) {
+        incomplete->assign(nv, 0);
+        for (size_t q = 0; q < done_count.size(); ++q) (*incomplete)[q] = done_count[q] != b.qd[q].K;
+    }
     if (stats) {
         stats->walk_kernel_ms += kernel_ms;
         stats->launches += launches;
@@ -965,7 +1059,7 @@ void build_batch(const bd_graph* g, int64_t nq, const int32_t* s, const int32_t*
         uint64_t nu = 0;
         for (const QueryDesc& d : b.qd) {
             if ((int64_t)d.R < umin) continue;
-            const ChunkPlan cp = chunk_plan(ex, d, g->layout);
+            const ChunkPlan cp = chunk_plan(ex, d, g->kernel_layout);
             const uint32_t ng = Groups(d).n;
             nu += cp.part ? (uint64_t)ng * ((d.R + cp.part - 1) / cp.part) : (ng + cp.gc - 1) / cp.gc;
         }
@@ -984,7 +1078,7 @@ void build_batch(const bd_graph* g, int64_t nq, const int32_t* s, const int32_t*
     b.chunk_begin.assign(b.qd.size(), 0);
     auto emit = [&](size_t q) {
         QueryDesc& d = b.qd[q];
-        ChunkCursor cur((uint32_t)q, d, ex, g->layout);
+        ChunkCursor cur((uint32_t)q, d, ex, g->kernel_layout);
         if (cur.plan.part) {
             d.psum_base = b.split_probes;
             b.split_probes += d.K;
@@ -1039,12 +1133,19 @@ extern "C" int bd_query_batch(bd_graph* g, int64_t nq, const int32_t* s, const i
     Batch b;
     build_batch(g, nq, s, t, L, uid, seed, out, ex, policy_share(p), b);
     std::vector<double> beta;
+    std::vector<uint8_t> incomplete;
     WorkPtrs wp;
     int rc = b.qd.empty() ? BD_OK : workspace_ptrs(g->ws, b, false, false, &wp);
-    if (rc == BD_OK) rc = run_batch(g, b, ex, (hipStream_t)stream, wp, true, beta, stats, nullptr, nullptr);
+    if (rc == BD_OK)
+        rc = run_batch(g, b, ex, (hipStream_t)stream, wp, true, beta, stats, nullptr, nullptr, &incomplete);
     if (rc != BD_OK) return rc;
     for (size_t q = 0; q < b.qd.size(); ++q) {
         bd_result& r = out[b.index[q]];
+        if (!incomplete.empty() && incomplete[q]) {
+            r.status = BD_E_TIMEOUT;  // abandoned at the deadline
+            r.beta = 0.0;
+            continue;
+        }
         r.beta = beta[q];
         if (stats) {
             stats->walk_steps += r.walk_steps;
@@ -1138,32 +1239,42 @@ extern "C" int bd_truncated_beta(bd_graph* g, int64_t nq, const int32_t* s, cons
     if (!g || nq < 0 || L < 0 || (nq > 0 && (!s || !t || !beta_L))) return BD_E_INVALID;
     for (int64_t i = 0; i < nq; ++i)
         if (s[i] < 0 || t[i] < 0 || s[i] >= g->n || t[i] >= g->n || s[i] == t[i]) return BD_E_INVALID;
+    if (nq == 0) return BD_OK;
     std::lock_guard<std::mutex> lock(g->mu);
     hipStream_t st = (hipStream_t)stream;
     const uint32_t n = (uint32_t)g->n;
     const uint32_t* rp = g->rp32.as<const uint32_t>();
-    const bool packed_ids = g->layout == 2 || g->layout == 3;
+    const bool packed_ids = g->layout == 2 || g->layout == 3 || g->layout == 5;
     const uint32_t* col = packed_ids ? nullptr : g->col.as<const uint32_t>();
     const uint32_t* col24 = packed_ids ? g->col24.as<const uint32_t>() : nullptr;
-    for (int64_t q0 = 0; q0 < nq; q0 += 64) {
-        const uint32_t Q = (uint32_t)std::min<int64_t>(64, nq - q0);
+    // queries per pass: three n x Q binary64 blocks within half the free device memory
+    size_t free_b = 0, total_b = 0;
+    HIP_TRY(hipMemGetInfo(&free_b, &total_b));
+    const size_t per_q = (size_t)n * 8 * 3;
+    const uint32_t Qmax = (uint32_t)std::max<size_t>(1, std::min<size_t>({64, (size_t)nq, free_b / 2 / per_q}));
+    DevBuf dv, dy, dh, dsq, dlin;
+    int rc = dv.alloc((size_t)n * Qmax * 8);
+    if (rc == BD_OK) rc = dy.alloc((size_t)n * Qmax * 8);
+    if (rc == BD_OK) rc = dh.alloc((size_t)n * Qmax * 8);
+    if (rc == BD_OK) rc = dsq.alloc(Qmax * 8);
+    if (rc == BD_OK) rc = dlin.alloc(Qmax * 8);
+    if (rc != BD_OK) return rc;
+    for (int64_t q0 = 0; q0 < nq; q0 += Qmax) {
+        const uint32_t Q = (uint32_t)std::min<int64_t>(Qmax, nq - q0);
         const size_t bytes = (size_t)n * Q * 8;
-        DevBuf dv, dy, dh, dsq, dlin;
-        int rc = dv.alloc(bytes);
-        if (rc == BD_OK) rc = dy.alloc(bytes);
-        if (rc == BD_OK) rc = dh.alloc(bytes);
-        if (rc == BD_OK) rc = dsq.alloc(Q * 8);
-        if (rc == BD_OK) rc = dlin.alloc(Q * 8);
-        if (rc != BD_OK) return rc;
         // v_0 = D^{-1} b_st in storage ids
-        std::vector<double> v0((size_t)n * Q, 0.0);
+        uint32_t ss[64], tt[64];
+        double vs[64], vt[64];
         for (uint32_t q = 0; q < Q; ++q) {
             const int32_t a = s[q0 + q], b = t[q0 + q];
-            v0[(size_t)storage_id(g, a) * Q + q] = 1.0 / (double)g->deg[(size_t)a];
-            v0[(size_t)storage_id(g, b) * Q + q] = -1.0 / (double)g->deg[(size_t)b];
+            ss[q] = storage_id(g, a);
+            tt[q] = storage_id(g, b);
+            vs[q] = 1.0 / (double)g->deg[(size_t)a];
+            vt[q] = -1.0 / (double)g->deg[(size_t)b];
         }
-        HIP_TRY(hipMemcpyAsync(dv.p, v0.data(), bytes, hipMemcpyHostToDevice, st));
-        HIP_TRY(hipMemcpyAsync(dh.p, v0.data(), bytes, hipMemcpyHostToDevice, st));
+        HIP_TRY(launch_zero(dv.p, bytes, st));
+        HIP_TRY(launch_zero(dh.p, bytes, st));
+        HIP_TRY(launch_series_seed(ss, tt, vs, vt, Q, dv.as<double>(), dh.as<double>(), st));
         for (int32_t i = 0; i < L; ++i) {
             HIP_TRY(launch_spmv_step(rp, col, col24, n, Q, dv.as<double>(), dy.as<double>(), dh.as<double>(), st));
             std::swap(dv.p, dy.p);
@@ -1185,54 +1296,23 @@ extern "C" int bd_graph_lambda(bd_graph* g, int32_t iters, uint64_t seed, void* 
     hipStream_t st = (hipStream_t)stream;
     const uint32_t n = (uint32_t)g->n;
     const uint32_t* rp = g->rp32.as<const uint32_t>();
-    const bool packed_ids = g->layout == 2 || g->layout == 3;
+    const bool packed_ids = g->layout == 2 || g->layout == 3 || g->layout == 5;
     const uint32_t* col = packed_ids ? nullptr : g->col.as<const uint32_t>();
     const uint32_t* col24 = packed_ids ? g->col24.as<const uint32_t>() : nullptr;
-    // phi = sqrt(d) / ||sqrt(d)|| in storage order; x0 from a seeded LCG, made orthogonal to phi
-    std::vector<double> phi(n), x(n), y(n);
-    double nrm = 0.0;
-    for (uint32_t i = 0; i < n; ++i) {
-        phi[i] = std::sqrt((double)g->deg[(size_t)i]);
-        nrm += phi[i] * phi[i];
-    }
-    if (!g->internal.empty()) {
-        for (uint32_t v = 0; v < n; ++v) y[g->internal[v]] = phi[v];
-        phi.swap(y);
-    }
-    nrm = std::sqrt(nrm);
-    for (auto& p : phi) p /= nrm;
-    uint64_t r = seed | 1u;
-    auto project = [&](std::vector<double>& v) {
-        double dot = 0.0, nn = 0.0;
-        for (uint32_t i = 0; i < n; ++i) dot += phi[i] * v[i];
-        for (uint32_t i = 0; i < n; ++i) {
-            v[i] -= dot * phi[i];
-            nn += v[i] * v[i];
-        }
-        return std::sqrt(nn);
-    };
-    for (uint32_t i = 0; i < n; ++i) {
-        r = r * 6364136223846793005ull + 1442695040888963407ull;
-        x[i] = (double)(r >> 11) * 0x1p-53 - 0.5;
-    }
-    double nx = project(x);
-    for (auto& v : x) v /= nx;
-    DevBuf dx, dy;
-    int rc = dx.alloc((size_t)n * 8);
-    if (rc == BD_OK) rc = dy.alloc((size_t)n * 8);
+    DevBuf phi, x, y, z, part, scal;
+    int rc = phi.alloc((size_t)n * 8);
+    if (rc == BD_OK) rc = x.alloc((size_t)n * 8);
+    if (rc == BD_OK) rc = y.alloc((size_t)n * 8);
+    if (rc == BD_OK) rc = z.alloc((size_t)n * 8);
+    if (rc == BD_OK) rc = part.alloc(2 * 1024 * 8);
+    if (rc == BD_OK) rc = scal.alloc(2 * 8);
     if (rc != BD_OK) return rc;
-    double est = 0.0;
-    for (int32_t it = 0; it < iters; ++it) {
-        HIP_TRY(hipMemcpyAsync(dx.p, x.data(), (size_t)n * 8, hipMemcpyHostToDevice, st));
-        HIP_TRY(launch_nmul(rp, col, col24, n, dx.as<double>(), dy.as<double>(), st));
-        HIP_TRY(hipMemcpyAsync(y.data(), dy.p, (size_t)n * 8, hipMemcpyDeviceToHost, st));
-        HIP_TRY(hipStreamSynchronize(st));
-        const double ny = project(y);  // ||N x|| off the stationary direction, with ||x|| = 1
-        est = ny;
-        if (ny == 0.0) break;
-        for (uint32_t i = 0; i < n; ++i) x[i] = y[i] / ny;
-    }
-    *lambda = est;
+    HIP_TRY(launch_lambda(rp, col, col24, n, (uint32_t)g->nnz, iters, seed, phi.as<double>(), x.as<double>(),
+                          y.as<double>(), z.as<double>(), part.as<double>(), scal.as<double>(), st));
+    double sc[2] = {0.0, 0.0};
+    HIP_TRY(hipMemcpyAsync(sc, scal.p, sizeof(sc), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    *lambda = sc[1];
     return BD_OK;
 }
 
@@ -1404,13 +1484,15 @@ extern "C" int bd_walk_trace(bd_graph* g, int64_t count, const int32_t* start, c
     HIP_TRY(hipMemcpyAsync(dk.p, k, c * 4, hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(dp.p, p, c * 4, hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(dsd.p, side, c * 4, hipMemcpyHostToDevice, st));
-    HIP_TRY(launch_trace(tables(g), g->layout, (uint32_t)c, ds.as<int32_t>(),
+    HIP_TRY(launch_trace(tables(g), g->kernel_layout, (uint32_t)c, ds.as<int32_t>(),
                          du.as<uint32_t>(), dk.as<uint32_t>(), dp.as<uint32_t>(), dsd.as<uint32_t>(), L,
                          (uint32_t)seed, (uint32_t)(seed >> 32), trace ? dt.as<int32_t>() : nullptr,
                          acc ? da.as<float>() : nullptr, st));
     if (trace) HIP_TRY(hipMemcpyAsync(trace, dt.p, c * (size_t)(L + 1) * 4, hipMemcpyDeviceToHost, st));
     if (acc) HIP_TRY(hipMemcpyAsync(acc, da.p, c * 4, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
+    if (trace && !g->external.empty())
+        for (size_t i = 0; i < c * (size_t)(L + 1); ++i) trace[i] = (int32_t)g->external[(size_t)trace[i]];
     return BD_OK;
 }
 
@@ -1451,17 +1533,17 @@ extern "C" int bd_gather_roofline(bd_graph* g, int32_t chains_per_lane, int32_t 
     hipStream_t st = (hipStream_t)stream;
     uint32_t grid = work_groups > 0 ? (uint32_t)work_groups : 4u * (uint32_t)resident_wgs(g, 1, 1);
     DevBuf sink;
-    const int wg = block_threads(g->layout, 1);
+    const int wg = block_threads(g->kernel_layout, 1);
     int rc = sink.alloc((size_t)grid * wg * 4);
     if (rc != BD_OK) return rc;
     const int fat = g->layout == 1;
     // warm-up launch (caches, clocks), then the timed one
-    HIP_TRY(launch_gather(tables(g), g->layout, chains_per_lane, grid, std::min(steps, 64), 1u, sink.as<uint32_t>(), st));
+    HIP_TRY(launch_gather(tables(g), g->kernel_layout, chains_per_lane, grid, std::min(steps, 64), 1u, sink.as<uint32_t>(), st));
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
     HIP_TRY(hipEventRecord(e0, st));
-    HIP_TRY(launch_gather(tables(g), g->layout, chains_per_lane, grid, steps, 2u, sink.as<uint32_t>(), st));
+    HIP_TRY(launch_gather(tables(g), g->kernel_layout, chains_per_lane, grid, steps, 2u, sink.as<uint32_t>(), st));
     HIP_TRY(hipEventRecord(e1, st));
     HIP_TRY(hipEventSynchronize(e1));
     float ms = 0.f;
@@ -1572,9 +1654,14 @@ struct Request {
     bool done = false;
     std::deque<uint32_t> rr_slots;  // admitted queries with chunks left to hand out
     bool in_rr = false;             // the request is in the server's round-robin
+    std::vector<uint32_t> slots;    // slots taken at admission
+    bool admitted = false;
+    bool cancelled = false;         // bd_server_cancel: no further chunk is handed out
+    uint64_t cancel_mark = 0;       // slices launched when it was cancelled
 };
 
 struct SlotState {
+    bool busy = false;         // held by a query of request `req`
     uint64_t req = 0;
     int64_t ridx = 0;
     ChunkCursor cur;           // next chunk of this query
@@ -1676,6 +1763,8 @@ struct bd_server {
     std::vector<SlotState> slot;
     std::deque<uint64_t> rr;  // requests with chunks left, round-robin
     uint64_t inflight_steps = 0;
+    uint64_t slices_launched = 0, slices_done = 0;
+    std::vector<uint64_t> cancelled;  // admitted requests waiting for their slots to be reclaimed
     double steps_per_ms = 5e7;
     double t_last_done = 0;
     // a lane's time per walk step (ms): a chunk needs about (L + 1) steps per
@@ -1734,14 +1823,15 @@ int admit(bd_server* S)
         bool fits = true;
         for (size_t i = 0; i < need && fits; ++i) {
             const QueryDesc& d = r.desc[i];
-            if (chunk_plan(ex, d, S->g->layout).part && !S->psum_alloc.alloc(d.K, &base[i])) {
+            if (chunk_plan(ex, d, S->g->kernel_layout).part && !S->psum_alloc.alloc(d.K, &base[i])) {
                 for (size_t j = 0; j < i; ++j)
-                    if (chunk_plan(ex, r.desc[j], S->g->layout).part) S->psum_alloc.release(base[j], r.desc[j].K);
+                    if (chunk_plan(ex, r.desc[j], S->g->kernel_layout).part) S->psum_alloc.release(base[j], r.desc[j].K);
                 fits = false;
             }
         }
         if (!fits) break;
         S->pending.pop_front();
+        r.admitted = true;
         if (need > 0 && !r.in_rr) {
             S->rr.push_back(id);
             r.in_rr = true;
@@ -1756,9 +1846,11 @@ int admit(bd_server* S)
             d.psum_base = base[i];
             S->h_qd.as<QueryDesc>()[sl] = d;
             SlotState& ss = S->slot[sl];
+            ss.busy = true;
             ss.req = id;
+            r.slots.push_back(sl);
             ss.ridx = r.index[i];
-            ss.cur = ChunkCursor(sl, d, ex, S->g->layout);
+            ss.cur = ChunkCursor(sl, d, ex, S->g->kernel_layout);
             ss.L = (uint32_t)d.L;
             ss.steps = (uint64_t)r.res[(size_t)ss.ridx].walk_steps;
             ss.uniform = d.R >= kUniformMinR;
@@ -1809,7 +1901,60 @@ int process_completions(bd_server* S, const Slice& sl)
         S->inflight_steps -= std::min(S->inflight_steps, ss.steps);
         S->psum_alloc.release(ss.psum_base, ss.psum_n);
         ss.psum_n = 0;
+        ss.busy = false;
         S->free_slots.push_back(c.slot);
+    }
+    return BD_OK;
+}
+
+// Cancelled requests whose slots no launched slice can touch any more: clear
+// the slots' device state (block sums, probe counter, split-probe
+// accumulators) on the admission stream, which every later slice waits for,
+// free them, and finish the request with BD_E_CANCELLED for the queries that
+// had not finished. Caller holds mu.
+int reclaim_cancelled(bd_server* S)
+{
+    for (size_t i = 0; i < S->cancelled.size();) {
+        const uint64_t id = S->cancelled[i];
+        auto it = S->reqs.find(id);
+        if (it == S->reqs.end()) {
+            S->cancelled.erase(S->cancelled.begin() + (ptrdiff_t)i);
+            continue;
+        }
+        Request& r = it->second;
+        if (S->slices_done < r.cancel_mark) {
+            ++i;
+            continue;
+        }
+        bool zeroed = false;
+        for (uint32_t sl : r.slots) {
+            SlotState& ss = S->slot[sl];
+            if (!ss.busy || ss.req != id) continue;  // finished (and recycled by its work group) already
+            if (launch_zero(S->d_bs.as<char>() + (size_t)sl * S->gdim * 16, (size_t)S->gdim * 16, S->st) !=
+                    hipSuccess ||
+                launch_zero(S->d_done.as<uint32_t>() + sl, 4, S->st) != hipSuccess ||
+                (ss.psum_n && (launch_zero(S->d_psum.as<char>() + (size_t)ss.psum_base * 32, (size_t)ss.psum_n * 32,
+                                           S->st) != hipSuccess ||
+                               launch_zero(S->d_pcount.as<uint32_t>() + ss.psum_base, (size_t)ss.psum_n * 4,
+                                           S->st) != hipSuccess)))
+                return BD_E_HIP;
+            zeroed = true;
+            r.res[(size_t)ss.ridx].status = BD_E_CANCELLED;
+            r.res[(size_t)ss.ridx].beta = 0.0;
+            S->inflight_steps -= std::min(S->inflight_steps, ss.steps);
+            S->psum_alloc.release(ss.psum_base, ss.psum_n);
+            ss.psum_n = 0;
+            ss.busy = false;
+            S->free_slots.push_back(sl);
+            --r.remaining;
+        }
+        if (zeroed) {
+            // slices launched from now on wait for the clearing
+            if (hipEventRecord(S->ev_admit, S->st) != hipSuccess) return BD_E_HIP;
+            S->admit_recorded = true;
+        }
+        if (!r.done) finish_request(S, id, r);
+        S->cancelled.erase(S->cancelled.begin() + (ptrdiff_t)i);
     }
     return BD_OK;
 }
@@ -1838,12 +1983,16 @@ void fill_slice(bd_server* S, Slice& sl)
         const uint64_t id = S->rr.front();
         S->rr.pop_front();
         Request& r = S->reqs[id];
+        if (r.cancelled) {
+            r.in_rr = false;
+            continue;
+        }
         const uint32_t q = r.rr_slots.front();
         r.rr_slots.pop_front();
         SlotState& ss = S->slot[q];
         sl.steps += ss.cur.chunk_steps(ss.L);
         const Chunk c = ss.cur.next();
-        const uint64_t wg = (uint64_t)block_threads(S->g->layout, share_class(policy_share(S->pol)));
+        const uint64_t wg = (uint64_t)block_threads(S->g->kernel_layout, share_class(policy_share(S->pol)));
         const double cost = ((double)ss.L + 1.0) * (double)(((uint64_t)c.gc * c.pc + wg - 1) / wg);
         sl.sum_cost += cost;
         if (cost > sl.max_cost) {
@@ -1904,7 +2053,7 @@ int launch_slice(bd_server* S, Slice& sl)
         ap.qoff[0] = 0;
         ap.qoff[1] = ap.nchunks;
         const uint32_t grid = std::min<uint32_t>((uint32_t)S->resident[part == 0], ap.nchunks);
-        if (grid && launch_walk(ap, S->g->layout, part == 0, share_class(policy_share(S->pol)), grid, st) !=
+        if (grid && launch_walk(ap, S->g->kernel_layout, part == 0, share_class(policy_share(S->pol)), grid, st) !=
                         hipSuccess)
             return BD_E_HIP;
     }
@@ -1913,6 +2062,7 @@ int launch_slice(bd_server* S, Slice& sl)
     if (hipEventRecord(sl.ev, st) != hipSuccess) return BD_E_HIP;
     sl.inflight = true;
     sl.t_launch = now_ms();
+    ++S->slices_launched;
     return BD_OK;
 }
 
@@ -1936,7 +2086,7 @@ void server_loop(bd_server* S)
     for (;;) {
         S->cv_work.wait(lk, [&] {
             return S->stop || !S->pending.empty() || !S->rr.empty() || S->slice[0].inflight ||
-                   S->slice[1].inflight;
+                   S->slice[1].inflight || !S->cancelled.empty();
         });
         const bool any_inflight = S->slice[0].inflight || S->slice[1].inflight;
         if (S->stop && !any_inflight) break;
@@ -1960,9 +2110,11 @@ void server_loop(bd_server* S)
                     S->ms_per_lane_step = 0.7 * S->ms_per_lane_step +
                                           0.3 * std::min(dt * (double)S->resident[0] / sl.sum_cost, 1e-2);
                 rc = process_completions(S, sl);
+                ++S->slices_done;
             }
             sl.inflight = false;
         }
+        if (rc == BD_OK && !S->cancelled.empty()) rc = reclaim_cancelled(S);
         if (rc == BD_OK && !S->stop) {
             rc = admit(S);
             if (rc == BD_OK) {
@@ -2081,7 +2233,7 @@ extern "C" int bd_server_submit(bd_server* S, int64_t nq, const int32_t* s, cons
         r.index.push_back(i);
         r.steps += (uint64_t)pr.walk_steps;
         const bd_exec ex = server_exec(S);
-        if (chunk_plan(ex, d, S->g->layout).part) r.split_probes += d.K;
+        if (chunk_plan(ex, d, S->g->kernel_layout).part) r.split_probes += d.K;
     }
     r.remaining = (int64_t)r.desc.size();
     if (r.desc.size() > S->slots || r.split_probes > S->arena) return BD_E_FULL;
@@ -2134,6 +2286,32 @@ extern "C" int bd_server_wait(bd_server* S, uint64_t request_id, double timeout_
     if (out) std::memcpy(out, it->second.res.data(), it->second.res.size() * sizeof(bd_result));
     if (latency_ms) *latency_ms = it->second.t_done - it->second.t_submit;
     S->reqs.erase(it);
+    return BD_OK;
+}
+
+extern "C" int bd_server_cancel(bd_server* S, uint64_t request_id)
+{
+    if (!S) return BD_E_INVALID;
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        auto it = S->reqs.find(request_id);
+        if (it == S->reqs.end()) return BD_E_NOTFOUND;
+        Request& r = it->second;
+        if (r.done || r.cancelled) return BD_OK;
+        r.cancelled = true;
+        if (!r.admitted) {
+            // still queued: nothing of it reached the device
+            S->pending.erase(std::remove(S->pending.begin(), S->pending.end(), request_id), S->pending.end());
+            for (size_t i = 0; i < r.index.size(); ++i) r.res[(size_t)r.index[i]].status = BD_E_CANCELLED;
+            finish_request(S, request_id, r);
+            return BD_OK;
+        }
+        // admitted: its chunks already on the device finish; the slots of the
+        // queries they leave unfinished are reclaimed once those slices are done
+        r.cancel_mark = S->slices_launched;
+        S->cancelled.push_back(request_id);
+    }
+    S->cv_work.notify_all();
     return BD_OK;
 }
 

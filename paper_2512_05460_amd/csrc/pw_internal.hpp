@@ -84,6 +84,10 @@ struct WalkArgs {
     // when that one is empty, so chunks of one query share an XCD's L2.
     uint32_t nqueues;
     uint32_t qoff[9];
+    // Optional abort flag in host memory mapped for the device (a watchdog on
+    // the host sets it): a work group reads it before each chunk and, once it
+    // is nonzero, takes no further chunk.
+    const uint32_t* abort_flag;
 };
 
 // Largest walk-sharing group the kernels are built for.
@@ -93,14 +97,18 @@ inline int share_class(uint32_t M) { return M <= 1 ? 1 : M <= 2 ? 2 : 4; }
 
 constexpr int kBlockThreads = 256;
 // Work-group size of the walk and gather kernels per layout code and walk
-// sharing class. With one probe per walk the hubs-first layouts (codes 3 and
-// 4) stage the node entries of the 8,192 highest-degree nodes (64 KB) in LDS
+// sharing class. With one probe per walk the hubs-first layouts (codes 3, 4
+// and 5) stage the node entries of the 8,192 highest-degree nodes (64 KB; the
+// 16,384 row offsets with the probe on storage ids, code 5) in LDS
 // once per 1,024-thread work group: two groups per CU keep 8 waves per SIMD
 // within the 160 KB of LDS, and the staged nodes take 42% of the steps on a
 // Chung-Lu n=1e5 graph (1,024 nodes per 256-thread group take 18%). The
 // sharing kernels run 4-5 waves per SIMD, one such group per CU, and keep
 // 256-thread groups with 1,024 staged nodes.
-constexpr int block_threads(int layout, int share) { return (layout == 3 || layout == 4) && share <= 1 ? 1024 : kBlockThreads; }
+constexpr int block_threads(int layout, int share)
+{
+    return (layout == 3 || layout == 4 || layout == 5) && share <= 1 ? 1024 : kBlockThreads;
+}
 constexpr uint32_t kMaxQueues = 8;      // one chunk queue per XCD
 constexpr int kMaxChunkProbes = 256;
 constexpr int kMaxG = 128;
@@ -133,8 +141,15 @@ hipError_t launch_gather(const GraphTables& g, int layout, int chains, uint32_t 
 hipError_t launch_spmv_step(const uint32_t* rp, const uint32_t* col, const uint32_t* col24, uint32_t n, uint32_t Q,
                             const double* V, double* Y, double* H, hipStream_t st);
 hipError_t launch_colsum(const double* H, uint32_t n, uint32_t Q, double* sq, double* lin, hipStream_t st);
-hipError_t launch_nmul(const uint32_t* rp, const uint32_t* col, const uint32_t* col24, uint32_t n, const double* x,
-                       double* y, hipStream_t st);
+// v_0 = D^{-1} b_st columns (Q <= 64): entries s[q] = vs[q], t[q] = vt[q] of V and H,
+// which the caller has zeroed.
+hipError_t launch_series_seed(const uint32_t* s, const uint32_t* t, const double* vs, const double* vt, uint32_t Q,
+                              double* V, double* H, hipStream_t st);
+// Power iteration for lambda, all on the device: phi, x, y, z are n doubles,
+// part 2 * 1024 doubles, scal 2 doubles; the estimate ends in scal[1].
+hipError_t launch_lambda(const uint32_t* rp, const uint32_t* col, const uint32_t* col24, uint32_t n, uint32_t nnz,
+                         int32_t iters, uint64_t seed, double* phi, double* x, double* y, double* z, double* part,
+                         double* scal, hipStream_t st);
 // Work groups of the walk kernel that fit on the device at once.
 int walk_occupancy(int layout, int uniform, int share, int* wgs_per_cu);
 

@@ -14,6 +14,8 @@
 // The same chunk routine serves one-query-per-launch (grid = chunks) and
 // persistent launches (grid = resident capacity, chunks claimed from per-XCD
 // atomic cursors until none are left, so every wave exits).
+#include <algorithm>
+
 #include "pw_device.hpp"
 #include "pw_internal.hpp"
 
@@ -29,6 +31,7 @@ __device__ __forceinline__ DevGraph make_graph(const GraphTables& g)
     G.col24 = g.col24;
     G.node8 = g.node8;
     G.hub = nullptr;
+    G.hub4 = nullptr;
     G.nhub = 0;
     G.dom.n = g.dom.n;
     G.dom.rb = g.dom.rb;
@@ -367,23 +370,36 @@ __device__ void run_chunk(const WalkArgs& A, const DevGraph& G, uint32_t ci,
     __syncthreads();
 }
 
+// The host watchdog's abort flag (host memory, read at system scope; the
+// value is uniform over the work group once read by one thread, and a flag
+// seen late only lets one more chunk run).
+__device__ __forceinline__ bool abort_raised(const WalkArgs& A)
+{
+    return A.abort_flag != nullptr &&
+           __hip_atomic_load(A.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) != 0u;
+}
+
 // kUniform: every chunk of the launch has R >= kUniformMinR (see run_chunk).
 // Eight waves per SIMD where the kernel fits 64 VGPRs without spilling.
 template <int kLayout, int kUniform, int kShare>
-__global__ __launch_bounds__(block_threads(kLayout, kShare), kShare == 1 && (kUniform || kLayout == kLayoutCompact ||
-                                                            kLayout == kLayoutCompactHub ||
-                                                            kLayout == kLayoutHub32) ? 8 : 1) void walk_kernel(
-    WalkArgs A)
+__global__ __launch_bounds__(block_threads(kLayout, kShare),
+                             kShare == 1 && (kUniform || kLayout == kLayoutCompact || hub_layout(kLayout)) ? 8
+                                                                                                            : 1) void
+walk_kernel(WalkArgs A)
 {
     __shared__ unsigned long long acc[kMaxChunkProbes * 4];
     __shared__ double ys[kMaxG];
     __shared__ uint32_t next;
-    constexpr uint32_t kHubs = hub_nodes(block_threads(kLayout, kShare));
-    __shared__ uint2 hub_lds[kLayout == kLayoutCompactHub || kLayout == kLayoutHub32 ? kHubs + 1 : 1];
+    constexpr int kT = block_threads(kLayout, kShare);
+    constexpr uint32_t kHubs = hub_nodes(kT, kLayout);
+    __shared__ __align__(16) uint32_t hub_lds[hub_words(kT, kLayout)];
     DevGraph G = make_graph(A.g);
     stage_hubs<kLayout>(G, hub_lds, kHubs);
     if (!A.persistent) {
-        if (blockIdx.x < A.nchunks) run_chunk<kLayout, kUniform, kShare>(A, G, blockIdx.x, acc, ys);
+        // one read of the abort flag for the whole work group (run_chunk has barriers)
+        if (threadIdx.x == 0) next = abort_raised(A) ? 1u : 0u;
+        __syncthreads();
+        if (blockIdx.x < A.nchunks && next == 0u) run_chunk<kLayout, kUniform, kShare>(A, G, blockIdx.x, acc, ys);
         return;
     }
     // Claim chunks from the queue of this XCD first, then from the others in
@@ -402,6 +418,7 @@ __global__ __launch_bounds__(block_threads(kLayout, kShare), kShare == 1 && (kUn
         if (threadIdx.x == 0) {
             uint32_t ci = 0xFFFFFFFFu;
             uint32_t qi = qstate[0], tried = qstate[1];
+            if (abort_raised(A)) tried = A.nqueues;  // take no further chunk
             while (tried < A.nqueues) {
                 const uint32_t beg = A.qoff[qi];
                 const uint32_t c = atomicAdd(A.cursor + qi, 1u);
@@ -435,9 +452,11 @@ static const void* walk_fn_l(int uniform, int share)
 static const void* walk_fn(int layout, int uniform, int share)
 {
     if (layout == kLayoutFat) return walk_fn_l<kLayoutFat>(uniform, share);
+    if (layout == kLayoutFatNT) return walk_fn_l<kLayoutFatNT>(uniform, share);
     if (layout == kLayoutCompact) return walk_fn_l<kLayoutCompact>(uniform, share);
     if (layout == kLayoutCompactHub) return walk_fn_l<kLayoutCompactHub>(uniform, share);
     if (layout == kLayoutHub32) return walk_fn_l<kLayoutHub32>(uniform, share);
+    if (layout == kLayoutHubId) return walk_fn_l<kLayoutHubId>(uniform, share);
     return walk_fn_l<kLayoutCsr>(uniform, share);
 }
 
@@ -458,6 +477,9 @@ hipError_t launch_walk(const WalkArgs& a, int layout, int uniform, int share, ui
     if (layout == kLayoutFat) {
         if (uniform) launch_l<kLayoutFat, 1>(a, share, grid, st);
         else launch_l<kLayoutFat, 0>(a, share, grid, st);
+    } else if (layout == kLayoutFatNT) {
+        if (uniform) launch_l<kLayoutFatNT, 1>(a, share, grid, st);
+        else launch_l<kLayoutFatNT, 0>(a, share, grid, st);
     } else if (layout == kLayoutCompact) {
         if (uniform) launch_l<kLayoutCompact, 1>(a, share, grid, st);
         else launch_l<kLayoutCompact, 0>(a, share, grid, st);
@@ -467,6 +489,9 @@ hipError_t launch_walk(const WalkArgs& a, int layout, int uniform, int share, ui
     } else if (layout == kLayoutHub32) {
         if (uniform) launch_l<kLayoutHub32, 1>(a, share, grid, st);
         else launch_l<kLayoutHub32, 0>(a, share, grid, st);
+    } else if (layout == kLayoutHubId) {
+        if (uniform) launch_l<kLayoutHubId, 1>(a, share, grid, st);
+        else launch_l<kLayoutHubId, 0>(a, share, grid, st);
     } else {
         if (uniform) launch_l<kLayoutCsr, 1>(a, share, grid, st);
         else launch_l<kLayoutCsr, 0>(a, share, grid, st);
@@ -561,9 +586,11 @@ hipError_t launch_trace(const GraphTables& g, int layout, uint32_t count, const 
     const uint32_t blocks = (count + 127) / 128;
 #define PW_TRACE(Lay) hipLaunchKernelGGL(trace_kernel<Lay>, dim3(blocks), dim3(128), 0, st, g, count, start, uid, k, p, side, L, slo, shi, trace, acc)
     if (layout == kLayoutFat) PW_TRACE(1);
+    else if (layout == kLayoutFatNT) PW_TRACE(6);
     else if (layout == kLayoutCompact) PW_TRACE(2);
     else if (layout == kLayoutCompactHub) PW_TRACE(3);
     else if (layout == kLayoutHub32) PW_TRACE(4);
+    else if (layout == kLayoutHubId) PW_TRACE(5);
     else PW_TRACE(0);
 #undef PW_TRACE
     return hipGetLastError();
@@ -605,8 +632,9 @@ template <int kLayout, int kChains>
 __global__ __launch_bounds__(block_threads(kLayout, 1)) void gather_kernel(GraphTables gt, int32_t steps, uint32_t seed,
                                                                uint32_t* sink)
 {
-    constexpr uint32_t kHubs = hub_nodes(block_threads(kLayout, 1));
-    __shared__ uint2 hub_lds[kLayout == kLayoutCompactHub || kLayout == kLayoutHub32 ? kHubs + 1 : 1];
+    constexpr int kT = block_threads(kLayout, 1);
+    constexpr uint32_t kHubs = hub_nodes(kT, kLayout);
+    __shared__ __align__(16) uint32_t hub_lds[hub_words(kT, kLayout)];
     DevGraph G = make_graph(gt);
     stage_hubs<kLayout>(G, hub_lds, kHubs);
     const uint32_t gid = blockIdx.x * blockDim.x + threadIdx.x;
@@ -651,9 +679,11 @@ hipError_t launch_gather(const GraphTables& g, int layout, int chains, uint32_t 
         else PW_GATHER(F, 8);           \
     } while (0)
     if (layout == kLayoutFat) PW_GATHER_C(1);
+    else if (layout == kLayoutFatNT) PW_GATHER_C(6);
     else if (layout == kLayoutCompact) PW_GATHER_C(2);
     else if (layout == kLayoutCompactHub) PW_GATHER_C(3);
     else if (layout == kLayoutHub32) PW_GATHER_C(4);
+    else if (layout == kLayoutHubId) PW_GATHER_C(5);
     else PW_GATHER_C(0);
 #undef PW_GATHER_C
 #undef PW_GATHER
@@ -665,39 +695,71 @@ hipError_t launch_gather(const GraphTables& g, int layout, int chains, uint32_t 
 namespace pw {
 
 // ---------------------------------------------------------------------------
-// Truncated series in binary64 (Lemma 2.3): h^(L) = sum_{i<=L} P^i D^{-1} b for
-// Q queries at once. V and Y are n x Q row-major; one wave per row, lanes over
-// queries, so the neighbour gathers of a row read Q consecutive values.
-//   y[x][q] = (1/d_x) * sum_{u in N(x)} v[u][q]     (in neighbour order)
-//   h[x][q] += y[x][q]
+// Sparse products in binary64 for the truncated series (Lemma 2.3) and the
+// mixing factor (section 2.1). V is n x Q row-major (Q <= 64 columns).
+//
+// One wave per row. Its lanes are J = 64/Qp neighbour slots times Qp columns
+// (Qp = the power of two >= Q): lane (j, q) sums V[u][q] over the row's
+// neighbours j, j + J, j + 2J, ..., and a butterfly over the J slots (the same
+// value in every lane of a column, in a fixed order) completes the row sum. With
+// Q = 64 a lane owns one column and walks the whole row; with Q = 1 the 64
+// lanes share the row's neighbours.
+//   kMode 0 (series step):     y[x][q] = (1/d_x) sum_u v[u][q];  h[x][q] += y[x][q]
+//   kMode 1 (normalised A):    y[x]    = (1/sqrt d_x) sum_u v[u]  (v = x / sqrt d)
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void spmv_step_kernel(const uint32_t* rp, const uint32_t* col,
-                                                        const uint32_t* col24, uint32_t n, uint32_t Q,
-                                                        const double* V, double* Y, double* H)
+__device__ __forceinline__ uint32_t nbr_at(const uint32_t* col, const uint32_t* col24, uint32_t i)
+{
+    if (col24) {
+        const uint32_t o = i * 3u;
+        return __builtin_amdgcn_alignbit(col24[(o >> 2) + 1], col24[o >> 2], (o & 3u) * 8u) & 0xFFFFFFu;
+    }
+    return col[i];
+}
+
+template <int kMode>
+__global__ __launch_bounds__(256) void rowsum_kernel(const uint32_t* rp, const uint32_t* col, const uint32_t* col24,
+                                                     uint32_t n, uint32_t Q, uint32_t qbits, const double* V,
+                                                     double* Y, double* H)
 {
     const uint32_t row = blockIdx.x * 4u + (threadIdx.x >> 6);
+    if (row >= n) return;  // wave-uniform: the whole wave leaves
     const uint32_t lane = threadIdx.x & 63u;
-    if (row >= n) return;
+    const uint32_t Qp = 1u << qbits;
+    const uint32_t q = lane & (Qp - 1u);
+    const uint32_t j = lane >> qbits;
+    const uint32_t J = 64u >> qbits;
     const uint32_t b = rp[row], e = rp[row + 1];
-    for (uint32_t q0 = 0; q0 < Q; q0 += 64u) {
-        const uint32_t q = q0 + lane;
-        if (q < Q) {
-            double acc = 0.0;
-            for (uint32_t i = b; i < e; ++i) {
-                uint32_t u;
-                if (col24) {
-                    const uint32_t o = i * 3u;
-                    u = __builtin_amdgcn_alignbit(col24[(o >> 2) + 1], col24[o >> 2], (o & 3u) * 8u) & 0xFFFFFFu;
-                } else {
-                    u = col[i];
-                }
-                acc = __dadd_rn(acc, V[(size_t)u * Q + q]);
-            }
-            const double y = __dmul_rn(acc, __ddiv_rn(1.0, (double)(e - b)));
-            Y[(size_t)row * Q + q] = y;
-            H[(size_t)row * Q + q] = __dadd_rn(H[(size_t)row * Q + q], y);
-        }
+    double acc = 0.0;
+    if (q < Q)
+        for (uint32_t i = b + j; i < e; i += J) acc = __dadd_rn(acc, V[(size_t)nbr_at(col, col24, i) * Q + q]);
+    for (uint32_t off = Qp; off < 64u; off <<= 1) acc = __dadd_rn(acc, __shfl_xor(acc, (int)off));
+    if (j != 0 || q >= Q) return;
+    const double d = (double)(e - b);
+    if (kMode == 0) {
+        const double y = __dmul_rn(acc, __ddiv_rn(1.0, d));
+        const size_t at = (size_t)row * Q + q;
+        Y[at] = y;
+        H[at] = __dadd_rn(H[at], y);
+    } else {
+        Y[row] = __ddiv_rn(acc, sqrt(d));
     }
+}
+
+// v_0 = D^{-1} b_st for up to 64 queries: zero first, then the two entries of
+// each column (storage ids and degrees in the argument block).
+struct SeriesSeed {
+    uint32_t s[64], t[64];
+    double vs[64], vt[64];
+};
+
+__global__ void series_seed_kernel(SeriesSeed a, uint32_t Q, double* V, double* H)
+{
+    const uint32_t q = threadIdx.x;
+    if (q >= Q) return;
+    V[(size_t)a.s[q] * Q + q] = a.vs[q];
+    V[(size_t)a.t[q] * Q + q] = a.vt[q];
+    H[(size_t)a.s[q] * Q + q] = a.vs[q];
+    H[(size_t)a.t[q] * Q + q] = a.vt[q];
 }
 
 // Per-query sums ||h||^2 and 1^T h in a fixed order: one work group per query,
@@ -729,10 +791,32 @@ __global__ __launch_bounds__(256) void colsum_kernel(const double* H, uint32_t n
     }
 }
 
+static uint32_t pow2_bits(uint32_t Q)
+{
+    uint32_t b = 0;
+    while ((1u << b) < Q) ++b;
+    return b;
+}
+
 hipError_t launch_spmv_step(const uint32_t* rp, const uint32_t* col, const uint32_t* col24, uint32_t n, uint32_t Q,
                             const double* V, double* Y, double* H, hipStream_t st)
 {
-    hipLaunchKernelGGL(spmv_step_kernel, dim3((n + 3) / 4), dim3(256), 0, st, rp, col, col24, n, Q, V, Y, H);
+    hipLaunchKernelGGL(rowsum_kernel<0>, dim3((n + 3) / 4), dim3(256), 0, st, rp, col, col24, n, Q, pow2_bits(Q), V,
+                       Y, H);
+    return hipGetLastError();
+}
+
+hipError_t launch_series_seed(const uint32_t* s, const uint32_t* t, const double* vs, const double* vt, uint32_t Q,
+                              double* V, double* H, hipStream_t st)
+{
+    SeriesSeed a{};
+    for (uint32_t q = 0; q < Q && q < 64; ++q) {
+        a.s[q] = s[q];
+        a.t[q] = t[q];
+        a.vs[q] = vs[q];
+        a.vt[q] = vt[q];
+    }
+    hipLaunchKernelGGL(series_seed_kernel, dim3(1), dim3(64), 0, st, a, Q, V, H);
     return hipGetLastError();
 }
 
@@ -744,34 +828,116 @@ hipError_t launch_colsum(const double* H, uint32_t n, uint32_t Q, double* sq, do
 
 // ---------------------------------------------------------------------------
 // Spectral radius of P off the stationary direction: power iteration on the
-// symmetric N = D^{-1/2} A D^{-1/2} (same spectrum as P) with the top
-// eigenvector sqrt(d)/||sqrt(d)|| projected out each step.
-//   y = N x; then y -= (phi . y) phi
+// symmetric N = D^{-1/2} A D^{-1/2} (same spectrum as P), whose top
+// eigenvector is phi = sqrt(d)/||sqrt(d)|| = sqrt(d / nnz). Every iteration
+// runs on the device: z = x / sqrt(d); y = N x (rowsum_kernel<1>); the two sums
+// phi.y and y.y in a fixed order (per-block partials, then one block); and
+// x = (y - (phi.y) phi) / ||y - (phi.y) phi||, whose norm
+// sqrt(y.y - (phi.y)^2) (phi is a unit vector) is the estimate of lambda.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void nmul_kernel(const uint32_t* rp, const uint32_t* col, const uint32_t* col24,
-                                                   uint32_t n, const double* x, double* y)
+constexpr uint32_t kDotBlocks = 1024;
+
+__global__ __launch_bounds__(256) void phi_kernel(const uint32_t* rp, uint32_t n, double nnz, double* phi)
 {
-    const uint32_t row = blockIdx.x * blockDim.x + threadIdx.x;
-    if (row >= n) return;
-    const uint32_t b = rp[row], e = rp[row + 1];
-    double acc = 0.0;
-    for (uint32_t i = b; i < e; ++i) {
-        uint32_t u;
-        if (col24) {
-            const uint32_t o = i * 3u;
-            u = __builtin_amdgcn_alignbit(col24[(o >> 2) + 1], col24[o >> 2], (o & 3u) * 8u) & 0xFFFFFFu;
-        } else {
-            u = col[i];
-        }
-        acc = __dadd_rn(acc, __ddiv_rn(x[u], sqrt((double)(rp[u + 1] - rp[u]))));
-    }
-    y[row] = __ddiv_rn(acc, sqrt((double)(e - b)));
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        phi[i] = sqrt(__ddiv_rn((double)(rp[i + 1] - rp[i]), nnz));
 }
 
-hipError_t launch_nmul(const uint32_t* rp, const uint32_t* col, const uint32_t* col24, uint32_t n, const double* x,
-                       double* y, hipStream_t st)
+// a counter-based start vector: the SplitMix64 output function of seed + i
+// times the golden-ratio increment, mapped to [-1/2, 1/2)
+__global__ __launch_bounds__(256) void start_vector_kernel(uint64_t seed, uint32_t n, double* x)
 {
-    hipLaunchKernelGGL(nmul_kernel, dim3((n + 255) / 256), dim3(256), 0, st, rp, col, col24, n, x, y);
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        uint64_t z = seed + (uint64_t)(i + 1) * 0x9E3779B97F4A7C15ull;
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        z ^= z >> 31;
+        x[i] = (double)(z >> 11) * 0x1p-53 - 0.5;
+    }
+}
+
+__global__ __launch_bounds__(256) void scale_rsqrt_deg_kernel(const uint32_t* rp, uint32_t n, const double* x,
+                                                              double* z)
+{
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        z[i] = __ddiv_rn(x[i], sqrt((double)(rp[i + 1] - rp[i])));
+}
+
+__device__ __forceinline__ void block_sum2(double* a, double* c)
+{
+    for (uint32_t w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+            a[threadIdx.x] = __dadd_rn(a[threadIdx.x], a[threadIdx.x + w]);
+            c[threadIdx.x] = __dadd_rn(c[threadIdx.x], c[threadIdx.x + w]);
+        }
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(256) void dot2_kernel(const double* phi, const double* y, uint32_t n, double* part)
+{
+    __shared__ double a[256], c[256];
+    double py = 0.0, yy = 0.0;
+    for (uint32_t i = blockIdx.x * 256u + threadIdx.x; i < n; i += gridDim.x * 256u) {
+        py = __dadd_rn(py, __dmul_rn(phi[i], y[i]));
+        yy = __dadd_rn(yy, __dmul_rn(y[i], y[i]));
+    }
+    a[threadIdx.x] = py;
+    c[threadIdx.x] = yy;
+    __syncthreads();
+    block_sum2(a, c);
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = a[0];
+        part[2 * blockIdx.x + 1] = c[0];
+    }
+}
+
+// scal[0] = phi.y, scal[1] = sqrt(max(y.y - (phi.y)^2, 0))
+__global__ __launch_bounds__(256) void dot2_finish_kernel(const double* part, uint32_t nb, double* scal)
+{
+    __shared__ double a[256], c[256];
+    double py = 0.0, yy = 0.0;
+    for (uint32_t i = threadIdx.x; i < nb; i += 256u) {
+        py = __dadd_rn(py, part[2 * i]);
+        yy = __dadd_rn(yy, part[2 * i + 1]);
+    }
+    a[threadIdx.x] = py;
+    c[threadIdx.x] = yy;
+    __syncthreads();
+    block_sum2(a, c);
+    if (threadIdx.x == 0) {
+        scal[0] = a[0];
+        scal[1] = sqrt(fmax(__dsub_rn(c[0], __dmul_rn(a[0], a[0])), 0.0));
+    }
+}
+
+__global__ __launch_bounds__(256) void project_kernel(const double* y, const double* phi, const double* scal,
+                                                      uint32_t n, double* x)
+{
+    const double dot = scal[0], nrm = scal[1];
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        x[i] = nrm > 0.0 ? __ddiv_rn(__dsub_rn(y[i], __dmul_rn(dot, phi[i])), nrm) : 0.0;
+}
+
+hipError_t launch_lambda(const uint32_t* rp, const uint32_t* col, const uint32_t* col24, uint32_t n, uint32_t nnz,
+                         int32_t iters, uint64_t seed, double* phi, double* x, double* y, double* z, double* part,
+                         double* scal, hipStream_t st)
+{
+    const dim3 grid(std::min<uint32_t>((n + 255) / 256, 16384u)), block(256);
+    const uint32_t nb = std::min<uint32_t>(kDotBlocks, (n + 255) / 256);
+    hipLaunchKernelGGL(phi_kernel, grid, block, 0, st, rp, n, (double)nnz, phi);
+    hipLaunchKernelGGL(start_vector_kernel, grid, block, 0, st, seed, n, y);
+    hipLaunchKernelGGL(dot2_kernel, dim3(nb), block, 0, st, phi, y, n, part);
+    hipLaunchKernelGGL(dot2_finish_kernel, dim3(1), block, 0, st, part, nb, scal);
+    hipLaunchKernelGGL(project_kernel, grid, block, 0, st, y, phi, scal, n, x);
+    for (int32_t it = 0; it < iters; ++it) {
+        hipLaunchKernelGGL(scale_rsqrt_deg_kernel, grid, block, 0, st, rp, n, x, z);
+        hipLaunchKernelGGL(rowsum_kernel<1>, dim3((n + 3) / 4), block, 0, st, rp, col, col24, n, 1u, 0u, z, y,
+                           (double*)nullptr);
+        hipLaunchKernelGGL(dot2_kernel, dim3(nb), block, 0, st, phi, y, n, part);
+        hipLaunchKernelGGL(dot2_finish_kernel, dim3(1), block, 0, st, part, nb, scal);
+        hipLaunchKernelGGL(project_kernel, grid, block, 0, st, y, phi, scal, n, x);
+    }
     return hipGetLastError();
 }
 

@@ -93,7 +93,8 @@ def test_result_layout_matches_header(tmp_path):
                      ctypes.sizeof(binding.BdExec), ctypes.sizeof(binding.BdStats),
                      ctypes.sizeof(binding.BdServerCfg), ctypes.sizeof(binding.BdGraphInfo),
                      ctypes.sizeof(binding.BdRoofline)]
-    assert ctypes.sizeof(binding.BdExec) == 28
+    assert ctypes.sizeof(binding.BdExec) == 40
+    assert ctypes.sizeof(binding.BdAllocator) == 3 * ctypes.sizeof(ctypes.c_void_p)
 
 
 def test_binding_has_no_fallback(monkeypatch, tmp_path):
@@ -101,3 +102,17 @@ def test_binding_has_no_fallback(monkeypatch, tmp_path):
     monkeypatch.setattr(binding, "_lib", None)
     with pytest.raises(ImportError):
         binding.lib()
+
+
+def test_storage_probe_flag_combinations():
+    # BD_PROBE_STORAGE_IDS needs BD_LAYOUT_COMPACT | BD_RELABEL_DEGREE and takes
+    # neither BD_WIDE_IDS nor BD_LAYOUT_AUTO; checked before any device work
+    g = graphs.workload_graph("ba1k")
+    full = binding.BD_LAYOUT_COMPACT | binding.BD_RELABEL_DEGREE | binding.BD_PROBE_STORAGE_IDS
+    for bad in (binding.BD_PROBE_STORAGE_IDS, binding.BD_PROBE_STORAGE_IDS | binding.BD_LAYOUT_COMPACT,
+                full | binding.BD_WIDE_IDS, binding.BD_PROBE_STORAGE_IDS | binding.BD_LAYOUT_AUTO,
+                binding.BD_PROBE_STORAGE_IDS | binding.BD_LAYOUT_FAT | binding.BD_RELABEL_DEGREE):
+        h = ctypes.c_void_p()
+        rc = binding.lib().graph_load_csr(g.n, g.row_ptr.ctypes.data_as(ctypes.c_void_p),
+                                          g.col.ctypes.data_as(ctypes.c_void_p), bad, None, ctypes.byref(h))
+        assert rc == binding.BD_E_INVALID, bad

@@ -64,12 +64,15 @@ def test_device_info():
 @pytest.mark.parametrize("layout,code", [(B.BD_LAYOUT_CSR, 0), (B.BD_LAYOUT_FAT, 1),
                                          (B.BD_LAYOUT_FAT | B.BD_RELABEL_DEGREE, 1), (B.BD_LAYOUT_COMPACT, 2),
                                          (B.BD_LAYOUT_COMPACT | B.BD_RELABEL_DEGREE, 3),
-                                         (B.BD_LAYOUT_COMPACT | B.BD_RELABEL_DEGREE | B.BD_WIDE_IDS, 4)])
+                                         (B.BD_LAYOUT_COMPACT | B.BD_RELABEL_DEGREE | B.BD_WIDE_IDS, 4),
+                                         (B.BD_LAYOUT_FAT | B.BD_NONTEMPORAL, 1),
+                                         (B.BD_LAYOUT_FAT | B.BD_RELABEL_DEGREE | B.BD_TEMPORAL, 1)])
 def test_graph_info(ba1k, layout, code):
     gi = load(ba1k, layout).info()
     assert gi["n"] == ba1k.n and gi["nnz"] == ba1k.nnz
     assert gi["d_min"] == ba1k.d_min and gi["d_max"] == ba1k.d_max
     assert gi["layout"] == code and gi["bipartite"] == 0
+    assert gi["nontemporal"] == (1 if layout & B.BD_NONTEMPORAL else 0)  # small fat tables: ordinary loads
 
 
 def test_auto_layout(ba1k):
@@ -103,7 +106,8 @@ def test_probe_parity(name):
 
 LAYOUTS = [B.BD_LAYOUT_CSR, B.BD_LAYOUT_FAT, B.BD_LAYOUT_CSR | B.BD_RELABEL_DEGREE,
            B.BD_LAYOUT_FAT | B.BD_RELABEL_DEGREE, B.BD_LAYOUT_COMPACT, B.BD_LAYOUT_COMPACT | B.BD_RELABEL_DEGREE,
-           B.BD_LAYOUT_COMPACT | B.BD_RELABEL_DEGREE | B.BD_WIDE_IDS]
+           B.BD_LAYOUT_COMPACT | B.BD_RELABEL_DEGREE | B.BD_WIDE_IDS,
+           B.BD_LAYOUT_FAT | B.BD_RELABEL_DEGREE | B.BD_NONTEMPORAL]
 
 
 @pytest.mark.parametrize("layout", LAYOUTS)

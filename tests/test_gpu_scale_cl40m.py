@@ -96,6 +96,7 @@ def test_cl40m_fat_equals_hubs_first(cl40m):
     try:
         info = fat.info()
         assert info["layout"] == 1
+        assert info["nontemporal"] == 1  # 20.7 GB of fat tables: above the 4 GiB threshold
         assert 16 * g.n + 20 * g.nnz <= info["device_bytes"] <= 20 * g.n + 20 * g.nnz + (64 << 20)
         res = B.bd_query_batch(fat, s, t, eps, L, SEED, pol, B.exec_cfg("batched"))
         assert np.array_equal(res["beta"], ref["beta"])

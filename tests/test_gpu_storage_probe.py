@@ -1,0 +1,113 @@
+"""The hubs-first layout with the probe on storage ids (BD_PROBE_STORAGE_IDS,
+layout code 5) against the oracle run on the relabelled graph.
+
+The relabelled graph is built here with numpy: node i of it is the caller's
+node of rank i in descending degree (ties by ascending id), each row keeps the
+caller's neighbour order with the ids renamed. On that graph the library's
+results must equal the oracle's bit for bit (Algorithm 1: probe values,
+walks, per-probe Q, block means, estimates, in every mode, with split probes
+and with walk sharing), and its walks, reported in caller ids, are the same
+walks as every other layout's.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import estimator as E
+from oracle import planner as OP
+from paper_2512_05460_amd import binding as B
+from synth import graphs, queries
+
+pytestmark = pytest.mark.gpu
+
+SEED = graphs.PHILOX_SEED
+FLAGS = B.BD_LAYOUT_COMPACT | B.BD_RELABEL_DEGREE | B.BD_PROBE_STORAGE_IDS
+
+
+def relabelled(g):
+    order = np.argsort(-g.deg, kind="stable")  # storage id -> caller id
+    internal = np.empty(g.n, dtype=np.int64)
+    internal[order] = np.arange(g.n)
+    deg = g.deg[order]
+    rp = np.zeros(g.n + 1, dtype=np.int64)
+    np.cumsum(deg, out=rp[1:])
+    src = np.repeat(g.row_ptr[:-1][order], deg) + (np.arange(g.nnz) - np.repeat(rp[:-1], deg))
+    col = internal[g.col[src]].astype(np.int32)
+    return graphs.Csr(n=g.n, row_ptr=rp, col=col, name=g.name + "-storage"), order, internal
+
+
+@pytest.fixture(scope="module", params=["ba1k", "cl100k"])
+def pair(request):
+    g = graphs.workload_graph(request.param)
+    g5, order, internal = relabelled(g)
+    dg = B.graph_load_csr(g.n, g.row_ptr, g.col, FLAGS)
+    assert dg.info()["layout"] == 5
+    yield g, g5, order, internal, dg
+    dg.free()
+
+
+def _plans(L, b, r, n):
+    return [OP.plan(0.1, int(x), 1, 1, 1, OP.Policy("fixed", B_fixed=b, R_fixed=r)) for x in L] if n else []
+
+
+@pytest.mark.parametrize("mode", ["plain", "batched"])
+def test_estimates_equal_oracle_on_relabelled_graph(pair, mode):
+    g, g5, order, internal, dg = pair
+    s, t = queries.uniform_pairs(g.n, 12, 5)
+    L = np.array([0, 1, 5, 50, 200, 1000] * 2, dtype=np.int32)
+    res = B.bd_query_batch(dg, s, t, 0.1, L, SEED, B.policy("fixed", B=2, R=70), B.exec_cfg(mode))
+    assert np.all(res["status"] == 0)
+    ref = E.estimate(g5, internal[s], internal[t], L, _plans(L, 2, 70, 1), SEED, threads=8)
+    assert np.array_equal(res["beta"], ref)
+
+
+def test_split_probes_and_served(pair):
+    g, g5, order, internal, dg = pair
+    s, t = queries.uniform_pairs(g.n, 5, 17)
+    pol = B.policy("fixed", B=1, R=5000)  # R above the split size
+    res = B.bd_query_batch(dg, s, t, 0.1, 20, SEED, pol, B.exec_cfg("batched"))
+    ref = E.estimate(g5, internal[s], internal[t], 20, _plans([20] * 5, 1, 5000, 1), SEED, threads=8)
+    assert np.array_equal(res["beta"], ref)
+    srv = B.Server(dg, pol)
+    o, _ = srv.wait(srv.submit(s, t, 0.1, 20, SEED))
+    srv.destroy()
+    assert np.array_equal(o["beta"], ref)
+
+
+def test_probe_q_and_block_means(pair):
+    g, g5, order, internal, dg = pair
+    s, t = queries.uniform_pairs(g.n, 1, 23)
+    pol = B.policy("fixed", B=3, R=97)
+    r, q, y = B.bd_query_probes(dg, int(s[0]), int(t[0]), 0.1, 77, 4, SEED, pol, B.exec_cfg("batched"))
+    plan = OP.plan(0.1, 77, 1, 1, 1, OP.Policy("fixed", B_fixed=3, R_fixed=97))
+    rb, rq, ry = E.estimate(g5, [internal[s[0]]], [internal[t[0]]], 77, [plan], SEED, uid=[4], want_q=True)
+    assert np.array_equal(q, rq) and np.array_equal(y, ry) and r["beta"] == rb[0]
+
+
+def test_walks_same_as_other_layouts_and_sums_match_oracle(pair):
+    g, g5, order, internal, dg = pair
+    starts = queries.uniform_pairs(g.n, 16, 3)[0]
+    n = starts.size
+    uid, k, p = np.arange(n) % 7, np.arange(n) % 5, np.arange(n) % 3
+    side = np.arange(n) % 2
+    tr, acc = B.bd_walk_trace(dg, starts, uid, k, p, side, 300, SEED)
+    other = B.graph_load_csr(g.n, g.row_ptr, g.col, B.BD_LAYOUT_COMPACT | B.BD_RELABEL_DEGREE)
+    tr3, _ = B.bd_walk_trace(other, starts, uid, k, p, side, 300, SEED)
+    other.free()
+    assert np.array_equal(tr, tr3)  # the same walks in caller ids
+    for i in range(n):
+        otr, oacc = E.walk_trace(g5, int(internal[starts[i]]), 300, SEED, int(uid[i]), int(k[i]), int(p[i]),
+                                 int(side[i]))
+        assert np.array_equal(order[otr], tr[i])
+        assert np.float32(acc[i]) == np.float32(oacc)
+
+
+@pytest.mark.parametrize("M", [2, 4])
+def test_walk_sharing(pair, M):
+    g, g5, order, internal, dg = pair
+    s, t = queries.uniform_pairs(g.n, 6, 29)
+    L = np.array([3, 40, 200] * 2, dtype=np.int32)
+    pol = B.policy("fixed", B=5, R=90, share=M)
+    res = B.bd_query_batch(dg, s, t, 0.1, L, SEED, pol, B.exec_cfg("batched"))
+    ref = E.estimate(g5, internal[s], internal[t], L, _plans(L, 5, 90, 1), SEED, threads=8, share=M)
+    assert np.array_equal(res["beta"], ref)
