@@ -40,7 +40,8 @@ L2_PEAK_REQ_PER_S = 8 * 16 * 2.4e9   # one request per L2 channel per clock, 16 
 COUNTERS = os.path.join(ROOT, "profiles", "walk_kernel_cl100k_counters.txt")
 FAT_SCALE_COUNTERS = os.path.join(ROOT, "profiles", "walk_kernel_fat_cl40m_counters.txt")
 KERNEL_SOURCES = ["pw_kernels.hip", "pw_device.hpp", "pw_internal.hpp"]
-LAYOUT_NAMES = {0: "csr", 1: "fat", 2: "compact", 3: "compact, hubs first", 4: "hubs first, 4-byte ids"}
+LAYOUT_NAMES = {0: "csr", 1: "fat", 2: "compact", 3: "compact, hubs first", 4: "hubs first, 4-byte ids",
+                5: "hubs first, probe on storage ids"}
 
 
 def log(*a):
@@ -107,17 +108,50 @@ def l2_requests(kernel_sps):
                      "request per L2 channel per clock: 8 XCDs x 16 channels x 2.4 GHz")}
 
 
+def host_cpus():
+    """The host's CPUs as this process sees them: the model name and socket
+    layout (lscpu, else /proc/cpuinfo), the logical CPUs of the machine and of
+    this process's affinity mask, and how many threads the oracle may use --
+    all of the affinity mask, capped by OMP_NUM_THREADS when the machine sets
+    one (the CPU share a job on a shared GPU machine is given)."""
+    info = {"model": "", "logical_cpus": os.cpu_count() or 1}
+    try:
+        info["affinity_cpus"] = len(os.sched_getaffinity(0))
+    except AttributeError:
+        info["affinity_cpus"] = info["logical_cpus"]
+    try:
+        import subprocess
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        kv = {ln.split(":", 1)[0].strip(): ln.split(":", 1)[1].strip() for ln in out.splitlines() if ":" in ln}
+        info["model"] = kv.get("Model name", "")
+        for k in ("Socket(s)", "Core(s) per socket", "Thread(s) per core", "CPU max MHz"):
+            if k in kv:
+                info[k] = kv[k]
+    except (OSError, ValueError, IndexError):
+        pass
+    if not info["model"]:
+        try:
+            with open("/proc/cpuinfo") as fh:
+                info["model"] = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), "")
+        except OSError:
+            pass
+    usable = info["affinity_cpus"]
+    share = os.environ.get("OMP_NUM_THREADS", "")
+    if share.isdigit() and int(share) > 0:
+        usable = min(usable, int(share))
+        info["cpu_share"] = f"OMP_NUM_THREADS={share}"
+    info["usable"] = usable
+    return info
+
+
 def cpu_baseline(g, s, t, plans, seed, target_s=20.0):
     """The oracle on a bounded sample: each of `threads` queries runs its first
     few probes at the full R and L; queries/s is the measured step rate divided
     by the mean full-query step count."""
     from oracle import estimator as E
 
-    try:
-        cores = len(os.sched_getaffinity(0))
-    except AttributeError:
-        cores = os.cpu_count() or 1
-    threads = max(1, min(16, cores, len(plans)))
+    host = host_cpus()
+    threads = max(1, min(host["usable"], len(plans)))
     sub = [plans[i] for i in range(threads)]
     per_probe = np.array([2.0 * p[3] * L for p in sub])
     kend = np.maximum(1, np.minimum([p[2] for p in sub], (1.5e7 * target_s / per_probe).astype(np.int64)))
@@ -127,14 +161,9 @@ def cpu_baseline(g, s, t, plans, seed, target_s=20.0):
     steps = float((kend * per_probe).sum())
     full = np.array([2.0 * p[2] * p[3] * L for p in plans])
     sps = steps / dt
-    model = ""
-    try:
-        with open("/proc/cpuinfo") as fh:
-            model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), "")
-    except OSError:
-        pass
     return {"value": sps / full.mean(), "unit": "queries/s", "cores": threads, "kind": "oracle",
-            "cpu_model": model, "walk_steps_per_s": sps, "walk_steps_per_s_per_core": sps / threads,
+            "cpu_model": host["model"], "host": host,
+            "walk_steps_per_s": sps, "walk_steps_per_s_per_core": sps / threads,
             "single_thread_seconds_per_query": full.mean() / (sps / threads),
             "sample": (f"{threads} of the step's queries, first {int(kend.min())}-{int(kend.max())} of their "
                        f"probes each at full R and L, one query per thread; {steps:.3e} walk steps in "
@@ -240,8 +269,11 @@ def grid_batched(B, torch, stream, plain_sample=512):
         "graph_walk_steps_per_s": steps / dt_graph,
         "kernel_ms": st["walk_kernel_ms"],
         "kernel_walk_steps_per_s": steps / (st["walk_kernel_ms"] / 1e3),
-        "gather_roofline_steps_per_s": roof["steps_per_s"],
-        "gather_roofline_frac": steps / (st["walk_kernel_ms"] / 1e3) / roof["steps_per_s"],
+        "random_start_gather_steps_per_s": roof["steps_per_s"],
+        "vs_random_start_gather": steps / (st["walk_kernel_ms"] / 1e3) / roof["steps_per_s"],
+        "random_start_gather_note": ("the same loads from random start nodes; the walks' locality (all replicas "
+                                     "of a chunk start at the same two nodes) runs above it, so this ratio is "
+                                     "not a roofline fraction"),
         "plain_sample": m,
         "plain_qps": m / dt_plain,
         "plain_walk_steps_per_s": steps_m / dt_plain,
@@ -250,7 +282,7 @@ def grid_batched(B, torch, stream, plain_sample=512):
     }
 
 
-def served_cl10m(B, torch, seconds_per_load=20.0):
+def served_cl10m(B, torch, seconds_per_load=10.0, calibrated_queries=8):
     """Continuous batching under Poisson arrivals: Chung-Lu n=10^7 (mean degree
     10, exponent 2.3, largest component, resident on the device in the layout
     the library picks: fat at this size); request batches of 2^U uniform pairs (U uniform
@@ -355,6 +387,8 @@ def served_cl10m(B, torch, seconds_per_load=20.0):
     dt_p = time.perf_counter() - t0
     steps5 = B.bd_plan(dg, s5, t5, 0.05, Lq, pol)["walk_steps"].astype(float)
     out["modes_eps005_L1000"] = {
+        "walk_counts": ("throughput setting, not calibrated: about 1/150 of the walk steps that meet eps "
+                        "(see modes_eps005_L1000_calibrated)"),
         "queries": 4096, "walk_steps_per_query_mean": float(steps5.mean()),
         "plain_queries_per_s": 256 / dt_p, "batched_queries_per_s": 4096 / dt_b,
         "served_queries_per_s": 4096 / dt_s,
@@ -362,8 +396,142 @@ def served_cl10m(B, torch, seconds_per_load=20.0):
         "plain_walk_steps_per_s": float(steps5[:256].sum()) / dt_p,
         "batched_walk_steps_per_s": float(steps5.sum()) / dt_b}
     srv.destroy()
+    out["modes_eps005_L1000_calibrated"] = calibrated_modes(B, torch, dg, s5[:calibrated_queries],
+                                                            t5[:calibrated_queries], seed)
     dg.free()
     return out
+
+
+def calibrated_modes(B, torch, dg, s, t, seed):
+    """Plain (one query per launch), batched and served on the same queries at
+    the walk counts calibrated for this graph at eps = 0.05, L = 1000."""
+    from paper_2512_05460_amd.budgets import BUDGETS, budget_policy
+
+    pol = budget_policy("cl10m@1000")
+    nq = s.size
+    plan = B.bd_plan(dg, s, t, 0.05, 1000, pol)
+    steps = plan["walk_steps"].astype(float)
+    log(f"served: calibrated walk counts, {nq} queries, {steps.sum():.3e} walk steps per mode")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ref = [B.bd_query_batch(dg, s[i:i + 1], t[i:i + 1], 0.05, 1000, seed, pol, B.exec_cfg("plain"), uid=[i])
+           for i in range(nq)]
+    torch.cuda.synchronize()
+    dt_p = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    rb = B.bd_query_batch(dg, s, t, 0.05, 1000, seed, pol, B.exec_cfg("batched"))
+    torch.cuda.synchronize()
+    dt_b = time.perf_counter() - t0
+    srv = B.Server(dg, pol)
+    t0 = time.perf_counter()
+    rids = [srv.submit(s[j:j + 4], t[j:j + 4], 0.05, 1000, seed, uid=np.arange(j, j + 4)) for j in range(0, nq, 4)]
+    outs = [srv.wait(r)[0] for r in rids]
+    dt_s = time.perf_counter() - t0
+    srv.destroy()
+    beta_p = np.array([r["beta"][0] for r in ref])
+    assert np.array_equal(beta_p, rb["beta"]) and np.array_equal(np.concatenate([o["beta"] for o in outs]), rb["beta"])
+    c_B, c_R, how = BUDGETS["cl10m@1000"]
+    return {
+        "walk_counts": "calibrated against binary64 CG distances (tests/golden): eps-accurate",
+        "policy": {"kind": "scaled", "c_B": c_B, "c_R": c_R, "calibration": how},
+        "queries": nq, "B": int(plan["B"][0]), "K": int(plan["K"][0]),
+        "R": {"median": float(np.median(plan["R"])), "max": int(plan["R"].max())},
+        "walk_steps_per_query": {"mean": float(steps.mean()), "median": float(np.median(steps)),
+                                 "max": float(steps.max())},
+        "plain_queries_per_s": nq / dt_p, "batched_queries_per_s": nq / dt_b, "served_queries_per_s": nq / dt_s,
+        "batched_vs_plain": dt_p / dt_b, "served_vs_plain": dt_p / dt_s,
+        "plain_walk_steps_per_s": steps.sum() / dt_p, "batched_walk_steps_per_s": steps.sum() / dt_b,
+        "note": ("each query carries ~1e6-1e7 walk pairs against ~5e5 lane slots, so one query already fills "
+                 "the device and batching adds little; the >= 5x regime is queries too small to fill it")}
+
+
+def scale_cl40m_default(B, torch, stream, pairs=32, thr_queries=65536):
+    """The scale graph in the default run: Chung-Lu n=4*10^7 (mean degree 25,
+    exponent 2.2, largest component, about 10^9 adjacency entries) in the
+    layout the library picks (fat). (1) The first `pairs` of its 64 CG
+    reference pairs at eps = 0.05, L = 1000 and the calibrated walk counts:
+    fraction within eps of the exact distance and the rate; the L = 10000 half
+    of the workload is priced from the planner at the measured rate. (2) The
+    first `thr_queries` of its 262,144 queries (L over {1000, 10000}) at the
+    throughput setting, in one persistent launch: walk steps/s and the HBM
+    bytes per step from the committed counters."""
+    from paper_2512_05460_amd.budgets import BUDGETS, budget_policy
+    from paper_2512_05460_amd.calibrate import load_reference
+    from synth import graphs, queries
+
+    log("scale: building Chung-Lu n=4e7")
+    t0 = time.perf_counter()
+    g = graphs.workload_graph("cl40m")
+    t_gen = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    dg = B.graph_load_csr(g.n, g.row_ptr, g.col, B.BD_LAYOUT_AUTO | B.BD_SKIP_VALIDATION)
+    t_load = time.perf_counter() - t0
+    info = dg.info()
+    seed = graphs.PHILOX_SEED
+    ref = load_reference(os.path.join(ROOT, "tests", "golden", "cl40m_cg_reference.txt"))
+    s = ref["s"][:pairs].astype(np.int32)
+    t = ref["t"][:pairs].astype(np.int32)
+    pol = budget_policy("cl40m@1000")
+    log(f"scale: {pairs} reference pairs at calibrated walk counts, L=1000")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r, st = B.bd_query_batch(dg, s, t, 0.05, 1000, seed, pol, B.exec_cfg("batched"), stream=stream,
+                             uid=ref["index"][:pairs].astype(np.uint32), with_stats=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    assert np.all(r["status"] == 0)
+    err = np.abs(r["beta"] - ref["beta_cg"][:pairs]) / ref["beta_cg"][:pairs]
+    steps = r["walk_steps"].astype(float)
+    sps = steps.sum() / dt
+    # the L = 10000 half priced at the same policy shape: the calibrated c_R scaled
+    # by the growth of the walk variance (about L) over Algorithm 1's (L+1)^2
+    c_B, c_R, how = BUDGETS["cl40m@1000"]
+    pol10 = B.policy("scaled", c_B=c_B, c_R=c_R * 10.0 * (1001.0 / 10001.0) ** 2)
+    p10 = B.bd_plan(dg, s, t, 0.05, 10000, pol10)["walk_steps"].astype(float)
+    calibrated = {
+        "walk_counts": "calibrated against binary64 CG distances (tests/golden): eps-accurate",
+        "policy": {"kind": "scaled", "c_B": c_B, "c_R": c_R, "calibration": how},
+        "pairs": pairs, "L": 1000, "within_eps": float((err <= 0.05).mean()),
+        "median_rel_err": float(np.median(err)),
+        "R": {"median": float(np.median(r["R"])), "max": int(r["R"].max())},
+        "walk_steps_per_query": {"mean": float(steps.mean()), "max": float(steps.max())},
+        "queries_per_s": pairs / dt, "walk_steps_per_s": sps,
+        "kernel_walk_steps_per_s": steps.sum() / (st["walk_kernel_ms"] / 1e3),
+        "L10000_projection": {"walk_steps_per_query_mean": float(p10.mean()),
+                              "seconds_per_query_at_measured_rate": float(p10.mean() / sps),
+                              "note": ("planner only: the walk variance grows about like L after mixing, so "
+                                       "R at L=10000 is ~10x and walk steps ~100x those at L=1000")}}
+    s2, t2, eps2, L2 = queries.workload_batch("cl40m", g.n, thr_queries)
+    tpol = budget_policy("cl40m")
+    tplan = B.bd_plan(dg, s2, t2, eps2, L2, tpol)
+    tsteps = float(tplan["walk_steps"].sum())
+    log(f"scale: {thr_queries} queries at the throughput setting, {tsteps:.3e} walk steps")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r2, st2 = B.bd_query_batch(dg, s2, t2, eps2, L2, seed, tpol, B.exec_cfg("batched"), stream=stream,
+                               with_stats=True)
+    torch.cuda.synchronize()
+    dt2 = time.perf_counter() - t0
+    assert np.all(r2["status"] == 0)
+    ksps = tsteps / (st2["walk_kernel_ms"] / 1e3)
+    thr = {"walk_counts": "throughput setting, not calibrated: " + BUDGETS["cl40m"][2],
+           "queries": thr_queries, "walk_steps": tsteps, "queries_per_s": thr_queries / dt2,
+           "walk_steps_per_s": tsteps / dt2, "kernel_walk_steps_per_s": ksps}
+    kv, why = read_counters(FAT_SCALE_COUNTERS)
+    if info["layout"] == 1 and kv is not None:
+        bps = float(kv["hbm_read_bytes_per_step"])
+        thr["hbm_roofline"] = {"bound": "hbm", "bytes_per_step": bps, "achieved": bps * ksps / 1e9,
+                               "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": bps * ksps / 1e9 / HBM_PEAK_GBS,
+                               "algorithmic_bytes_per_step": BYTES_PER_STEP,
+                               "algorithmic_frac": BYTES_PER_STEP * ksps / 1e9 / HBM_PEAK_GBS}
+    else:
+        thr["hbm_roofline"] = {"note": why if kv is None else "not the fat layout"}
+    dg.free()
+    return {"workload": ("Chung-Lu n=40,000,000 mean degree 25 exponent 2.2 LCC; eps=0.05; 64 CG reference "
+                         "pairs; 262,144 uniform pairs with L over {1000, 10000}"),
+            "graph": {"n": g.n, "nnz": g.nnz, "generate_s": t_gen, "load_s": t_load,
+                      "layout": LAYOUT_NAMES[info["layout"]], "device_bytes": info["device_bytes"]},
+            "calibrated_L1000": calibrated, "throughput_setting": thr}
 
 
 def scale_cl40m(B, torch, stream, served_queries=65536, which=("csr", "hubs", "auto")):
@@ -417,8 +585,8 @@ def scale_cl40m(B, torch, stream, served_queries=65536, which=("csr", "hubs", "a
                          "device_bytes": dg.info()["device_bytes"], "load_s": t_load,
                          "batched_queries_per_s": s.size / dt, "batched_walk_steps_per_s": steps / dt,
                          "kernel_walk_steps_per_s": steps / (st["walk_kernel_ms"] / 1e3),
-                         "gather_roofline_steps_per_s": roof["steps_per_s"],
-                         "gather_roofline_frac": steps / (st["walk_kernel_ms"] / 1e3) / roof["steps_per_s"]}
+                         "random_start_gather_steps_per_s": roof["steps_per_s"],
+                         "vs_random_start_gather": steps / (st["walk_kernel_ms"] / 1e3) / roof["steps_per_s"]}
     m = served_queries
     dg_layout = dg.info()["layout"]
     srv = B.Server(dg, pol)
@@ -471,9 +639,10 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--queries", type=int, default=32, help="queries per step")
-    ap.add_argument("--layout", choices=["hubs", "compact", "csr", "fat", "auto"], default="hubs",
+    ap.add_argument("--layout", choices=["hubs", "hubsid", "compact", "csr", "fat", "auto"], default="hubs",
                     help="hubs: compact layout with nodes in descending-degree order and hub entries in LDS; "
-                         "auto: the library's choice (the same at this size)")
+                         "hubsid: the same with the probe on storage ids (4-byte node entries, 16,384 hubs in "
+                         "LDS); auto: the library's choice (hubs at this size)")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--no-roofline", action="store_true")
@@ -486,6 +655,8 @@ def main():
     ap.add_argument("--scale", action="store_true",
                     help="also run the Chung-Lu n=4e7 workload (about 3 minutes more)")
     ap.add_argument("--no-served-cl10m", action="store_true")
+    ap.add_argument("--no-scale-cl40m", action="store_true",
+                    help="leave out the default n=4e7 block (calibrated reference pairs, throughput setting)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calib", type=int, default=0,
                     help="also run a device copy of this many MiB (counter calibration)")
@@ -509,7 +680,9 @@ def main():
     s_all, t_all = queries.uniform_pairs(g.n, 4096, graphs.GRAPH_SEED + 1 + graphs.QUERY_SEED_OFFSET)
     nq = args.queries
     s, t = s_all[:nq], t_all[:nq]
-    flags = {"hubs": B.BD_LAYOUT_COMPACT | B.BD_RELABEL_DEGREE, "compact": B.BD_LAYOUT_COMPACT,
+    flags = {"hubs": B.BD_LAYOUT_COMPACT | B.BD_RELABEL_DEGREE,
+             "hubsid": B.BD_LAYOUT_COMPACT | B.BD_RELABEL_DEGREE | B.BD_PROBE_STORAGE_IDS,
+             "compact": B.BD_LAYOUT_COMPACT,
              "csr": B.BD_LAYOUT_CSR | B.BD_RELABEL_DEGREE,
              "fat": B.BD_LAYOUT_FAT | B.BD_RELABEL_DEGREE, "auto": B.BD_LAYOUT_AUTO}[args.layout]
     dg = B.graph_load_csr(g.n, g.row_ptr, g.col, flags)
@@ -518,8 +691,13 @@ def main():
     plan = B.bd_plan(dg, s, t, EPS, L, pol)
     assert np.all(plan["status"] == 0), plan["status"]
     steps_per_batch = float(plan["walk_steps"].sum())
+    # the timed batch is the first nq of the 4,096 pairs; its walk work against
+    # the whole set's (host planner only), since per-query budgets are heavy-tailed
+    plan_set = B.bd_plan(dg, s_all, t_all, EPS, L, pol)
+    set_steps = plan_set["walk_steps"].astype(np.float64)
     log(f"batch: {nq} queries, K={int(plan['K'][0])}, R median {int(np.median(plan['R']))} "
-        f"max {int(plan['R'].max())}, {steps_per_batch:.3e} walk steps")
+        f"max {int(plan['R'].max())}, {steps_per_batch:.3e} walk steps "
+        f"({steps_per_batch / nq / set_steps.mean():.2f}x the set's mean per query)")
     plain = B.exec_cfg("plain")
     stream = torch.cuda.current_stream()
 
@@ -625,6 +803,8 @@ def main():
         extra["grid_batched"] = grid_batched(B, torch, stream)
     if not args.no_served_cl10m:
         extra["served_cl10m"] = served_cl10m(B, torch)
+    if not args.no_scale_cl40m and not args.scale:
+        extra["scale_cl40m"] = scale_cl40m_default(B, torch, stream)
     if args.scale:
         which = args.scale_layouts.split(",")
         if not which or not set(which) <= {"csr", "hubs", "auto"}:
@@ -678,6 +858,13 @@ def main():
             "policy": {"kind": "scaled", "c_B": c_B, "c_R": c_R, "delta": 0.01, "calibration": how},
             "K": int(plan["K"][0]), "R_median": int(np.median(plan["R"])),
             "walk_steps_per_step": steps_per_batch,
+            "sample": (f"the first {nq} of 4,096 uniform pairs, the same batch every step; latency "
+                       "percentiles are over these queries"),
+            "sample_walk_steps_per_query": steps_per_batch / nq,
+            "set_walk_steps_per_query": {"mean": float(set_steps.mean()), "median": float(np.median(set_steps)),
+                                         "max": float(set_steps.max())},
+            "sample_vs_set_walk_steps": steps_per_batch / nq / float(set_steps.mean()),
+            "set_queries_per_s_at_measured_rate": walk_sps / float(set_steps.mean()),
         },
         "walk_steps_per_s": walk_sps,
         "latency_ms": {"p50": float(np.percentile(lat_all, 50)), "p99": float(np.percentile(lat_all, 99))},
