@@ -3,13 +3,16 @@
 Workload: Chung-Lu graph n=100,000, mean degree 10, exponent 2.5, largest
 connected component (99,163 nodes, 997,038 adjacency entries); uniform (s,t)
 pairs; eps = 0.05, L = 1000; walk counts from the scaled policy of Algorithm 1
-(constants in paper_2512_05460_amd/budgets.py). One step = one batch of
+(constants in paper_2512_05460_amd/budgets.py); tables in the compact
+hubs-first layout with the probe on storage ids. One step = one batch of
 queries run in the plain mode (one query per launch, fixed tiling). The same
 batch is also run in the batched (persistent, work-stealing) mode, through
 the server (continuous batching) and with walk sharing, reported beside the
-headline; so are the small-query, grid (mixed eps and L, hipGraph) and served
-Chung-Lu n=10^7 (Poisson arrivals) workloads, and with --scale the Chung-Lu
-n=4*10^7 one.
+headline; so are the small-query, grid (mixed eps and L, hipGraph), served
+Chung-Lu n=10^7 (Poisson arrivals; plain, batched and served at calibrated
+walk counts) and Chung-Lu n=4*10^7 (calibrated reference pairs and a
+throughput-setting launch) workloads; --scale adds the full n=4*10^7 report
+over three layouts.
 
 Prints one JSON line. The graph is resident on the device before the timed
 region; each query's 48-byte descriptor travels host->device inside the call
@@ -639,7 +642,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--queries", type=int, default=32, help="queries per step")
-    ap.add_argument("--layout", choices=["hubs", "hubsid", "compact", "csr", "fat", "auto"], default="hubs",
+    ap.add_argument("--layout", choices=["hubs", "hubsid", "compact", "csr", "fat", "auto"], default="hubsid",
                     help="hubs: compact layout with nodes in descending-degree order and hub entries in LDS; "
                          "hubsid: the same with the probe on storage ids (4-byte node entries, 16,384 hubs in "
                          "LDS); auto: the library's choice (hubs at this size)")

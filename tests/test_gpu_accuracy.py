@@ -55,14 +55,18 @@ def test_accuracy_ba1k():
 
 
 @pytest.mark.timeout(900)
-def test_accuracy_cl100k():
+@pytest.mark.parametrize("flags", [B.BD_LAYOUT_COMPACT,
+                                   B.BD_LAYOUT_COMPACT | B.BD_RELABEL_DEGREE | B.BD_PROBE_STORAGE_IDS])
+def test_accuracy_cl100k(flags):
+    # the probe on caller ids, and on storage ids (the headline's layout): the
+    # same walks scored by differently labelled probes, both within eps
     g = graphs.workload_graph("cl100k")
     ref = np.loadtxt(GOLDEN, comments="#")
     s = ref[:, 1].astype(np.int32)
     t = ref[:, 2].astype(np.int32)
     beta = ref[:, 5]
     assert np.all(np.abs(ref[:, 6] - beta) <= 1e-10 * beta)  # the two CG solves agree
-    dg = B.graph_load_csr(g.n, g.row_ptr, g.col, B.BD_LAYOUT_COMPACT)
+    dg = B.graph_load_csr(g.n, g.row_ptr, g.col, flags)
     res, st = B.bd_query_batch(dg, s, t, 0.05, 1000, SEED, budget_policy("cl100k"),
                                B.exec_cfg("batched"), with_stats=True)
     assert np.all(res["status"] == 0)
