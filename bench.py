@@ -537,7 +537,7 @@ def scale_cl40m_default(B, torch, stream, pairs=32, thr_queries=65536):
             "calibrated_L1000": calibrated, "throughput_setting": thr}
 
 
-def scale_cl40m(B, torch, stream, served_queries=65536, which=("csr", "hubs", "auto")):
+def scale_cl40m(B, torch, stream, served_queries=65536, which=("csr", "hubs", "auto"), refs=False):
     """The scale workload: Chung-Lu n=4*10^7 (mean degree 25, exponent 2.2,
     largest component, about 10^9 adjacency entries; native generator); the
     262,144 queries (eps = 0.05, L over {1000, 10000}) in one persistent launch
@@ -605,7 +605,28 @@ def scale_cl40m(B, torch, stream, served_queries=65536, which=("csr", "hubs", "a
     dts = time.perf_counter() - t0
     srv.destroy()
     steps_m = float(plan["walk_steps"][:m].sum())
-    dg.free()
+    # the reference routines at this size: lambda by power iteration (section
+    # 2.1) and beta^(L) by sparse products (Lemma 2.3), on the device
+    ref_routines = None
+    if not refs:
+        dg.free()
+        dg = None
+    else:
+        log("scale: lambda (200 power iterations) and beta^(1000) of 8 pairs")
+        free0 = torch.cuda.mem_get_info()[0]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lam = B.bd_graph_lambda(dg, 200, 7, stream=stream)
+        dt_lam = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        bl = B.bd_truncated_beta(dg, s[:8], t[:8], 1000, stream=stream)
+        dt_bl = time.perf_counter() - t0
+        ref_routines = {
+            "lambda": {"iterations": 200, "estimate": lam, "seconds": dt_lam,
+                       "device_bytes": 4 * 8 * g.n + 2 * 1024 * 8 + 16},
+            "beta_truncated": {"pairs": 8, "L": 1000, "seconds": dt_bl, "beta": [float(x) for x in bl],
+                               "device_bytes_per_pass": 3 * 8 * g.n * 8, "free_device_bytes_before": int(free0)}}
+        dg.free()
     c_B, c_R, how = BUDGETS["cl40m"]
     best = max(layouts.values(), key=lambda x: x["batched_queries_per_s"])
     # the fat layout's HBM roofline: bytes per step from the committed counters
@@ -633,6 +654,7 @@ def scale_cl40m(B, torch, stream, served_queries=65536, which=("csr", "hubs", "a
         "batched_walk_steps_per_s": best["batched_walk_steps_per_s"],
         "served_queries": m, "served_queries_per_s": m / dts, "served_walk_steps_per_s": steps_m / dts,
         "served_request_latency_ms": {"p50": float(np.percentile(lat, 50)), "max": float(max(lat))},
+        "reference_routines": ref_routines,
     }
 
 
@@ -657,6 +679,8 @@ def main():
                     help="layouts of the scale report, from csr, hubs, auto")
     ap.add_argument("--scale", action="store_true",
                     help="also run the Chung-Lu n=4e7 workload (about 3 minutes more)")
+    ap.add_argument("--scale-refs", action="store_true",
+                    help="with --scale: time lambda and beta^(1000) of 8 pairs at n=4e7")
     ap.add_argument("--no-served-cl10m", action="store_true")
     ap.add_argument("--no-scale-cl40m", action="store_true",
                     help="leave out the default n=4e7 block (calibrated reference pairs, throughput setting)")
@@ -812,7 +836,7 @@ def main():
         which = args.scale_layouts.split(",")
         if not which or not set(which) <= {"csr", "hubs", "auto"}:
             raise SystemExit(f"--scale-layouts takes csr, hubs, auto; got {args.scale_layouts}")
-        extra["scale_cl40m"] = scale_cl40m(B, torch, stream, which=which)
+        extra["scale_cl40m"] = scale_cl40m(B, torch, stream, which=which, refs=args.scale_refs)
     roof = None
     if not args.no_roofline:
         log("gather roofline")

@@ -429,14 +429,18 @@ typedef struct {
     int32_t   chunk_probes;           /* 0 = automatic */
     double    slice_ms;               /* least device time per scheduling slice (0 = 20); a slice
                                          also lasts at least four times its longest chunk */
+    double    small_first;            /* share of each slice's work given first to the requests
+                                         with the fewest walk steps left, smallest first (the rest
+                                         is round-robin over requests): 0 = 0.5, < 0 = none */
 } bd_server_cfg;
 
 /*
  * Create a server over a loaded graph. The server owns a host scheduler thread
  * and device streams; requests submitted while others run are admitted at
  * the next slice boundary as capacity frees up, and their chunks share the
- * device with the running ones (round-robin over requests, replica parts of
- * at most 1024 pairs). The graph must outlive the server.
+ * device with the running ones (part of each slice to the requests with the
+ * least work left, the rest round-robin over requests; replica parts of at
+ * most 1024 pairs). The graph must outlive the server.
  */
 int  bd_server_create(bd_graph* g, const bd_server_cfg* cfg, bd_server** out);
 /* Submit nq queries (host arrays, copied). Returns a request id. BD_E_FULL if

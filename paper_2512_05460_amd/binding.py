@@ -116,7 +116,7 @@ class BdRoofline(ctypes.Structure):
 class BdServerCfg(ctypes.Structure):
     _fields_ = [("policy", BdPolicy), ("max_queries_inflight", ctypes.c_int64),
                 ("max_steps_inflight", ctypes.c_uint64), ("chunk_probes", ctypes.c_int32),
-                ("slice_ms", ctypes.c_double)]
+                ("slice_ms", ctypes.c_double), ("small_first", ctypes.c_double)]
 
 
 _ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -425,9 +425,9 @@ class Server:
     """Owning wrapper of a ``bd_server*`` (served mode, continuous batching)."""
 
     def __init__(self, g: Graph, pol: BdPolicy, max_queries: int = 0, max_steps: int = 0,
-                 chunk_probes: int = 0, slice_ms: float = 0.0):
+                 chunk_probes: int = 0, slice_ms: float = 0.0, small_first: float = 0.0):
         self.graph = g  # the graph must outlive the server
-        cfg = BdServerCfg(pol, max_queries, max_steps, chunk_probes, slice_ms)
+        cfg = BdServerCfg(pol, max_queries, max_steps, chunk_probes, slice_ms, small_first)
         h = _P()
         _check(lib().bd_server_create(g.handle, ctypes.byref(cfg), ctypes.byref(h)), "bd_server_create")
         self._h = h

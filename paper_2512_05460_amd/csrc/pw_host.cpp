@@ -1657,6 +1657,7 @@ struct Request {
     std::vector<uint32_t> slots;    // slots taken at admission
     bool admitted = false;
     bool cancelled = false;         // bd_server_cancel: no further chunk is handed out
+    uint64_t left_steps = 0;        // walk steps not yet handed out (slice ordering)
     uint64_t cancel_mark = 0;       // slices launched when it was cancelled
 };
 
@@ -1832,6 +1833,7 @@ int admit(bd_server* S)
         if (!fits) break;
         S->pending.pop_front();
         r.admitted = true;
+        r.left_steps = r.steps;
         if (need > 0 && !r.in_rr) {
             S->rr.push_back(id);
             r.in_rr = true;
@@ -1967,6 +1969,8 @@ int reclaim_cancelled(bd_server* S)
 void fill_slice(bd_server* S, Slice& sl)
 {
     const double slice_ms = S->cfg.slice_ms > 0 ? S->cfg.slice_ms : 20.0;
+    const double small_share = S->cfg.small_first < 0 ? 0.0 : S->cfg.small_first > 0 ? std::min(S->cfg.small_first, 1.0)
+                                                                                    : 0.5;
     Chunk* out = sl.chunks_h.as<Chunk>();
     sl.n = 0;
     sl.steps = 0;
@@ -1978,21 +1982,18 @@ void fill_slice(bd_server* S, Slice& sl)
         Chunk c;
     };
     std::vector<Item> big, small;  // wave-uniform chunks, then the rest
-    while (!S->rr.empty() && big.size() + small.size() < kSliceMaxChunks &&
-           ((double)sl.steps < target || big.size() + small.size() < (size_t)S->resident[1])) {
-        const uint64_t id = S->rr.front();
-        S->rr.pop_front();
-        Request& r = S->reqs[id];
-        if (r.cancelled) {
-            r.in_rr = false;
-            continue;
-        }
+    const uint64_t wg = (uint64_t)block_threads(S->g->kernel_layout, share_class(policy_share(S->pol)));
+    auto room = [&] { return big.size() + small.size() < kSliceMaxChunks; };
+    // one chunk of request r (its next query in turn); false when it has none left
+    auto take = [&](Request& r) {
+        if (r.rr_slots.empty()) return false;
         const uint32_t q = r.rr_slots.front();
         r.rr_slots.pop_front();
         SlotState& ss = S->slot[q];
-        sl.steps += ss.cur.chunk_steps(ss.L);
+        const uint64_t cs = ss.cur.chunk_steps(ss.L);
+        sl.steps += cs;
+        r.left_steps -= std::min(r.left_steps, cs);
         const Chunk c = ss.cur.next();
-        const uint64_t wg = (uint64_t)block_threads(S->g->kernel_layout, share_class(policy_share(S->pol)));
         const double cost = ((double)ss.L + 1.0) * (double)(((uint64_t)c.gc * c.pc + wg - 1) / wg);
         sl.sum_cost += cost;
         if (cost > sl.max_cost) {
@@ -2001,6 +2002,38 @@ void fill_slice(bd_server* S, Slice& sl)
         }
         (ss.uniform ? big : small).push_back(Item{cost, c});
         if (!ss.cur.done()) r.rr_slots.push_back(q);
+        return true;
+    };
+    // First the requests with the least work left, smallest first, up to
+    // small_share of the slice: a short request that arrives under load
+    // finishes in the next slice or two instead of waiting its turn behind
+    // long ones; the rest of the slice is round-robin, so none starves.
+    if (small_share > 0.0 && S->rr.size() > 1) {
+        std::vector<uint64_t> order(S->rr.begin(), S->rr.end());
+        std::stable_sort(order.begin(), order.end(),
+                         [&](uint64_t a, uint64_t b) { return S->reqs[a].left_steps < S->reqs[b].left_steps; });
+        for (uint64_t id : order) {
+            Request& r = S->reqs[id];
+            if (r.cancelled) continue;
+            while ((double)sl.steps < small_share * target && room() && take(r)) {
+            }
+            if (r.rr_slots.empty()) {
+                S->rr.erase(std::find(S->rr.begin(), S->rr.end(), id));
+                r.in_rr = false;
+            }
+            if ((double)sl.steps >= small_share * target || !room()) break;
+        }
+    }
+    while (!S->rr.empty() && room() &&
+           ((double)sl.steps < target || big.size() + small.size() < (size_t)S->resident[1])) {
+        const uint64_t id = S->rr.front();
+        S->rr.pop_front();
+        Request& r = S->reqs[id];
+        if (r.cancelled) {
+            r.in_rr = false;
+            continue;
+        }
+        take(r);
         if (!r.rr_slots.empty()) S->rr.push_back(id);
         else r.in_rr = false;
     }
