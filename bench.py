@@ -564,6 +564,7 @@ def scale_cl40m(B, torch, stream, served_queries=65536, which=("csr", "hubs", "a
     # part; the first load validates the graph, the others reuse its arrays
     cand = [("csr", "csr, hubs first", B.BD_LAYOUT_CSR | B.BD_RELABEL_DEGREE),
             ("hubs", "compact, hubs first", B.BD_LAYOUT_COMPACT | B.BD_RELABEL_DEGREE),
+            ("fatt", "fat, ordinary loads", B.BD_LAYOUT_FAT | B.BD_TEMPORAL),
             ("auto", "automatic", B.BD_LAYOUT_AUTO)]
     for key, name, flags in [c for c in cand if c[0] in which]:
         if dg is not None:
@@ -584,7 +585,7 @@ def scale_cl40m(B, torch, stream, served_queries=65536, which=("csr", "hubs", "a
         dt = time.perf_counter() - t0
         assert np.all(r["status"] == 0)
         roof = max((B.bd_gather_roofline(dg, c, 1000) for c in (2, 4, 8)), key=lambda x: x["steps_per_s"])
-        layouts[name] = {"layout": LAYOUT_NAMES[dg.info()["layout"]],
+        layouts[name] = {"layout": LAYOUT_NAMES[dg.info()["layout"]], "nontemporal": dg.info()["nontemporal"],
                          "device_bytes": dg.info()["device_bytes"], "load_s": t_load,
                          "batched_queries_per_s": s.size / dt, "batched_walk_steps_per_s": steps / dt,
                          "kernel_walk_steps_per_s": steps / (st["walk_kernel_ms"] / 1e3),
@@ -676,7 +677,7 @@ def main():
     ap.add_argument("--no-sharing", action="store_true")
     ap.add_argument("--no-stabilize", action="store_true")
     ap.add_argument("--scale-layouts", default="csr,hubs,auto",
-                    help="layouts of the scale report, from csr, hubs, auto")
+                    help="layouts of the scale report, from csr, hubs, fatt (fat with ordinary loads), auto")
     ap.add_argument("--scale", action="store_true",
                     help="also run the Chung-Lu n=4e7 workload (about 3 minutes more)")
     ap.add_argument("--scale-refs", action="store_true",
@@ -834,8 +835,8 @@ def main():
         extra["scale_cl40m"] = scale_cl40m_default(B, torch, stream)
     if args.scale:
         which = args.scale_layouts.split(",")
-        if not which or not set(which) <= {"csr", "hubs", "auto"}:
-            raise SystemExit(f"--scale-layouts takes csr, hubs, auto; got {args.scale_layouts}")
+        if not which or not set(which) <= {"csr", "hubs", "fatt", "auto"}:
+            raise SystemExit(f"--scale-layouts takes csr, hubs, fatt, auto; got {args.scale_layouts}")
         extra["scale_cl40m"] = scale_cl40m(B, torch, stream, which=which, refs=args.scale_refs)
     roof = None
     if not args.no_roofline:
