@@ -665,10 +665,12 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--queries", type=int, default=32, help="queries per step")
-    ap.add_argument("--layout", choices=["hubs", "hubsid", "compact", "csr", "fat", "auto"], default="hubsid",
+    ap.add_argument("--layout", choices=["hubs", "hubsid", "hubsidn", "compact", "csr", "fat", "auto"],
+                    default="hubsid",
                     help="hubs: compact layout with nodes in descending-degree order and hub entries in LDS; "
-                         "hubsid: the same with the probe on storage ids (4-byte node entries, 16,384 hubs in "
-                         "LDS); auto: the library's choice (hubs at this size)")
+                         "hubsid: the same with the probe on storage ids (4-byte node entries; one work group per "
+                         "CU with 36,864 hubs in LDS and two replica pairs per thread); hubsidn: hubsid with two "
+                         "work groups per CU and 16,384 hubs each; auto: the library's choice (hubs at this size)")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--no-roofline", action="store_true")
@@ -710,6 +712,7 @@ def main():
     s, t = s_all[:nq], t_all[:nq]
     flags = {"hubs": B.BD_LAYOUT_COMPACT | B.BD_RELABEL_DEGREE,
              "hubsid": B.BD_LAYOUT_COMPACT | B.BD_RELABEL_DEGREE | B.BD_PROBE_STORAGE_IDS,
+             "hubsidn": B.BD_LAYOUT_COMPACT | B.BD_RELABEL_DEGREE | B.BD_PROBE_STORAGE_IDS | B.BD_NARROW_HUBS,
              "compact": B.BD_LAYOUT_COMPACT,
              "csr": B.BD_LAYOUT_CSR | B.BD_RELABEL_DEGREE,
              "fat": B.BD_LAYOUT_FAT | B.BD_RELABEL_DEGREE, "auto": B.BD_LAYOUT_AUTO}[args.layout]

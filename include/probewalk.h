@@ -101,15 +101,21 @@ typedef struct bd_graph bd_graph;
                                    the same, and a uniformly random probe composed with a
                                    fixed relabelling is again one, but the bits of every
                                    result follow the relabelled ids. Node entries shrink to
-                                   the 4-byte row offset and the 16,384 highest-degree ones
-                                   are staged in LDS (layout code 5). bd_walk_trace still
-                                   reports caller ids */
+                                   the 4-byte row offset and 36,864 (BD_NARROW_HUBS: 16,384)
+                                   of the highest-degree ones are staged in LDS (layout code
+                                   5). bd_walk_trace still reports caller ids */
 #define BD_NONTEMPORAL    256u  /* with BD_LAYOUT_FAT: read the adjacency entries with
                                    non-temporal loads at any size (same results) */
 #define BD_TEMPORAL       512u  /* with BD_LAYOUT_FAT: ordinary loads at any size. Without
                                    either flag the fat layout uses non-temporal loads when
                                    its tables take at least 4 GiB (16x the Infinity Cache:
                                    measured +9.5% at 20.7 GB, -3.5% at 2.2 GB) */
+#define BD_NARROW_HUBS   1024u  /* with BD_PROBE_STORAGE_IDS: two 1,024-thread work groups per
+                                   CU, each staging the 16,384 highest-degree row offsets
+                                   (64 KB), one replica pair per thread. Without it the walks
+                                   of this layout run one 1,024-thread work group per CU that
+                                   stages 36,864 offsets (144 KB of the CU's 160 KB of LDS)
+                                   with two replica pairs per thread. Same results */
 #define BD_DEVICE_PTRS     64u  /* row_ptr and col_idx are device pointers on the current
                                    device (e.g. the data of PyTorch tensors) instead of host
                                    arrays; they are read once, on `stream`, and not kept.
@@ -132,7 +138,8 @@ typedef struct {
                                 the probe on storage ids */
     int64_t  device_bytes;   /* device memory held by the graph tables */
     int32_t  nontemporal;    /* 1 if the fat layout reads its entries with non-temporal loads */
-    int32_t  reserved;
+    int32_t  lds_hubs;       /* node entries staged in LDS per work group of the walk kernels
+                                with one probe per walk (0 = none) */
 } bd_graph_info;
 
 /*

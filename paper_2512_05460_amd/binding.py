@@ -59,6 +59,7 @@ BD_DEVICE_PTRS = 64
 BD_PROBE_STORAGE_IDS = 128
 BD_NONTEMPORAL = 256
 BD_TEMPORAL = 512
+BD_NARROW_HUBS = 1024
 
 BD_POLICY_PAPER = 0
 BD_POLICY_SCALED = 1
@@ -104,7 +105,7 @@ class BdStats(ctypes.Structure):
 class BdGraphInfo(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("d_min", ctypes.c_int32),
                 ("d_max", ctypes.c_int32), ("bipartite", ctypes.c_int32), ("layout", ctypes.c_int32),
-                ("device_bytes", ctypes.c_int64), ("nontemporal", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("device_bytes", ctypes.c_int64), ("nontemporal", ctypes.c_int32), ("lds_hubs", ctypes.c_int32)]
 
 
 class BdRoofline(ctypes.Structure):

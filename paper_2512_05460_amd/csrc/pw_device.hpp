@@ -15,6 +15,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "pw_internal.hpp"
+
 namespace pw {
 
 typedef __int128 i128;
@@ -177,30 +179,7 @@ __device__ __forceinline__ int probe_value(uint32_t x, const Probe& pr, const Do
 // probe is evaluated on the storage id itself (the node's rank in descending
 // degree), so a node entry is its 4-byte row offset alone (rp[x], rp[x + 1]:
 // one 8-byte load) and twice as many hubs fit in the same LDS.
-constexpr int kLayoutCsr = 0, kLayoutFat = 1, kLayoutCompact = 2, kLayoutCompactHub = 3, kLayoutHub32 = 4,
-              kLayoutHubId = 5;
-// The fat layout read with non-temporal loads (the same tables and results):
-// for tables far larger than the Infinity Cache, where every step misses it
-// anyway and keeping the entries out of the caches' replacement order leaves
-// them to the node entries of the walks' start nodes.
-constexpr int kLayoutFatNT = 6;
-constexpr bool hub_layout(int layout)
-{
-    return layout == kLayoutCompactHub || layout == kLayoutHub32 || layout == kLayoutHubId;
-}
-// hub entries staged per work group (64 KB in 1,024-thread groups, 8 KB in
-// 256-thread ones): 8,192 / 1,024 node entries of 8 bytes, or 16,384 / 2,048
-// row offsets of 4 bytes with the probe on storage ids
-constexpr uint32_t hub_nodes(int threads, int layout)
-{
-    return (threads >= 1024 ? 8192u : 1024u) * (layout == kLayoutHubId ? 2u : 1u);
-}
-// 32-bit words of the LDS hub copy (entries 0 .. hub_nodes, inclusive)
-constexpr uint32_t hub_words(int threads, int layout)
-{
-    return !hub_layout(layout) ? 2u : layout == kLayoutHubId ? hub_nodes(threads, layout) + 1u
-                                                            : 2u * (hub_nodes(threads, layout) + 1u);
-}
+// (layout codes and hub counts: pw_internal.hpp)
 
 struct DevGraph {
     const uint4* node;      // n entries (CSR and fat layouts)
@@ -286,7 +265,7 @@ __device__ __forceinline__ WalkState start_at(const DevGraph& G, uint32_t x)
         hub_row(G, x, w);
         return w;
     }
-    if (kLayout == kLayoutHubId) {
+    if (hubid_layout(kLayout)) {
         WalkState w;
         hubid_row(G, x, w);
         return w;
@@ -313,7 +292,7 @@ __device__ __forceinline__ void step(WalkState& w, uint32_t u, const DevGraph& G
         w.off = e.y;
         w.deg = e.z;
         w.inv = __uint_as_float(e.w);
-    } else if (kLayout == kLayoutCompact || kLayout == kLayoutCompactHub || kLayout == kLayoutHubId) {
+    } else if (kLayout == kLayoutCompact || kLayout == kLayoutCompactHub || hubid_layout(kLayout)) {
         // the 3 bytes at byte offset 3*pos lie in the aligned 8 bytes at word (3*pos)/4
         const uint32_t o = pos * 3u;
         const uint32_t wi = o >> 2;
@@ -321,7 +300,7 @@ __device__ __forceinline__ void step(WalkState& w, uint32_t u, const DevGraph& G
         const uint32_t hi = G.col24[wi + 1];
         const uint32_t x = __builtin_amdgcn_alignbit(hi, lo, (o & 3u) * 8u) & 0xFFFFFFu;
         if (kLayout == kLayoutCompact) compact_row(G, x, w);
-        else if (kLayout == kLayoutHubId) hubid_row(G, x, w);
+        else if (hubid_layout(kLayout)) hubid_row(G, x, w);
         else hub_row(G, x, w);
     } else if (kLayout == kLayoutHub32) {
         hub_row(G, G.col[pos], w);
@@ -346,7 +325,7 @@ __device__ __forceinline__ void stage_hubs(DevGraph& G, uint32_t* lds, uint32_t 
         __syncthreads();
         G.hub = l2;
         G.nhub = nh;
-    } else if constexpr (kLayout == kLayoutHubId) {
+    } else if constexpr (hubid_layout(kLayout)) {
         const uint32_t nh = min(capacity, G.dom.n);
         for (uint32_t i = threadIdx.x; i <= nh; i += blockDim.x) lds[i] = G.rp[i];
         __syncthreads();

@@ -322,6 +322,7 @@ extern "C" int graph_load_csr(int64_t n, const int64_t* row_ptr, const int32_t* 
     const bool wide = (flags & BD_LAYOUT_COMPACT) && (flags & BD_RELABEL_DEGREE) && !storage_probe &&
                       (n > (int64_t(1) << 24) || (flags & BD_WIDE_IDS));
     if ((flags & BD_NONTEMPORAL) && (flags & BD_TEMPORAL)) return BD_E_INVALID;
+    if ((flags & BD_NARROW_HUBS) && !(flags & BD_PROBE_STORAGE_IDS)) return BD_E_INVALID;
     if ((flags & (BD_NONTEMPORAL | BD_TEMPORAL)) && !(flags & BD_LAYOUT_FAT)) return BD_E_INVALID;
     if (flags & BD_LAYOUT_COMPACT) {
         if (flags & BD_LAYOUT_FAT) return BD_E_INVALID;
@@ -351,6 +352,7 @@ extern "C" int graph_load_csr(int64_t n, const int64_t* row_ptr, const int32_t* 
     g->layout = (flags & BD_LAYOUT_COMPACT) ? (storage_probe ? 5 : wide ? 4 : (flags & BD_RELABEL_DEGREE) ? 3 : 2)
                                             : (flags & BD_LAYOUT_FAT) ? 1 : 0;
     g->kernel_layout = g->layout;
+    if (g->layout == 5 && !(flags & BD_NARROW_HUBS)) g->kernel_layout = 7;
     if (g->layout == 1) {
         const int64_t fat_bytes = 16 * nnz + 16 * n;
         const bool nt = (flags & BD_NONTEMPORAL) ? true
@@ -503,6 +505,7 @@ extern "C" int bd_graph_get_info(const bd_graph* g, bd_graph_info* info)
     info->bipartite = g->bipartite;
     info->layout = g->layout;
     info->nontemporal = g->kernel_layout == 6 ? 1 : 0;
+    info->lds_hubs = hub_layout(g->kernel_layout) ? (int32_t)std::min<int64_t>(hub_nodes(1024, g->kernel_layout), g->n) : 0;
     info->device_bytes = g->device_bytes;
     return BD_OK;
 }
@@ -673,7 +676,7 @@ ChunkPlan chunk_plan(const bd_exec& ex, const QueryDesc& d, int layout)
     const Groups grp(d);
     const uint32_t R = d.R;
     const uint32_t pairs = ex.chunk_pairs > 0 ? std::max<uint32_t>((uint32_t)ex.chunk_pairs, 64u)
-                           : ex.mode == BD_MODE_PLAIN ? (uint32_t)block_threads(layout, share_class(d.share))
+                           : ex.mode == BD_MODE_PLAIN ? (uint32_t)group_pairs(layout, share_class(d.share))
                                                       : kSplitReplicas;
     if (ex.mode != BD_MODE_PLAIN && R >= kUniformMinR && R > pairs) {
         const uint32_t parts = (R + pairs - 1) / pairs;
@@ -1982,7 +1985,7 @@ void fill_slice(bd_server* S, Slice& sl)
         Chunk c;
     };
     std::vector<Item> big, small;  // wave-uniform chunks, then the rest
-    const uint64_t wg = (uint64_t)block_threads(S->g->kernel_layout, share_class(policy_share(S->pol)));
+    const uint64_t wg = (uint64_t)group_pairs(S->g->kernel_layout, share_class(policy_share(S->pol)));
     auto room = [&] { return big.size() + small.size() < kSliceMaxChunks; };
     // one chunk of request r (its next query in turn); false when it has none left
     auto take = [&](Request& r) {

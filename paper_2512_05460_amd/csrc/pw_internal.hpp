@@ -95,19 +95,60 @@ constexpr uint32_t kMaxShare = 4;
 // Kernel instance for a sharing factor M: 1, 2 or 4 probes per walk.
 inline int share_class(uint32_t M) { return M <= 1 ? 1 : M <= 2 ? 2 : 4; }
 
+// Layout codes of the kernels (0-5 are the graph layouts bd_graph_get_info
+// reports; 6 and 7 are kernel variants of layouts 1 and 5), and the hub
+// nodes they stage in LDS.
+constexpr int kLayoutCsr = 0, kLayoutFat = 1, kLayoutCompact = 2, kLayoutCompactHub = 3, kLayoutHub32 = 4,
+              kLayoutHubId = 5;
+// The fat layout read with non-temporal loads (the same tables and results):
+// for tables far larger than the Infinity Cache, where every step misses it
+// anyway and keeping the entries out of the caches' replacement order leaves
+// them to the node entries of the walks' start nodes.
+constexpr int kLayoutFatNT = 6;
+// Layout 5's tables with one 1,024-thread work group per CU: 36,864 hub row
+// offsets (144 KB of LDS) and two replica pairs per lane, so four dependent
+// load chains per lane keep as many loads in flight at four waves per SIMD as
+// two chains at eight.
+constexpr int kLayoutHubIdX2 = 7;
+constexpr bool hubid_layout(int layout) { return layout == kLayoutHubId || layout == kLayoutHubIdX2; }
+// replica pairs a lane runs at once
+constexpr int lane_pairs(int layout) { return layout == kLayoutHubIdX2 ? 2 : 1; }
+constexpr bool hub_layout(int layout)
+{
+    return layout == kLayoutCompactHub || layout == kLayoutHub32 || hubid_layout(layout);
+}
+// hub entries staged per work group (64 KB in 1,024-thread groups, 8 KB in
+// 256-thread ones): 8,192 / 1,024 node entries of 8 bytes, or 16,384 / 2,048
+// row offsets of 4 bytes with the probe on storage ids; 36,864 offsets in the
+// one-group-per-CU kernel of code 7
+constexpr uint32_t hub_nodes(int threads, int layout)
+{
+    if (layout == kLayoutHubIdX2 && threads >= 1024) return 36864u;  // 144 KB: what the CU's 160 KB leaves
+    return (threads >= 1024 ? 8192u : 1024u) * (layout == kLayoutHubIdX2 ? 4u : layout == kLayoutHubId ? 2u : 1u);
+}
+// 32-bit words of the LDS hub copy (entries 0 .. hub_nodes, inclusive)
+constexpr uint32_t hub_words(int threads, int layout)
+{
+    return !hub_layout(layout) ? 2u : hubid_layout(layout) ? hub_nodes(threads, layout) + 1u
+                                                            : 2u * (hub_nodes(threads, layout) + 1u);
+}
+
 constexpr int kBlockThreads = 256;
 // Work-group size of the walk and gather kernels per layout code and walk
-// sharing class. With one probe per walk the hubs-first layouts (codes 3, 4
-// and 5) stage the node entries of the 8,192 highest-degree nodes (64 KB; the
-// 16,384 row offsets with the probe on storage ids, code 5) in LDS
-// once per 1,024-thread work group: two groups per CU keep 8 waves per SIMD
-// within the 160 KB of LDS, and the staged nodes take 42% of the steps on a
-// Chung-Lu n=1e5 graph (1,024 nodes per 256-thread group take 18%). The
-// sharing kernels run 4-5 waves per SIMD, one such group per CU, and keep
-// 256-thread groups with 1,024 staged nodes.
-constexpr int block_threads(int layout, int share)
+// sharing class. With one probe per walk the hubs-first kernels (codes 3, 4, 5
+// and 7) run 1,024-thread work groups: codes 3 and 4 stage the node entries of
+// the 8,192 highest-degree nodes (64 KB), code 5 their 16,384 row offsets, two
+// groups per CU at 8 waves per SIMD; code 7 stages 36,864 offsets (144 KB) in
+// one group per CU at 4 waves per SIMD with two replica pairs per thread. On
+// the Chung-Lu n=1e5 graph the staged nodes take 42%, 54% and 73% of the walk
+// steps. The sharing kernels run 4-5 waves per SIMD, one such group per CU,
+// and keep 256-thread groups.
+constexpr int block_threads(int layout, int share) { return hub_layout(layout) && share <= 1 ? 1024 : kBlockThreads; }
+// (probe, replica) pairs one work group runs at once: a pair per thread, two
+// per thread in the kernel of layout code 7
+constexpr int group_pairs(int layout, int share)
 {
-    return (layout == 3 || layout == 4 || layout == 5) && share <= 1 ? 1024 : kBlockThreads;
+    return block_threads(layout, share) * (share <= 1 ? lane_pairs(layout) : 1);
 }
 constexpr uint32_t kMaxQueues = 8;      // one chunk queue per XCD
 constexpr int kMaxChunkProbes = 256;

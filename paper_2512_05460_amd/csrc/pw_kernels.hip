@@ -97,6 +97,71 @@ __device__ __forceinline__ float walk_pair(const DevGraph& G, const Probe& pr, W
     return __fsub_rn(a, b);
 }
 
+// Two replica pairs per lane (layout code 7): U_p1 of probe k1 and U_p2 of
+// probe k2, the four walks interleaved step by step so that four dependent
+// loads are in flight per lane. Each walk is the one walk_pair runs.
+template <int kLayout>
+__device__ __forceinline__ void walk_pair2(const DevGraph& G, const Probe& pr1, const Probe& pr2, WalkState s0,
+                                           WalkState t0, int L, uint32_t p1, uint32_t k1, uint32_t p2, uint32_t k2,
+                                           uint32_t uid, uint32_t slo, uint32_t shi, float* U1, float* U2)
+{
+    WalkState s1 = s0, t1 = t0, s2 = s0, t2 = t0;
+    float a1 = 0.0f, b1 = 0.0f, a2 = 0.0f, b2 = 0.0f;
+    const uint32_t cs = uid << 1, ct = (uid << 1) | 1u;
+    const int full = L >> 2;
+    for (int blk = 0; blk < full; ++blk) {
+        const U4 rs1 = philox10((uint32_t)blk, p1, k1, cs, slo, shi);
+        const U4 rt1 = philox10((uint32_t)blk, p1, k1, ct, slo, shi);
+        const U4 rs2 = philox10((uint32_t)blk, p2, k2, cs, slo, shi);
+        const U4 rt2 = philox10((uint32_t)blk, p2, k2, ct, slo, shi);
+        a1 = advance<kLayout>(s1, a1, rs1.x, G, pr1);
+        b1 = advance<kLayout>(t1, b1, rt1.x, G, pr1);
+        a2 = advance<kLayout>(s2, a2, rs2.x, G, pr2);
+        b2 = advance<kLayout>(t2, b2, rt2.x, G, pr2);
+        a1 = advance<kLayout>(s1, a1, rs1.y, G, pr1);
+        b1 = advance<kLayout>(t1, b1, rt1.y, G, pr1);
+        a2 = advance<kLayout>(s2, a2, rs2.y, G, pr2);
+        b2 = advance<kLayout>(t2, b2, rt2.y, G, pr2);
+        a1 = advance<kLayout>(s1, a1, rs1.z, G, pr1);
+        b1 = advance<kLayout>(t1, b1, rt1.z, G, pr1);
+        a2 = advance<kLayout>(s2, a2, rs2.z, G, pr2);
+        b2 = advance<kLayout>(t2, b2, rt2.z, G, pr2);
+        a1 = advance<kLayout>(s1, a1, rs1.w, G, pr1);
+        b1 = advance<kLayout>(t1, b1, rt1.w, G, pr1);
+        a2 = advance<kLayout>(s2, a2, rs2.w, G, pr2);
+        b2 = advance<kLayout>(t2, b2, rt2.w, G, pr2);
+    }
+    const int rem = L & 3;
+    if (rem) {
+        const U4 rs1 = philox10((uint32_t)full, p1, k1, cs, slo, shi);
+        const U4 rt1 = philox10((uint32_t)full, p1, k1, ct, slo, shi);
+        const U4 rs2 = philox10((uint32_t)full, p2, k2, cs, slo, shi);
+        const U4 rt2 = philox10((uint32_t)full, p2, k2, ct, slo, shi);
+        a1 = advance<kLayout>(s1, a1, rs1.x, G, pr1);
+        b1 = advance<kLayout>(t1, b1, rt1.x, G, pr1);
+        a2 = advance<kLayout>(s2, a2, rs2.x, G, pr2);
+        b2 = advance<kLayout>(t2, b2, rt2.x, G, pr2);
+        if (rem > 1) {
+            a1 = advance<kLayout>(s1, a1, rs1.y, G, pr1);
+            b1 = advance<kLayout>(t1, b1, rt1.y, G, pr1);
+            a2 = advance<kLayout>(s2, a2, rs2.y, G, pr2);
+            b2 = advance<kLayout>(t2, b2, rt2.y, G, pr2);
+        }
+        if (rem > 2) {
+            a1 = advance<kLayout>(s1, a1, rs1.z, G, pr1);
+            b1 = advance<kLayout>(t1, b1, rt1.z, G, pr1);
+            a2 = advance<kLayout>(s2, a2, rs2.z, G, pr2);
+            b2 = advance<kLayout>(t2, b2, rt2.z, G, pr2);
+        }
+    }
+    a1 = add_term(a1, s1.x, s1.inv, pr1, G.dom);
+    b1 = add_term(b1, t1.x, t1.inv, pr1, G.dom);
+    a2 = add_term(a2, s2.x, s2.inv, pr2, G.dom);
+    b2 = add_term(b2, t2.x, t2.inv, pr2, G.dom);
+    *U1 = __fsub_rn(a1, b1);
+    *U2 = __fsub_rn(a2, b2);
+}
+
 // Walk sharing: one walk scored against the m <= kShare probes of a group.
 // The terms of each probe enter its own binary32 sum in step order, exactly as
 // in advance/walk_pair.
@@ -235,7 +300,82 @@ __device__ void run_chunk(const WalkArgs& A, const DevGraph& G, uint32_t ci,
     // walk sharing: M probes per group, ceil(B/M) groups per block
     const uint32_t M = kShare == 1 ? 1u : d.share;
     const uint32_t gpb = (d.B + M - 1) / M;
-    if (kUniform) {
+    constexpr bool kDual = kLayout == kLayoutHubIdX2 && kShare == 1;
+    if (kDual && kUniform) {
+        // Two blocks of 64 replicas per wave pass: units u and u + nw, each of
+        // one probe (wave-uniform keys). A lane whose replica lies past the
+        // chunk walks a clamped in-range replica and drops the result, so the
+        // wave never splits into the single- and two-pair paths.
+        const uint32_t wave = __builtin_amdgcn_readfirstlane((uint32_t)tid >> 6);
+        const uint32_t lane = (uint32_t)tid & 63u;
+        const uint32_t nb = (c.pc + 63u) >> 6;
+        const uint32_t units = c.gc * nb;
+        const uint32_t pend = c.p0 + c.pc;
+        constexpr uint32_t nw = (uint32_t)kT / 64u;
+        for (uint32_t u = wave; u < units; u += 2u * nw) {
+            const uint32_t gg1 = u / nb;
+            const uint32_t q1 = c.p0 + (u - gg1 * nb) * 64u + lane;
+            const uint32_t k1 = c.k0 + gg1;
+            const Probe pr1 = make_probe(d.seed_lo, d.seed_hi, d.uid, k1, G.dom.n);
+            const uint32_t u2 = u + nw;
+            if (u2 < units) {
+                const uint32_t gg2 = u2 / nb;
+                const uint32_t q2 = c.p0 + (u2 - gg2 * nb) * 64u + lane;
+                const uint32_t k2 = c.k0 + gg2;
+                const Probe pr2 = make_probe(d.seed_lo, d.seed_hi, d.uid, k2, G.dom.n);
+                float U1, U2;
+                walk_pair2<kLayout>(G, pr1, pr2, s0, t0, d.L, min(q1, pend - 1u), k1, min(q2, pend - 1u), k2, d.uid,
+                                    d.seed_lo, d.seed_hi, &U1, &U2);
+                if (q1 < pend) {
+                    lds_add_i128(acc + 4 * gg1, fix54(U1));
+                    lds_add_i128(acc + 4 * gg1 + 2, (i128)sqfix64(U1));
+                }
+                if (q2 < pend) {
+                    lds_add_i128(acc + 4 * gg2, fix54(U2));
+                    lds_add_i128(acc + 4 * gg2 + 2, (i128)sqfix64(U2));
+                }
+            } else if (q1 < pend) {
+                const float U = walk_pair<kLayout>(G, pr1, s0, t0, d.L, q1, k1, d.uid, d.seed_lo, d.seed_hi);
+                lds_add_i128(acc + 4 * gg1, fix54(U));
+                lds_add_i128(acc + 4 * gg1 + 2, (i128)sqfix64(U));
+            }
+        }
+    } else if (kDual) {
+        // Lanes over the chunk's (probe, replica) pairs, two per lane per pass
+        // (items base + tid and base + kT + tid); as above, an item past the
+        // end is replaced by the last one and its result dropped.
+        const uint64_t total = (uint64_t)c.gc * c.pc;
+        for (uint64_t base = 0; base < total; base += 2u * (uint64_t)kT) {
+            const uint64_t w1 = base + (uint64_t)tid, w2 = w1 + (uint64_t)kT;
+            if (base + (uint64_t)kT < total) {
+                const uint64_t x1 = min(w1, total - 1u), x2 = min(w2, total - 1u);
+                const uint32_t gg1 = (uint32_t)(x1 / c.pc), gg2 = (uint32_t)(x2 / c.pc);
+                const uint32_t p1 = c.p0 + (uint32_t)(x1 - (uint64_t)gg1 * c.pc);
+                const uint32_t p2 = c.p0 + (uint32_t)(x2 - (uint64_t)gg2 * c.pc);
+                const uint32_t k1 = c.k0 + gg1, k2 = c.k0 + gg2;
+                const Probe pr1 = make_probe(d.seed_lo, d.seed_hi, d.uid, k1, G.dom.n);
+                const Probe pr2 = make_probe(d.seed_lo, d.seed_hi, d.uid, k2, G.dom.n);
+                float U1, U2;
+                walk_pair2<kLayout>(G, pr1, pr2, s0, t0, d.L, p1, k1, p2, k2, d.uid, d.seed_lo, d.seed_hi, &U1, &U2);
+                if (w1 < total) {
+                    lds_add_i128(acc + 4 * gg1, fix54(U1));
+                    lds_add_i128(acc + 4 * gg1 + 2, (i128)sqfix64(U1));
+                }
+                if (w2 < total) {
+                    lds_add_i128(acc + 4 * gg2, fix54(U2));
+                    lds_add_i128(acc + 4 * gg2 + 2, (i128)sqfix64(U2));
+                }
+            } else if (w1 < total) {
+                const uint32_t gg = (uint32_t)(w1 / c.pc);
+                const uint32_t p = c.p0 + (uint32_t)(w1 - (uint64_t)gg * c.pc);
+                const uint32_t k = c.k0 + gg;
+                const Probe pr = make_probe(d.seed_lo, d.seed_hi, d.uid, k, G.dom.n);
+                const float U = walk_pair<kLayout>(G, pr, s0, t0, d.L, p, k, d.uid, d.seed_lo, d.seed_hi);
+                lds_add_i128(acc + 4 * gg, fix54(U));
+                lds_add_i128(acc + 4 * gg + 2, (i128)sqfix64(U));
+            }
+        }
+    } else if (kUniform) {
         // Each wave takes blocks of 64 consecutive replicas of one group, so the
         // group and every probe key are uniform across the wave (scalar
         // registers); only the last block of a group runs partially masked.
@@ -383,7 +523,8 @@ __device__ __forceinline__ bool abort_raised(const WalkArgs& A)
 // Eight waves per SIMD where the kernel fits 64 VGPRs without spilling.
 template <int kLayout, int kUniform, int kShare>
 __global__ __launch_bounds__(block_threads(kLayout, kShare),
-                             kShare == 1 && (kUniform || kLayout == kLayoutCompact || hub_layout(kLayout)) ? 8
+                             kShare == 1 && kLayout == kLayoutHubIdX2                                       ? 4
+                             : kShare == 1 && (kUniform || kLayout == kLayoutCompact || hub_layout(kLayout)) ? 8
                                                                                                             : 1) void
 walk_kernel(WalkArgs A)
 {
@@ -457,6 +598,7 @@ static const void* walk_fn(int layout, int uniform, int share)
     if (layout == kLayoutCompactHub) return walk_fn_l<kLayoutCompactHub>(uniform, share);
     if (layout == kLayoutHub32) return walk_fn_l<kLayoutHub32>(uniform, share);
     if (layout == kLayoutHubId) return walk_fn_l<kLayoutHubId>(uniform, share);
+    if (layout == kLayoutHubIdX2) return walk_fn_l<kLayoutHubIdX2>(uniform, share);
     return walk_fn_l<kLayoutCsr>(uniform, share);
 }
 
@@ -492,6 +634,9 @@ hipError_t launch_walk(const WalkArgs& a, int layout, int uniform, int share, ui
     } else if (layout == kLayoutHubId) {
         if (uniform) launch_l<kLayoutHubId, 1>(a, share, grid, st);
         else launch_l<kLayoutHubId, 0>(a, share, grid, st);
+    } else if (layout == kLayoutHubIdX2) {
+        if (uniform) launch_l<kLayoutHubIdX2, 1>(a, share, grid, st);
+        else launch_l<kLayoutHubIdX2, 0>(a, share, grid, st);
     } else {
         if (uniform) launch_l<kLayoutCsr, 1>(a, share, grid, st);
         else launch_l<kLayoutCsr, 0>(a, share, grid, st);
@@ -591,6 +736,7 @@ hipError_t launch_trace(const GraphTables& g, int layout, uint32_t count, const 
     else if (layout == kLayoutCompactHub) PW_TRACE(3);
     else if (layout == kLayoutHub32) PW_TRACE(4);
     else if (layout == kLayoutHubId) PW_TRACE(5);
+    else if (layout == kLayoutHubIdX2) PW_TRACE(7);
     else PW_TRACE(0);
 #undef PW_TRACE
     return hipGetLastError();
@@ -684,6 +830,7 @@ hipError_t launch_gather(const GraphTables& g, int layout, int chains, uint32_t 
     else if (layout == kLayoutCompactHub) PW_GATHER_C(3);
     else if (layout == kLayoutHub32) PW_GATHER_C(4);
     else if (layout == kLayoutHubId) PW_GATHER_C(5);
+    else if (layout == kLayoutHubIdX2) PW_GATHER_C(7);
     else PW_GATHER_C(0);
 #undef PW_GATHER_C
 #undef PW_GATHER

@@ -290,18 +290,23 @@ def test_alone_equals_in_batch(ba1k):
 
 
 @pytest.mark.parametrize("layout", [B.BD_LAYOUT_COMPACT, B.BD_LAYOUT_FAT, B.BD_LAYOUT_COMPACT | B.BD_RELABEL_DEGREE])
-def test_full_size_sampled_parity(cl100k, layout):
+@pytest.mark.parametrize("mode", ["plain", "batched"])
+def test_full_size_sampled_parity(cl100k, layout, mode):
     # Bench shape: Chung-Lu n=1e5, L = 1000, eps = 0.05; per-probe Q checked on
     # sampled probes (the oracle runs R walk pairs of 1000 steps per probe).
+    # Queries 0 and 1 of the set, and the first with R above the batched split
+    # size (4096 replicas), whose probes the batched mode cuts into replica parts.
     from paper_2512_05460_amd.budgets import budget_policy
     dg = load(cl100k, layout)
     s, t = queries.uniform_pairs(cl100k.n, 4096, graphs.GRAPH_SEED + 1 + graphs.QUERY_SEED_OFFSET)
     pol = budget_policy("cl100k")
-    for i in (0, 1):
+    Rs = B.bd_plan(dg, s[:200], t[:200], 0.05, 1000, pol)["R"]
+    split = int(np.flatnonzero((Rs > 4096) & (Rs <= 20000))[0])
+    for i in sorted({0, 1, split}):
         plan = B.bd_plan(dg, s[i:i + 1], t[i:i + 1], [0.05], [1000], pol)[0]
         if plan["R"] > 20000:
             continue
-        res, q, y = B.bd_query_probes(dg, int(s[i]), int(t[i]), 0.05, 1000, i, SEED, pol)
+        res, q, y = B.bd_query_probes(dg, int(s[i]), int(t[i]), 0.05, 1000, i, SEED, pol, B.exec_cfg(mode))
         ks = np.linspace(0, plan["K"] - 1, 8).astype(np.uint32)
         _say(f"[sampled] query {i} K={plan['K']} R={plan['R']}")
         oq = E.probe_q(cl100k, int(s[i]), int(t[i]), 1000, i, int(plan["R"]), SEED, ks, threads=8)

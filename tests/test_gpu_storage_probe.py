@@ -7,7 +7,9 @@ caller's neighbour order with the ids renamed. On that graph the library's
 results must equal the oracle's bit for bit (Algorithm 1: probe values,
 walks, per-probe Q, block means, estimates, in every mode, with split probes
 and with walk sharing), and its walks, reported in caller ids, are the same
-walks as every other layout's.
+walks as every other layout's. The same holds for both of its kernels: one
+work group per CU with two replica pairs per thread (the default) and two
+work groups per CU with one (BD_NARROW_HUBS).
 """
 
 import numpy as np
@@ -36,12 +38,19 @@ def relabelled(g):
     return graphs.Csr(n=g.n, row_ptr=rp, col=col, name=g.name + "-storage"), order, internal
 
 
-@pytest.fixture(scope="module", params=["ba1k", "cl100k"])
+@pytest.fixture(scope="module", params=[("ba1k", 0), ("cl100k", 0), ("ba1k", B.BD_NARROW_HUBS),
+                                        ("cl100k", B.BD_NARROW_HUBS)])
 def pair(request):
-    g = graphs.workload_graph(request.param)
+    # the default kernel (one work group per CU, 36,864 staged offsets, two
+    # replica pairs per thread) and BD_NARROW_HUBS (two work groups per CU,
+    # 16,384 offsets, one pair per thread)
+    key, narrow = request.param
+    g = graphs.workload_graph(key)
     g5, order, internal = relabelled(g)
-    dg = B.graph_load_csr(g.n, g.row_ptr, g.col, FLAGS)
-    assert dg.info()["layout"] == 5
+    dg = B.graph_load_csr(g.n, g.row_ptr, g.col, FLAGS | narrow)
+    info = dg.info()
+    assert info["layout"] == 5
+    assert info["lds_hubs"] == min(g.n, 16384 if narrow else 36864)
     yield g, g5, order, internal, dg
     dg.free()
 
@@ -111,3 +120,25 @@ def test_walk_sharing(pair, M):
     res = B.bd_query_batch(dg, s, t, 0.1, L, SEED, pol, B.exec_cfg("batched"))
     ref = E.estimate(g5, internal[s], internal[t], L, _plans(L, 5, 90, 1), SEED, threads=8, share=M)
     assert np.array_equal(res["beta"], ref)
+
+
+@pytest.mark.parametrize("mode", ["plain", "batched"])
+def test_bench_shape_sampled_probes(pair, mode):
+    # The headline's shape: Chung-Lu n=1e5, eps = 0.05, L = 1000 at its
+    # calibrated walk counts; sampled per-probe Q against the oracle on the
+    # relabelled graph, for query 0 of the set and the first one whose R
+    # exceeds the batched split size (its probes run as replica parts).
+    from paper_2512_05460_amd.budgets import budget_policy
+    g, g5, order, internal, dg = pair
+    if g.name != "cl100k":
+        pytest.skip("bench shape is the Chung-Lu n=1e5 graph")
+    s, t = queries.uniform_pairs(g.n, 4096, graphs.GRAPH_SEED + 1 + graphs.QUERY_SEED_OFFSET)
+    pol = budget_policy("cl100k")
+    Rs = B.bd_plan(dg, s[:200], t[:200], 0.05, 1000, pol)["R"]
+    split = int(np.flatnonzero((Rs > 4096) & (Rs <= 20000))[0])
+    for i in sorted({0, split}):
+        plan = B.bd_plan(dg, s[i:i + 1], t[i:i + 1], [0.05], [1000], pol)[0]
+        res, q, y = B.bd_query_probes(dg, int(s[i]), int(t[i]), 0.05, 1000, i, SEED, pol, B.exec_cfg(mode))
+        ks = np.linspace(0, plan["K"] - 1, 8).astype(np.uint32)
+        oq = E.probe_q(g5, int(internal[s[i]]), int(internal[t[i]]), 1000, i, int(plan["R"]), SEED, ks, threads=8)
+        assert np.array_equal(q[ks], oq), (i, int(plan["R"]))
