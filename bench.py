@@ -517,8 +517,10 @@ def scale_cl40m_default(B, torch, stream, pairs=32, thr_queries=65536):
     dt2 = time.perf_counter() - t0
     assert np.all(r2["status"] == 0)
     ksps = tsteps / (st2["walk_kernel_ms"] / 1e3)
-    thr = {"walk_counts": "throughput setting, not calibrated: " + BUDGETS["cl40m"][2],
-           "queries": thr_queries, "walk_steps": tsteps, "queries_per_s": thr_queries / dt2,
+    thr = {"walk_counts": BUDGETS["cl40m"][2] + " (not eps-accurate: compare walk_steps_per_query_mean "
+                                                 "with calibrated_L1000)",
+           "queries": thr_queries, "walk_steps": tsteps, "walk_steps_per_query_mean": tsteps / thr_queries,
+           "queries_per_s": thr_queries / dt2,
            "walk_steps_per_s": tsteps / dt2, "kernel_walk_steps_per_s": ksps}
     kv, why = read_counters(FAT_SCALE_COUNTERS)
     if info["layout"] == 1 and kv is not None:
