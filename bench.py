@@ -667,12 +667,14 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--queries", type=int, default=32, help="queries per step")
-    ap.add_argument("--layout", choices=["hubs", "hubsid", "hubsidn", "compact", "csr", "fat", "auto"],
+    ap.add_argument("--layout", choices=["hubs", "hubsid", "hubsidd", "hubsidn", "compact", "csr", "fat", "auto"],
                     default="hubsid",
                     help="hubs: compact layout with nodes in descending-degree order and hub entries in LDS; "
-                         "hubsid: the same with the probe on storage ids (4-byte node entries; one work group per "
-                         "CU with 36,864 hubs in LDS and two replica pairs per thread); hubsidn: hubsid with two "
-                         "work groups per CU and 16,384 hubs each; auto: the library's choice (hubs at this size)")
+                         "hubsid: the same with the probe on storage ids (one work group per CU with two replica "
+                         "pairs per thread and every node's row offset and degree in LDS from the degree-run "
+                         "table); hubsidd: hubsid with the row offsets of the 36,864 highest-degree nodes in LDS "
+                         "instead; hubsidn: hubsid with two work groups per CU and 16,384 offsets each; auto: the "
+                         "library's choice (hubs at this size)")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--no-roofline", action="store_true")
@@ -714,6 +716,7 @@ def main():
     s, t = s_all[:nq], t_all[:nq]
     flags = {"hubs": B.BD_LAYOUT_COMPACT | B.BD_RELABEL_DEGREE,
              "hubsid": B.BD_LAYOUT_COMPACT | B.BD_RELABEL_DEGREE | B.BD_PROBE_STORAGE_IDS,
+             "hubsidd": B.BD_LAYOUT_COMPACT | B.BD_RELABEL_DEGREE | B.BD_PROBE_STORAGE_IDS | B.BD_DIRECT_HUBS,
              "hubsidn": B.BD_LAYOUT_COMPACT | B.BD_RELABEL_DEGREE | B.BD_PROBE_STORAGE_IDS | B.BD_NARROW_HUBS,
              "compact": B.BD_LAYOUT_COMPACT,
              "csr": B.BD_LAYOUT_CSR | B.BD_RELABEL_DEGREE,
@@ -888,6 +891,7 @@ def main():
                          "eps=0.05, L=1000; plain mode, one query per launch"),
             "queries_per_step": nq,
             "layout": args.layout,
+            "lds_nodes": int(dg.info()["lds_hubs"]),
             "policy": {"kind": "scaled", "c_B": c_B, "c_R": c_R, "delta": 0.01, "calibration": how},
             "K": int(plan["K"][0]), "R_median": int(np.median(plan["R"])),
             "walk_steps_per_step": steps_per_batch,

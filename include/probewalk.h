@@ -116,6 +116,16 @@ typedef struct bd_graph bd_graph;
                                    of this layout run one 1,024-thread work group per CU that
                                    stages 36,864 offsets (144 KB of the CU's 160 KB of LDS)
                                    with two replica pairs per thread. Same results */
+#define BD_DIRECT_HUBS   2048u  /* with BD_PROBE_STORAGE_IDS: stage the row offsets of the
+                                   36,864 highest-degree nodes (layout code 7) even where
+                                   the degree-run table fits. Without it (and without
+                                   BD_NARROW_HUBS) the walks resolve every node in LDS when
+                                   they can: the offsets of the first h1 storage ids, past
+                                   which every run of equal degree is at least 64 long and
+                                   at most 4,095, then one 8-byte record per 64 storage ids
+                                   (layout code 8), if those take at most 144 KB (on the
+                                   Chung-Lu n=1e5 graph h1 = 1,934 and 20 KB); a walk step
+                                   then makes one global load instead of two. Same results */
 #define BD_DEVICE_PTRS     64u  /* row_ptr and col_idx are device pointers on the current
                                    device (e.g. the data of PyTorch tensors) instead of host
                                    arrays; they are read once, on `stream`, and not kept.
@@ -138,8 +148,9 @@ typedef struct {
                                 the probe on storage ids */
     int64_t  device_bytes;   /* device memory held by the graph tables */
     int32_t  nontemporal;    /* 1 if the fat layout reads its entries with non-temporal loads */
-    int32_t  lds_hubs;       /* node entries staged in LDS per work group of the walk kernels
-                                with one probe per walk (0 = none) */
+    int32_t  lds_hubs;       /* nodes whose row offset and degree the walk kernels with one
+                                probe per walk read from LDS (0 = none; n with the
+                                degree-run table) */
 } bd_graph_info;
 
 /*
@@ -446,8 +457,9 @@ typedef struct {
  * and device streams; requests submitted while others run are admitted at
  * the next slice boundary as capacity frees up, and their chunks share the
  * device with the running ones (part of each slice to the requests with the
- * least work left, the rest round-robin over requests; replica parts of at
- * most 1024 pairs). The graph must outlive the server.
+ * least work left, the rest round-robin over requests; chunks of at most one
+ * work group's pairs, so that no chunk holds a slice open for long). The
+ * graph must outlive the server.
  */
 int  bd_server_create(bd_graph* g, const bd_server_cfg* cfg, bd_server** out);
 /* Submit nq queries (host arrays, copied). Returns a request id. BD_E_FULL if

@@ -60,6 +60,7 @@ BD_PROBE_STORAGE_IDS = 128
 BD_NONTEMPORAL = 256
 BD_TEMPORAL = 512
 BD_NARROW_HUBS = 1024
+BD_DIRECT_HUBS = 2048
 
 BD_POLICY_PAPER = 0
 BD_POLICY_SCALED = 1

@@ -59,13 +59,15 @@ def probe_values(dg, s, t, eps: float, L, seed: int, c_B: float, c_R: float, uid
     pol = B.policy("scaled", c_B=c_B, c_R=c_R)
     out = []
     L = np.broadcast_to(np.asarray(L), np.shape(s))
+    t0 = time.time()
     for i in range(len(s)):
         u = i if uid is None else int(uid[i])
         res, q, _ = B.bd_query_probes(dg, int(s[i]), int(t[i]), eps, int(L[i]), u, seed, pol,
                                       B.exec_cfg("batched"))
         out.append((q, res))
-        if log is not None and (i + 1) % 16 == 0:
-            log(f"    {i + 1}/{len(s)} queries")
+        # a line per query where queries are long (each is one device call)
+        if log is not None and ((i + 1) % 16 == 0 or int(L[i]) > 2000):
+            log(f"    {i + 1}/{len(s)} queries, {time.time() - t0:.1f} s")
     return out
 
 

@@ -190,6 +190,9 @@ struct DevGraph {
     const uint2* node8;     // n + 1 entries {row offset, original id} (compact layout, hubs first)
     const uint2* hub;       // LDS copy of node8[0 .. nhub] (nhub = 0: none)
     const uint32_t* hub4;   // LDS copy of rp[0 .. nhub] (probe on storage ids)
+    const uint2* runrec;    // code 8: LDS run records of the storage ids past nhub (null: none)
+    const uint32_t* runtab; // code 8: the table staged in LDS (global memory)
+    uint32_t run_h1, run_words;
     uint32_t nhub;
     Domain dom;
 };
@@ -251,6 +254,35 @@ __device__ __forceinline__ void hubid_row(const DevGraph& G, uint32_t x, WalkSta
     w.inv = __fdiv_rn(1.0f, (float)w.deg);
 }
 
+// Node x with every node resolved from LDS (code 8): the row offsets of the
+// first nhub storage ids, then one record per block of kRunBlock storage ids
+// past them (the layout is described with kLayoutHubRuns). Without the
+// records (a kernel that did not stage them) the global row offsets give the
+// same values.
+__device__ __forceinline__ void runs_row(const DevGraph& G, uint32_t x, WalkState& w)
+{
+    uint32_t b, d;
+    if (x < G.nhub) {
+        b = G.hub4[x];
+        d = G.hub4[x + 1] - b;
+    } else if (G.runrec != nullptr) {
+        const uint32_t i = x - G.nhub;
+        const uint2 r = G.runrec[i / kRunBlock];
+        const uint32_t j = i % kRunBlock;
+        const uint32_t dA = r.y & kRunMaxDeg, dB = (r.y >> 12) & kRunMaxDeg, bnd = r.y >> 24;
+        const uint32_t ja = min(j, bnd);
+        b = r.x + ja * dA + (j - ja) * dB;
+        d = j < bnd ? dA : dB;
+    } else {
+        b = G.rp[x];
+        d = G.rp[x + 1] - b;
+    }
+    w.x = x;
+    w.off = b;
+    w.deg = d;
+    w.inv = __fdiv_rn(1.0f, (float)d);
+}
+
 // Walk state at internal id x (the start of a walk).
 template <int kLayout>
 __device__ __forceinline__ WalkState start_at(const DevGraph& G, uint32_t x)
@@ -263,6 +295,11 @@ __device__ __forceinline__ WalkState start_at(const DevGraph& G, uint32_t x)
     if (kLayout == kLayoutCompactHub || kLayout == kLayoutHub32) {
         WalkState w;
         hub_row(G, x, w);
+        return w;
+    }
+    if (kLayout == kLayoutHubRuns) {
+        WalkState w;
+        runs_row(G, x, w);
         return w;
     }
     if (hubid_layout(kLayout)) {
@@ -300,6 +337,7 @@ __device__ __forceinline__ void step(WalkState& w, uint32_t u, const DevGraph& G
         const uint32_t hi = G.col24[wi + 1];
         const uint32_t x = __builtin_amdgcn_alignbit(hi, lo, (o & 3u) * 8u) & 0xFFFFFFu;
         if (kLayout == kLayoutCompact) compact_row(G, x, w);
+        else if (kLayout == kLayoutHubRuns) runs_row(G, x, w);
         else if (hubid_layout(kLayout)) hubid_row(G, x, w);
         else hub_row(G, x, w);
     } else if (kLayout == kLayoutHub32) {
@@ -325,6 +363,17 @@ __device__ __forceinline__ void stage_hubs(DevGraph& G, uint32_t* lds, uint32_t 
         __syncthreads();
         G.hub = l2;
         G.nhub = nh;
+    } else if constexpr (kLayout == kLayoutHubRuns) {
+        // the whole run table when it fits, else the first row offsets only
+        // (the other nodes then read the global row offsets)
+        const bool all = G.run_words <= capacity + 1u;
+        const uint32_t nh = all ? G.run_h1 : min(capacity, G.run_h1);
+        const uint32_t words = all ? G.run_words : nh + 1u;
+        for (uint32_t i = threadIdx.x; i < words; i += blockDim.x) lds[i] = G.runtab[i];
+        __syncthreads();
+        G.hub4 = lds;
+        G.nhub = nh;
+        G.runrec = all ? reinterpret_cast<const uint2*>(lds + run_records_at(nh)) : nullptr;
     } else if constexpr (hubid_layout(kLayout)) {
         const uint32_t nh = min(capacity, G.dom.n);
         for (uint32_t i = threadIdx.x; i <= nh; i += blockDim.x) lds[i] = G.rp[i];

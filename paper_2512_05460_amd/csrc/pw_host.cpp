@@ -154,12 +154,14 @@ struct bd_graph {
     int32_t d_min = 0, d_max = 0;
     int32_t bipartite = 0;
     int32_t layout = 0;  // 0 CSR, 1 fat, 2 compact, ... (kLayout* of the kernels)
-    int32_t kernel_layout = 0;  // the kernels' layout code: layout, or 6 for fat with non-temporal loads
+    int32_t kernel_layout = 0;  // the kernels' layout code: layout, 6 for fat with non-temporal
+                                // loads, 7 or 8 for layout 5 (kLayout* of the kernels)
     int device = 0;
     std::vector<int32_t> deg;        // host copy for the planner, by caller id
     std::vector<uint32_t> internal;  // caller id -> storage id (empty: identity)
     std::vector<uint32_t> external;  // storage id -> caller id where walks see storage ids (layout 5)
-    DevBuf node, col, adj, rp32, col24, node8;
+    DevBuf node, col, adj, rp32, col24, node8, runtab;
+    uint32_t run_h1 = 0, run_words = 0;  // code 8: direct row offsets, words of runtab
     DomainParams dom{};
     int64_t device_bytes = 0;
     std::mutex mu;  // serialises calls that use the per-graph work buffers
@@ -183,6 +185,45 @@ DomainParams make_domain(uint32_t n)
     d.A = (uint32_t)((uint64_t(n) + d.mask) >> d.rb);
     d.A8 = d.A << 8;
     return d;
+}
+
+// The degree-run table of kernel code 8 from the row offsets rp[0..n] of a
+// graph stored in descending-degree order: h1 is the end of the last run of
+// equal degree that is shorter than kRunBlock or whose degree exceeds
+// kRunMaxDeg, so each block of kRunBlock storage ids past it holds at most two
+// runs. The table is rp[0..h1], padding to an even word, then per block
+// {rp of its first node, dA | dB << 12 | bnd << 24}. False if it would not fit
+// the LDS of the walk kernels.
+bool build_run_table(const std::vector<uint32_t>& rp, uint32_t* h1_out, std::vector<uint32_t>* out)
+{
+    const size_t n = rp.size() - 1;
+    auto deg = [&](size_t i) { return rp[i + 1] - rp[i]; };
+    size_t h1 = 0;
+    for (size_t i = 0; i < n;) {
+        size_t j = i + 1;
+        while (j < n && deg(j) == deg(i)) ++j;
+        if (j - i < kRunBlock || deg(i) > kRunMaxDeg) h1 = j;
+        i = j;
+    }
+    const size_t blocks = (n - h1 + kRunBlock - 1) / kRunBlock;
+    const size_t at = run_records_at((uint32_t)h1);
+    const size_t words = at + 2 * blocks;
+    if (words > hub_words(1024, kLayoutHubRuns)) return false;
+    out->assign(words, 0u);
+    for (size_t i = 0; i <= h1; ++i) (*out)[i] = rp[i];
+    for (size_t b = 0; b < blocks; ++b) {
+        const size_t f = h1 + b * kRunBlock, len = std::min<size_t>(kRunBlock, n - f);
+        const uint32_t dA = deg(f);
+        size_t bnd = 0;
+        while (bnd < len && deg(f + bnd) == dA) ++bnd;
+        const uint32_t dB = bnd < len ? deg(f + bnd) : 0u;
+        for (size_t k = bnd; k < len; ++k)
+            if (deg(f + k) != dB) return false;  // three runs in one block: cannot happen past h1
+        (*out)[at + 2 * b] = rp[f];
+        (*out)[at + 2 * b + 1] = dA | (dB << 12) | ((uint32_t)bnd << 24);
+    }
+    *h1_out = (uint32_t)h1;
+    return true;
 }
 
 // Checks run on the host, in parallel over node ranges.
@@ -323,6 +364,7 @@ extern "C" int graph_load_csr(int64_t n, const int64_t* row_ptr, const int32_t* 
                       (n > (int64_t(1) << 24) || (flags & BD_WIDE_IDS));
     if ((flags & BD_NONTEMPORAL) && (flags & BD_TEMPORAL)) return BD_E_INVALID;
     if ((flags & BD_NARROW_HUBS) && !(flags & BD_PROBE_STORAGE_IDS)) return BD_E_INVALID;
+    if ((flags & BD_DIRECT_HUBS) && !(flags & BD_PROBE_STORAGE_IDS)) return BD_E_INVALID;
     if ((flags & (BD_NONTEMPORAL | BD_TEMPORAL)) && !(flags & BD_LAYOUT_FAT)) return BD_E_INVALID;
     if (flags & BD_LAYOUT_COMPACT) {
         if (flags & BD_LAYOUT_FAT) return BD_E_INVALID;
@@ -484,8 +526,22 @@ extern "C" int graph_load_csr(int64_t n, const int64_t* row_ptr, const int32_t* 
         delete g;
         return BD_E_HIP;
     }
+    if (g->kernel_layout == 7 && !(flags & BD_DIRECT_HUBS)) {
+        std::vector<uint32_t> runtab;
+        if (build_run_table(rp32, &g->run_h1, &runtab)) {
+            g->run_words = (uint32_t)runtab.size();
+            if (g->runtab.alloc(runtab.size() * 4) != BD_OK ||
+                hipMemcpyAsync(g->runtab.p, runtab.data(), runtab.size() * 4, hipMemcpyHostToDevice, st) !=
+                    hipSuccess ||
+                hipStreamSynchronize(st) != hipSuccess) {
+                delete g;
+                return BD_E_HIP;
+            }
+            g->kernel_layout = kLayoutHubRuns;
+        }
+    }
     g->device_bytes = (int64_t)(g->node.bytes + g->col.bytes + g->adj.bytes + g->rp32.bytes + g->col24.bytes +
-                                g->node8.bytes);
+                                g->node8.bytes + g->runtab.bytes);
     *out = g;
     return BD_OK;
 }
@@ -505,7 +561,10 @@ extern "C" int bd_graph_get_info(const bd_graph* g, bd_graph_info* info)
     info->bipartite = g->bipartite;
     info->layout = g->layout;
     info->nontemporal = g->kernel_layout == 6 ? 1 : 0;
-    info->lds_hubs = hub_layout(g->kernel_layout) ? (int32_t)std::min<int64_t>(hub_nodes(1024, g->kernel_layout), g->n) : 0;
+    info->lds_hubs = g->kernel_layout == kLayoutHubRuns ? (int32_t)g->n
+                     : hub_layout(g->kernel_layout)
+                         ? (int32_t)std::min<int64_t>(hub_nodes(1024, g->kernel_layout), g->n)
+                         : 0;
     info->device_bytes = g->device_bytes;
     return BD_OK;
 }
@@ -627,6 +686,9 @@ GraphTables tables(const bd_graph* g)
     t.rp = g->rp32.as<const uint32_t>();
     t.col24 = g->col24.as<const uint32_t>();
     t.node8 = g->node8.as<const uint2>();
+    t.runtab = g->runtab.as<const uint32_t>();
+    t.run_h1 = g->run_h1;
+    t.run_words = g->run_words;
     t.dom = g->dom;
     return t;
 }
@@ -687,8 +749,16 @@ ChunkPlan chunk_plan(const bd_exec& ex, const QueryDesc& d, int layout)
     uint32_t gc;
     if (ex.chunk_probes > 0) {
         gc = std::max<uint32_t>(1u, (uint32_t)ex.chunk_probes / grp.M);
-    } else {
+    } else if (ex.mode == BD_MODE_PLAIN) {
         gc = (uint32_t)std::max<uint64_t>(1, ((uint64_t)pairs + R - 1) / R);
+    } else {
+        // at most `pairs` lane slots per chunk, counted as the kernels lay the
+        // pairs out (probes with R >= kUniformMinR in blocks of 64 replicas, one
+        // wave block each; others a pair per lane), so that a chunk of one work
+        // group's pairs runs in one pass: rounding up would add a nearly empty
+        // second one
+        const uint64_t slots = R >= kUniformMinR ? ((uint64_t)R + 63) / 64 * 64 : R;
+        gc = (uint32_t)std::max<uint64_t>(1, (uint64_t)pairs / slots);
     }
     gc = std::min<uint32_t>(gc, (uint32_t)kMaxChunkProbes / grp.M);
     gc = std::min<uint32_t>(gc, std::max<uint32_t>(grp.n, 1));
@@ -1737,7 +1807,6 @@ struct Slice {
 };
 
 constexpr uint32_t kSliceMaxChunks = 1u << 18;
-constexpr int32_t kServerChunkPairs = 1024;
 
 }  // namespace
 
@@ -1774,18 +1843,32 @@ struct bd_server {
     // a lane's time per walk step (ms): a chunk needs about (L + 1) steps per
     // pass of the work group over its pairs, however few pairs it has
     double ms_per_lane_step = 1e-3;
+    // The last kRateWindow completed slices: walk steps, summed chunk costs,
+    // and the time from the later of the slice's launch and the previous
+    // completion to its own completion. Slices overlap (two are in flight, and
+    // one holding a few long chunks runs beside the next), so one slice's
+    // interval can be far shorter than its work took; but the intervals of
+    // consecutive slices tile the busy time, so the sums over the window give
+    // the device's rate.
+    static constexpr int kRateWindow = 8;
+    double win_steps[kRateWindow] = {}, win_cost[kRateWindow] = {}, win_ms[kRateWindow] = {};
+    int win_next = 0;
 };
 
 namespace {
 
-// How the server cuts queries into chunks: as the batched mode, with replica
-// parts of at most 1024 pairs so that no chunk holds a slice open for long.
+// How the server cuts queries into chunks: as the batched mode, with at most
+// one pass of a work group per chunk (its pairs fit the group's lanes). A
+// chunk takes about (L + 1) lane steps per pass, and under load a lane step
+// waits on a loaded memory system (several microseconds on the fat layout),
+// so a chunk of several passes would hold its slice, and every request that
+// arrives meanwhile, open for tens of milliseconds.
 bd_exec server_exec(const bd_server* S)
 {
     bd_exec ex{};
     ex.mode = BD_MODE_BATCHED;
     ex.chunk_probes = S->cfg.chunk_probes;
-    ex.chunk_pairs = kServerChunkPairs;
+    ex.chunk_pairs = group_pairs(S->g->kernel_layout, share_class(policy_share(S->pol)));
     return ex;
 }
 
@@ -2140,11 +2223,24 @@ void server_loop(bd_server* S)
                 const double tn = now_ms();
                 const double dt = tn - std::max(sl.t_launch, S->t_last_done);
                 S->t_last_done = tn;
-                if (dt > 0.5 && sl.steps > 0) S->steps_per_ms = 0.7 * S->steps_per_ms + 0.3 * (sl.steps / dt);
-                // resident work groups ran the slice's summed chunk costs in dt
-                if (dt > 0.5 && sl.sum_cost > 0)
-                    S->ms_per_lane_step = 0.7 * S->ms_per_lane_step +
-                                          0.3 * std::min(dt * (double)S->resident[0] / sl.sum_cost, 1e-2);
+                if (sl.steps > 0) {
+                    const int w = S->win_next;
+                    S->win_next = (w + 1) % bd_server::kRateWindow;
+                    S->win_steps[w] = (double)sl.steps;
+                    S->win_cost[w] = sl.sum_cost;
+                    S->win_ms[w] = std::max(dt, 0.0);
+                    double st = 0, sc = 0, sm = 0;
+                    for (int i = 0; i < bd_server::kRateWindow; ++i) {
+                        st += S->win_steps[i];
+                        sc += S->win_cost[i];
+                        sm += S->win_ms[i];
+                    }
+                    if (sm > 2.0) {
+                        S->steps_per_ms = st / sm;
+                        // resident work groups ran the summed chunk costs in that time
+                        if (sc > 0) S->ms_per_lane_step = std::min(sm * (double)S->resident[0] / sc, 1e-2);
+                    }
+                }
                 rc = process_completions(S, sl);
                 ++S->slices_done;
             }

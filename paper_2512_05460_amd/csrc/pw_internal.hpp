@@ -48,6 +48,8 @@ struct GraphTables {
     const uint32_t* rp;
     const uint32_t* col24;
     const uint2* node8;
+    const uint32_t* runtab;  // code 8: rp[0 .. run_h1], then the run records (run_words words)
+    uint32_t run_h1, run_words;
     DomainParams dom;
 };
 
@@ -96,7 +98,7 @@ constexpr uint32_t kMaxShare = 4;
 inline int share_class(uint32_t M) { return M <= 1 ? 1 : M <= 2 ? 2 : 4; }
 
 // Layout codes of the kernels (0-5 are the graph layouts bd_graph_get_info
-// reports; 6 and 7 are kernel variants of layouts 1 and 5), and the hub
+// reports; 6 is a kernel variant of layout 1, 7 and 8 of layout 5), and the hub
 // nodes they stage in LDS.
 constexpr int kLayoutCsr = 0, kLayoutFat = 1, kLayoutCompact = 2, kLayoutCompactHub = 3, kLayoutHub32 = 4,
               kLayoutHubId = 5;
@@ -110,9 +112,26 @@ constexpr int kLayoutFatNT = 6;
 // load chains per lane keep as many loads in flight at four waves per SIMD as
 // two chains at eight.
 constexpr int kLayoutHubIdX2 = 7;
-constexpr bool hubid_layout(int layout) { return layout == kLayoutHubId || layout == kLayoutHubIdX2; }
+// Layout 5's tables with the row offset and degree of every node resolved in
+// LDS, so that a walk step issues one global load (the neighbour id) instead
+// of two. Storage order is descending degree: the first h1 storage ids (the
+// high-degree nodes, whose degrees are nearly all distinct) keep their row
+// offsets; past h1 the degrees form runs of equal value at least kRunBlock
+// long, so each block of kRunBlock storage ids holds at most two runs and one
+// 8-byte record describes it: {row offset of its first node,
+// dA | dB << 12 | bnd << 24}, its nodes before bnd having degree dA and the
+// rest dB. The launch shape is code 7's; the results are layout 5's.
+constexpr int kLayoutHubRuns = 8;
+constexpr uint32_t kRunBlock = 64;
+constexpr uint32_t kRunMaxDeg = 0xFFFu;
+constexpr bool hubid_layout(int layout)
+{
+    return layout == kLayoutHubId || layout == kLayoutHubIdX2 || layout == kLayoutHubRuns;
+}
 // replica pairs a lane runs at once
-constexpr int lane_pairs(int layout) { return layout == kLayoutHubIdX2 ? 2 : 1; }
+constexpr int lane_pairs(int layout) { return layout == kLayoutHubIdX2 || layout == kLayoutHubRuns ? 2 : 1; }
+// first 32-bit word of the run records in the LDS copy of code 8 (8-byte aligned)
+constexpr uint32_t run_records_at(uint32_t h1) { return (h1 + 2u) & ~1u; }
 constexpr bool hub_layout(int layout)
 {
     return layout == kLayoutCompactHub || layout == kLayoutHub32 || hubid_layout(layout);
@@ -124,6 +143,8 @@ constexpr bool hub_layout(int layout)
 constexpr uint32_t hub_nodes(int threads, int layout)
 {
     if (layout == kLayoutHubIdX2 && threads >= 1024) return 36864u;  // 144 KB: what the CU's 160 KB leaves
+    // code 8: capacity in 32-bit words of row offsets and run records
+    if (layout == kLayoutHubRuns) return threads >= 1024 ? 36864u : 6143u;
     return (threads >= 1024 ? 8192u : 1024u) * (layout == kLayoutHubIdX2 ? 4u : layout == kLayoutHubId ? 2u : 1u);
 }
 // 32-bit words of the LDS hub copy (entries 0 .. hub_nodes, inclusive)
@@ -135,17 +156,18 @@ constexpr uint32_t hub_words(int threads, int layout)
 
 constexpr int kBlockThreads = 256;
 // Work-group size of the walk and gather kernels per layout code and walk
-// sharing class. With one probe per walk the hubs-first kernels (codes 3, 4, 5
-// and 7) run 1,024-thread work groups: codes 3 and 4 stage the node entries of
-// the 8,192 highest-degree nodes (64 KB), code 5 their 16,384 row offsets, two
-// groups per CU at 8 waves per SIMD; code 7 stages 36,864 offsets (144 KB) in
-// one group per CU at 4 waves per SIMD with two replica pairs per thread. On
-// the Chung-Lu n=1e5 graph the staged nodes take 42%, 54% and 73% of the walk
-// steps. The sharing kernels run 4-5 waves per SIMD, one such group per CU,
-// and keep 256-thread groups.
+// sharing class. With one probe per walk the hubs-first kernels (codes 3, 4, 5,
+// 7 and 8) run 1,024-thread work groups: codes 3 and 4 stage the node entries
+// of the 8,192 highest-degree nodes (64 KB), code 5 their 16,384 row offsets,
+// two groups per CU at 8 waves per SIMD; code 7 stages 36,864 offsets (144 KB)
+// in one group per CU at 4 waves per SIMD with two replica pairs per thread,
+// and code 8 the run table in the same shape. On the Chung-Lu n=1e5 graph the
+// nodes resolved in LDS take 42%, 54%, 73% and 100% of the walk steps. The
+// sharing kernels run 4-5 waves per SIMD, one such group per CU, and keep
+// 256-thread groups.
 constexpr int block_threads(int layout, int share) { return hub_layout(layout) && share <= 1 ? 1024 : kBlockThreads; }
 // (probe, replica) pairs one work group runs at once: a pair per thread, two
-// per thread in the kernel of layout code 7
+// per thread in the kernels of layout codes 7 and 8
 constexpr int group_pairs(int layout, int share)
 {
     return block_threads(layout, share) * (share <= 1 ? lane_pairs(layout) : 1);

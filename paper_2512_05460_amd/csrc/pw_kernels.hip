@@ -32,6 +32,10 @@ __device__ __forceinline__ DevGraph make_graph(const GraphTables& g)
     G.node8 = g.node8;
     G.hub = nullptr;
     G.hub4 = nullptr;
+    G.runrec = nullptr;
+    G.runtab = g.runtab;
+    G.run_h1 = g.run_h1;
+    G.run_words = g.run_words;
     G.nhub = 0;
     G.dom.n = g.dom.n;
     G.dom.rb = g.dom.rb;
@@ -300,7 +304,7 @@ __device__ void run_chunk(const WalkArgs& A, const DevGraph& G, uint32_t ci,
     // walk sharing: M probes per group, ceil(B/M) groups per block
     const uint32_t M = kShare == 1 ? 1u : d.share;
     const uint32_t gpb = (d.B + M - 1) / M;
-    constexpr bool kDual = kLayout == kLayoutHubIdX2 && kShare == 1;
+    constexpr bool kDual = lane_pairs(kLayout) == 2 && kShare == 1;
     if (kDual && kUniform) {
         // Two blocks of 64 replicas per wave pass: units u and u + nw, each of
         // one probe (wave-uniform keys). A lane whose replica lies past the
@@ -523,7 +527,7 @@ __device__ __forceinline__ bool abort_raised(const WalkArgs& A)
 // Eight waves per SIMD where the kernel fits 64 VGPRs without spilling.
 template <int kLayout, int kUniform, int kShare>
 __global__ __launch_bounds__(block_threads(kLayout, kShare),
-                             kShare == 1 && kLayout == kLayoutHubIdX2                                       ? 4
+                             kShare == 1 && lane_pairs(kLayout) == 2                                         ? 4
                              : kShare == 1 && (kUniform || kLayout == kLayoutCompact || hub_layout(kLayout)) ? 8
                                                                                                             : 1) void
 walk_kernel(WalkArgs A)
@@ -599,6 +603,7 @@ static const void* walk_fn(int layout, int uniform, int share)
     if (layout == kLayoutHub32) return walk_fn_l<kLayoutHub32>(uniform, share);
     if (layout == kLayoutHubId) return walk_fn_l<kLayoutHubId>(uniform, share);
     if (layout == kLayoutHubIdX2) return walk_fn_l<kLayoutHubIdX2>(uniform, share);
+    if (layout == kLayoutHubRuns) return walk_fn_l<kLayoutHubRuns>(uniform, share);
     return walk_fn_l<kLayoutCsr>(uniform, share);
 }
 
@@ -637,6 +642,9 @@ hipError_t launch_walk(const WalkArgs& a, int layout, int uniform, int share, ui
     } else if (layout == kLayoutHubIdX2) {
         if (uniform) launch_l<kLayoutHubIdX2, 1>(a, share, grid, st);
         else launch_l<kLayoutHubIdX2, 0>(a, share, grid, st);
+    } else if (layout == kLayoutHubRuns) {
+        if (uniform) launch_l<kLayoutHubRuns, 1>(a, share, grid, st);
+        else launch_l<kLayoutHubRuns, 0>(a, share, grid, st);
     } else {
         if (uniform) launch_l<kLayoutCsr, 1>(a, share, grid, st);
         else launch_l<kLayoutCsr, 0>(a, share, grid, st);
@@ -702,8 +710,13 @@ __global__ void trace_kernel(GraphTables gt, uint32_t count, const int32_t* star
                              int32_t* trace, float* acc_out)
 {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    DevGraph G = make_graph(gt);
+    if constexpr (kLayout == kLayoutHubRuns) {
+        // the run table in LDS, as the walk kernels read it
+        __shared__ __align__(16) uint32_t lds[hub_words(1024, kLayout)];
+        stage_hubs<kLayout>(G, lds, hub_nodes(1024, kLayout));
+    }
     if (i >= count) return;
-    const DevGraph G = make_graph(gt);
     const uint32_t x0 = (uint32_t)start[i];
     const Probe pr = make_probe(slo, shi, uid[i], kk[i], G.dom.n);
     WalkState w = start_at<kLayout>(G, x0);
@@ -737,6 +750,7 @@ hipError_t launch_trace(const GraphTables& g, int layout, uint32_t count, const 
     else if (layout == kLayoutHub32) PW_TRACE(4);
     else if (layout == kLayoutHubId) PW_TRACE(5);
     else if (layout == kLayoutHubIdX2) PW_TRACE(7);
+    else if (layout == kLayoutHubRuns) PW_TRACE(8);
     else PW_TRACE(0);
 #undef PW_TRACE
     return hipGetLastError();
@@ -831,6 +845,7 @@ hipError_t launch_gather(const GraphTables& g, int layout, int chains, uint32_t 
     else if (layout == kLayoutHub32) PW_GATHER_C(4);
     else if (layout == kLayoutHubId) PW_GATHER_C(5);
     else if (layout == kLayoutHubIdX2) PW_GATHER_C(7);
+    else if (layout == kLayoutHubRuns) PW_GATHER_C(8);
     else PW_GATHER_C(0);
 #undef PW_GATHER_C
 #undef PW_GATHER

@@ -7,9 +7,12 @@ caller's neighbour order with the ids renamed. On that graph the library's
 results must equal the oracle's bit for bit (Algorithm 1: probe values,
 walks, per-probe Q, block means, estimates, in every mode, with split probes
 and with walk sharing), and its walks, reported in caller ids, are the same
-walks as every other layout's. The same holds for both of its kernels: one
-work group per CU with two replica pairs per thread (the default) and two
-work groups per CU with one (BD_NARROW_HUBS).
+walks as every other layout's. The same holds for its three kernels: one
+work group per CU with two replica pairs per thread and every node's row
+offset and degree in LDS (the degree-run table, the default where it fits),
+the same with the row offsets of the 36,864 highest-degree nodes in LDS
+(BD_DIRECT_HUBS), and two work groups per CU with one pair per thread and
+16,384 offsets each (BD_NARROW_HUBS).
 """
 
 import numpy as np
@@ -38,19 +41,18 @@ def relabelled(g):
     return graphs.Csr(n=g.n, row_ptr=rp, col=col, name=g.name + "-storage"), order, internal
 
 
-@pytest.fixture(scope="module", params=[("ba1k", 0), ("cl100k", 0), ("ba1k", B.BD_NARROW_HUBS),
-                                        ("cl100k", B.BD_NARROW_HUBS)])
+@pytest.fixture(scope="module", params=[(key, kernel) for kernel in (0, B.BD_DIRECT_HUBS, B.BD_NARROW_HUBS)
+                                        for key in ("ba1k", "cl100k")])
 def pair(request):
-    # the default kernel (one work group per CU, 36,864 staged offsets, two
-    # replica pairs per thread) and BD_NARROW_HUBS (two work groups per CU,
-    # 16,384 offsets, one pair per thread)
-    key, narrow = request.param
+    key, kernel = request.param
     g = graphs.workload_graph(key)
     g5, order, internal = relabelled(g)
-    dg = B.graph_load_csr(g.n, g.row_ptr, g.col, FLAGS | narrow)
+    dg = B.graph_load_csr(g.n, g.row_ptr, g.col, FLAGS | kernel)
     info = dg.info()
     assert info["layout"] == 5
-    assert info["lds_hubs"] == min(g.n, 16384 if narrow else 36864)
+    # nodes resolved in LDS: all with the run table, else the staged offsets
+    assert info["lds_hubs"] == {0: g.n, B.BD_DIRECT_HUBS: min(g.n, 36864),
+                                B.BD_NARROW_HUBS: min(g.n, 16384)}[kernel]
     yield g, g5, order, internal, dg
     dg.free()
 
@@ -109,6 +111,21 @@ def test_walks_same_as_other_layouts_and_sums_match_oracle(pair):
                                  int(side[i]))
         assert np.array_equal(order[otr], tr[i])
         assert np.float32(acc[i]) == np.float32(oacc)
+
+
+def test_every_node_entry(pair):
+    # one short walk from every node: X_1 is read at row offset + floor(u d)
+    # of the start and X_2 likewise from X_1, so every node's row offset and
+    # degree as the kernel resolves it (the LDS run table by default) is
+    # checked against the plain row offsets of layout 3
+    g, g5, order, internal, dg = pair
+    starts = np.arange(g.n, dtype=np.int32)
+    z = np.zeros(g.n, dtype=np.int64)
+    tr, acc = B.bd_walk_trace(dg, starts, z + 5, z + 1, np.arange(g.n) % 11, np.arange(g.n) % 2, 2, SEED)
+    other = B.graph_load_csr(g.n, g.row_ptr, g.col, B.BD_LAYOUT_COMPACT | B.BD_RELABEL_DEGREE)
+    tr3, _ = B.bd_walk_trace(other, starts, z + 5, z + 1, np.arange(g.n) % 11, np.arange(g.n) % 2, 2, SEED)
+    other.free()
+    assert np.array_equal(tr, tr3)
 
 
 @pytest.mark.parametrize("M", [2, 4])
