@@ -190,9 +190,10 @@ struct DevGraph {
     const uint2* node8;     // n + 1 entries {row offset, original id} (compact layout, hubs first)
     const uint2* hub;       // LDS copy of node8[0 .. nhub] (nhub = 0: none)
     const uint32_t* hub4;   // LDS copy of rp[0 .. nhub] (probe on storage ids)
-    const uint2* runrec;    // code 8: LDS run records of the storage ids past nhub (null: none)
-    const uint32_t* runtab; // code 8: the table staged in LDS (global memory)
-    uint32_t run_h1, run_words;
+    const uint32_t* runtab; // code 8: the run table (global memory), staged in LDS as hub4
+    const float* inv;       // code 8: LDS table of 1.0f/d for d = 0 .. d_max
+    uint32_t run_h1, run_words, run_ninv;
+    uint32_t rec_word;      // code 8: word index of the run records in hub4
     uint32_t nhub;
     Domain dom;
 };
@@ -261,26 +262,20 @@ __device__ __forceinline__ void hubid_row(const DevGraph& G, uint32_t x, WalkSta
 // same values.
 __device__ __forceinline__ void runs_row(const DevGraph& G, uint32_t x, WalkState& w)
 {
-    uint32_t b, d;
-    if (x < G.nhub) {
-        b = G.hub4[x];
-        d = G.hub4[x + 1] - b;
-    } else if (G.runrec != nullptr) {
-        const uint32_t i = x - G.nhub;
-        const uint2 r = G.runrec[i / kRunBlock];
-        const uint32_t j = i % kRunBlock;
-        const uint32_t dA = r.y & kRunMaxDeg, dB = (r.y >> 12) & kRunMaxDeg, bnd = r.y >> 24;
-        const uint32_t ja = min(j, bnd);
-        b = r.x + ja * dA + (j - ja) * dB;
-        d = j < bnd ? dA : dB;
-    } else {
-        b = G.rp[x];
-        d = G.rp[x + 1] - b;
-    }
+    // one two-word LDS read at either x (direct offsets: rp[x], rp[x + 1]) or
+    // x's block record, both decoded and the right one selected
+    const bool direct = x < G.nhub;
+    const uint32_t i = x - G.nhub;
+    const uint32_t at = direct ? x : G.rec_word + 2u * (i / kRunBlock);
+    const uint32_t w0 = G.hub4[at], w1 = G.hub4[at + 1];
+    const uint32_t j = i % kRunBlock;
+    const uint32_t dA = w1 & kRunMaxDeg, dB = (w1 >> 12) & kRunMaxDeg, bnd = w1 >> 24;
+    const uint32_t ja = min(j, bnd);
+    const uint32_t d = direct ? w1 - w0 : (j < bnd ? dA : dB);
     w.x = x;
-    w.off = b;
+    w.off = direct ? w0 : w0 + ja * dA + (j - ja) * dB;
     w.deg = d;
-    w.inv = __fdiv_rn(1.0f, (float)d);
+    w.inv = G.inv[d];
 }
 
 // Walk state at internal id x (the start of a walk).
@@ -364,16 +359,20 @@ __device__ __forceinline__ void stage_hubs(DevGraph& G, uint32_t* lds, uint32_t 
         G.hub = l2;
         G.nhub = nh;
     } else if constexpr (kLayout == kLayoutHubRuns) {
-        // the whole run table when it fits, else the first row offsets only
-        // (the other nodes then read the global row offsets)
-        const bool all = G.run_words <= capacity + 1u;
-        const uint32_t nh = all ? G.run_h1 : min(capacity, G.run_h1);
-        const uint32_t words = all ? G.run_words : nh + 1u;
+        // the run table, then 1.0f/d for every degree 0 .. d_max (the same
+        // correctly rounded quotients a step would compute); the host takes
+        // this layout only where both fit `capacity` + 1 words
+        const uint32_t words = G.run_words;
+        const uint32_t inv_at = (words + 3u) & ~3u;
         for (uint32_t i = threadIdx.x; i < words; i += blockDim.x) lds[i] = G.runtab[i];
+        for (uint32_t i = threadIdx.x; i < G.run_ninv; i += blockDim.x)
+            lds[inv_at + i] = __float_as_uint(__fdiv_rn(1.0f, (float)max(i, 1u)));
         __syncthreads();
         G.hub4 = lds;
-        G.nhub = nh;
-        G.runrec = all ? reinterpret_cast<const uint2*>(lds + run_records_at(nh)) : nullptr;
+        G.nhub = G.run_h1;
+        G.rec_word = run_records_at(G.run_h1);
+        G.inv = reinterpret_cast<const float*>(lds + inv_at);
+        (void)capacity;
     } else if constexpr (hubid_layout(kLayout)) {
         const uint32_t nh = min(capacity, G.dom.n);
         for (uint32_t i = threadIdx.x; i <= nh; i += blockDim.x) lds[i] = G.rp[i];

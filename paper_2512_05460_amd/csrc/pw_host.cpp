@@ -161,7 +161,7 @@ struct bd_graph {
     std::vector<uint32_t> internal;  // caller id -> storage id (empty: identity)
     std::vector<uint32_t> external;  // storage id -> caller id where walks see storage ids (layout 5)
     DevBuf node, col, adj, rp32, col24, node8, runtab;
-    uint32_t run_h1 = 0, run_words = 0;  // code 8: direct row offsets, words of runtab
+    uint32_t run_h1 = 0, run_words = 0, run_ninv = 0;  // code 8: direct row offsets, words of runtab, d_max + 1
     DomainParams dom{};
     int64_t device_bytes = 0;
     std::mutex mu;  // serialises calls that use the per-graph work buffers
@@ -192,9 +192,10 @@ DomainParams make_domain(uint32_t n)
 // equal degree that is shorter than kRunBlock or whose degree exceeds
 // kRunMaxDeg, so each block of kRunBlock storage ids past it holds at most two
 // runs. The table is rp[0..h1], padding to an even word, then per block
-// {rp of its first node, dA | dB << 12 | bnd << 24}. False if it would not fit
-// the LDS of the walk kernels.
-bool build_run_table(const std::vector<uint32_t>& rp, uint32_t* h1_out, std::vector<uint32_t>* out)
+// {rp of its first node, dA | dB << 12 | bnd << 24}. False if it and the
+// ninv reciprocals the kernels place after it (from a 4-word boundary) would
+// not fit their LDS.
+bool build_run_table(const std::vector<uint32_t>& rp, uint32_t ninv, uint32_t* h1_out, std::vector<uint32_t>* out)
 {
     const size_t n = rp.size() - 1;
     auto deg = [&](size_t i) { return rp[i + 1] - rp[i]; };
@@ -208,7 +209,7 @@ bool build_run_table(const std::vector<uint32_t>& rp, uint32_t* h1_out, std::vec
     const size_t blocks = (n - h1 + kRunBlock - 1) / kRunBlock;
     const size_t at = run_records_at((uint32_t)h1);
     const size_t words = at + 2 * blocks;
-    if (words > hub_words(1024, kLayoutHubRuns)) return false;
+    if (((words + 3) & ~(size_t)3) + ninv > hub_words(1024, kLayoutHubRuns)) return false;
     out->assign(words, 0u);
     for (size_t i = 0; i <= h1; ++i) (*out)[i] = rp[i];
     for (size_t b = 0; b < blocks; ++b) {
@@ -528,8 +529,9 @@ extern "C" int graph_load_csr(int64_t n, const int64_t* row_ptr, const int32_t* 
     }
     if (g->kernel_layout == 7 && !(flags & BD_DIRECT_HUBS)) {
         std::vector<uint32_t> runtab;
-        if (build_run_table(rp32, &g->run_h1, &runtab)) {
+        if (build_run_table(rp32, (uint32_t)dmax + 1u, &g->run_h1, &runtab)) {
             g->run_words = (uint32_t)runtab.size();
+            g->run_ninv = (uint32_t)dmax + 1u;
             if (g->runtab.alloc(runtab.size() * 4) != BD_OK ||
                 hipMemcpyAsync(g->runtab.p, runtab.data(), runtab.size() * 4, hipMemcpyHostToDevice, st) !=
                     hipSuccess ||
@@ -689,6 +691,7 @@ GraphTables tables(const bd_graph* g)
     t.runtab = g->runtab.as<const uint32_t>();
     t.run_h1 = g->run_h1;
     t.run_words = g->run_words;
+    t.run_ninv = g->run_ninv;
     t.dom = g->dom;
     return t;
 }

@@ -49,7 +49,7 @@ struct GraphTables {
     const uint32_t* col24;
     const uint2* node8;
     const uint32_t* runtab;  // code 8: rp[0 .. run_h1], then the run records (run_words words)
-    uint32_t run_h1, run_words;
+    uint32_t run_h1, run_words, run_ninv;  // run_ninv: d_max + 1 reciprocals
     DomainParams dom;
 };
 
@@ -120,10 +120,14 @@ constexpr int kLayoutHubIdX2 = 7;
 // long, so each block of kRunBlock storage ids holds at most two runs and one
 // 8-byte record describes it: {row offset of its first node,
 // dA | dB << 12 | bnd << 24}, its nodes before bnd having degree dA and the
-// rest dB. The launch shape is code 7's; the results are layout 5's.
+// rest dB. After the table the LDS holds 1.0f/d for d = 0 .. d_max, so a step
+// reads the reciprocal instead of dividing. The launch shape is code 7's; the
+// results are layout 5's. Walk sharing runs code 7's kernels on these tables.
 constexpr int kLayoutHubRuns = 8;
 constexpr uint32_t kRunBlock = 64;
 constexpr uint32_t kRunMaxDeg = 0xFFFu;
+// the kernel that runs a layout code with a walk-sharing class
+constexpr int walk_layout(int layout, int share) { return layout == kLayoutHubRuns && share > 1 ? 7 : layout; }
 constexpr bool hubid_layout(int layout)
 {
     return layout == kLayoutHubId || layout == kLayoutHubIdX2 || layout == kLayoutHubRuns;
@@ -143,8 +147,9 @@ constexpr bool hub_layout(int layout)
 constexpr uint32_t hub_nodes(int threads, int layout)
 {
     if (layout == kLayoutHubIdX2 && threads >= 1024) return 36864u;  // 144 KB: what the CU's 160 KB leaves
-    // code 8: capacity in 32-bit words of row offsets and run records
-    if (layout == kLayoutHubRuns) return threads >= 1024 ? 36864u : 6143u;
+    // code 8 (1,024-thread groups only): capacity in 32-bit words of the run
+    // table and the reciprocals
+    if (layout == kLayoutHubRuns) return 36864u;
     return (threads >= 1024 ? 8192u : 1024u) * (layout == kLayoutHubIdX2 ? 4u : layout == kLayoutHubId ? 2u : 1u);
 }
 // 32-bit words of the LDS hub copy (entries 0 .. hub_nodes, inclusive)

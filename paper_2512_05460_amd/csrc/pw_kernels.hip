@@ -32,10 +32,12 @@ __device__ __forceinline__ DevGraph make_graph(const GraphTables& g)
     G.node8 = g.node8;
     G.hub = nullptr;
     G.hub4 = nullptr;
-    G.runrec = nullptr;
+    G.inv = nullptr;
+    G.rec_word = 0;
     G.runtab = g.runtab;
     G.run_h1 = g.run_h1;
     G.run_words = g.run_words;
+    G.run_ninv = g.run_ninv;
     G.nhub = 0;
     G.dom.n = g.dom.n;
     G.dom.rb = g.dom.rb;
@@ -589,13 +591,18 @@ walk_kernel(WalkArgs A)
 template <int kLayout>
 static const void* walk_fn_l(int uniform, int share)
 {
-    if (share == 4) return uniform ? (const void*)walk_kernel<kLayout, 1, 4> : (const void*)walk_kernel<kLayout, 0, 4>;
-    if (share == 2) return uniform ? (const void*)walk_kernel<kLayout, 1, 2> : (const void*)walk_kernel<kLayout, 0, 2>;
+    if constexpr (kLayout != kLayoutHubRuns) {  // code 8 has no sharing kernels (walk_layout)
+        if (share == 4)
+            return uniform ? (const void*)walk_kernel<kLayout, 1, 4> : (const void*)walk_kernel<kLayout, 0, 4>;
+        if (share == 2)
+            return uniform ? (const void*)walk_kernel<kLayout, 1, 2> : (const void*)walk_kernel<kLayout, 0, 2>;
+    }
     return uniform ? (const void*)walk_kernel<kLayout, 1, 1> : (const void*)walk_kernel<kLayout, 0, 1>;
 }
 
 static const void* walk_fn(int layout, int uniform, int share)
 {
+    layout = walk_layout(layout, share);
     if (layout == kLayoutFat) return walk_fn_l<kLayoutFat>(uniform, share);
     if (layout == kLayoutFatNT) return walk_fn_l<kLayoutFatNT>(uniform, share);
     if (layout == kLayoutCompact) return walk_fn_l<kLayoutCompact>(uniform, share);
@@ -610,17 +617,26 @@ static const void* walk_fn(int layout, int uniform, int share)
 template <int kLayout, int kUniform>
 static void launch_l(const WalkArgs& a, int share, uint32_t grid, hipStream_t st)
 {
-    if (share == 4)
-        hipLaunchKernelGGL((walk_kernel<kLayout, kUniform, 4>), dim3(grid), dim3(block_threads(kLayout, 4)), 0, st, a);
-    else if (share == 2)
-        hipLaunchKernelGGL((walk_kernel<kLayout, kUniform, 2>), dim3(grid), dim3(block_threads(kLayout, 2)), 0, st, a);
-    else
+    if constexpr (kLayout == kLayoutHubRuns) {  // no sharing kernels (walk_layout)
+        (void)share;
         hipLaunchKernelGGL((walk_kernel<kLayout, kUniform, 1>), dim3(grid), dim3(block_threads(kLayout, 1)), 0, st, a);
+    } else {
+        if (share == 4)
+            hipLaunchKernelGGL((walk_kernel<kLayout, kUniform, 4>), dim3(grid), dim3(block_threads(kLayout, 4)), 0, st,
+                               a);
+        else if (share == 2)
+            hipLaunchKernelGGL((walk_kernel<kLayout, kUniform, 2>), dim3(grid), dim3(block_threads(kLayout, 2)), 0, st,
+                               a);
+        else
+            hipLaunchKernelGGL((walk_kernel<kLayout, kUniform, 1>), dim3(grid), dim3(block_threads(kLayout, 1)), 0, st,
+                               a);
+    }
 }
 
 hipError_t launch_walk(const WalkArgs& a, int layout, int uniform, int share, uint32_t grid, hipStream_t st)
 {
     if (grid == 0) return hipSuccess;
+    layout = walk_layout(layout, share);
     if (layout == kLayoutFat) {
         if (uniform) launch_l<kLayoutFat, 1>(a, share, grid, st);
         else launch_l<kLayoutFat, 0>(a, share, grid, st);
@@ -656,7 +672,7 @@ int walk_occupancy(int layout, int uniform, int share, int* wgs_per_cu)
 {
     int nb = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, walk_fn(layout, uniform, share),
-                                                     block_threads(layout, share), 0) !=
+                                                     block_threads(walk_layout(layout, share), share), 0) !=
         hipSuccess)
         return -1;
     *wgs_per_cu = nb;
