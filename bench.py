@@ -211,20 +211,24 @@ def small_queries(B, torch, stream):
     return out
 
 
-def grid_batched(B, torch, stream, plain_sample=512):
+def grid_batched(B, torch, stream, plain_sample=512, layout="hubsid"):
     """Mixed eps and L in one persistent launch: the 1,414 x 1,414 grid (5% of
     edges removed), 65,536 queries, eps over {0.02, 0.05, 0.1}, L over {500,
-    2000, 5000}, throughput walk counts; tables in the layout the library
-    picks (fat at this size); chunking from the autotuner, the launches
-    captured into a hipGraph and run from it. The plain mode (one query per
-    launch) runs the first `plain_sample` queries of the same set."""
+    2000, 5000}, throughput walk counts; tables hubs first with the probe on
+    storage ids (every node's entry from the degree-run table in LDS), or with
+    layout="auto" the library's choice (fat at this size); chunking from the
+    autotuner, the launches captured into a hipGraph and run from it. The
+    plain mode (one query per launch) runs the first `plain_sample` queries
+    of the same set on the same tables."""
     from paper_2512_05460_amd.budgets import BUDGETS, budget_policy
     from synth import graphs, queries
 
     g = graphs.workload_graph("grid1414")
     s, t, eps, Ls = queries.workload_batch("grid1414", g.n)
     nq = s.size
-    dg = B.graph_load_csr(g.n, g.row_ptr, g.col, B.BD_LAYOUT_AUTO)
+    flags = {"auto": B.BD_LAYOUT_AUTO,
+             "hubsid": B.BD_LAYOUT_COMPACT | B.BD_RELABEL_DEGREE | B.BD_PROBE_STORAGE_IDS}[layout]
+    dg = B.graph_load_csr(g.n, g.row_ptr, g.col, flags)
     info = dg.info()
     pol = budget_policy("grid1414")
     seed = graphs.PHILOX_SEED
@@ -262,7 +266,7 @@ def grid_batched(B, torch, stream, plain_sample=512):
     return {
         "workload": ("1,414 x 1,414 grid, 5% of edges removed, connected (bipartite); 65,536 uniform pairs, "
                      "eps over {0.02, 0.05, 0.1}, L over {500, 2000, 5000}"),
-        "layout": LAYOUT_NAMES[info["layout"]], "device_bytes": info["device_bytes"],
+        "layout": LAYOUT_NAMES[info["layout"]], "lds_nodes": info["lds_hubs"], "device_bytes": info["device_bytes"],
         "policy": {"kind": "scaled", "c_B": c_B, "c_R": c_R, "calibration": how},
         "R_range": [int(plan["R"].min()), int(plan["R"].max())],
         "walk_steps": steps,
@@ -680,6 +684,9 @@ def main():
     ap.add_argument("--no-roofline", action="store_true")
     ap.add_argument("--no-small", action="store_true")
     ap.add_argument("--no-grid", action="store_true")
+    ap.add_argument("--grid-layout", choices=["auto", "hubsid"], default="hubsid",
+                    help="grid tables: hubs first with the probe on storage ids (the degree-run table in LDS; "
+                         "the default), or the library's choice (fat at this size)")
     ap.add_argument("--no-sharing", action="store_true")
     ap.add_argument("--no-stabilize", action="store_true")
     ap.add_argument("--scale-layouts", default="csr,hubs,auto",
@@ -836,7 +843,7 @@ def main():
     if not args.no_small:
         extra["small_queries"] = small_queries(B, torch, stream)
     if not args.no_grid:
-        extra["grid_batched"] = grid_batched(B, torch, stream)
+        extra["grid_batched"] = grid_batched(B, torch, stream, layout=args.grid_layout)
     if not args.no_served_cl10m:
         extra["served_cl10m"] = served_cl10m(B, torch)
     if not args.no_scale_cl40m and not args.scale:

@@ -121,11 +121,13 @@ typedef struct bd_graph bd_graph;
                                    the degree-run table fits. Without it (and without
                                    BD_NARROW_HUBS) the walks resolve every node in LDS when
                                    they can: the offsets of the first h1 storage ids, past
-                                   which every run of equal degree is at least 64 long and
-                                   at most 4,095, then one 8-byte record per 64 storage ids
-                                   (layout code 8), if those take at most 144 KB (on the
-                                   Chung-Lu n=1e5 graph h1 = 1,934 and 20 KB); a walk step
-                                   then makes one global load instead of two. Same results */
+                                   which every run of equal degree is at least a block long
+                                   and of degree at most 2,047, then one 8-byte record per
+                                   block (64 to 512 storage ids, the smallest that fits)
+                                   and 1/d for every degree (layout code 8), if those take
+                                   at most 144 KB (on the Chung-Lu n=1e5 graph h1 = 1,934
+                                   and 24 KB); a walk step then makes one global load
+                                   instead of two. Same results */
 #define BD_DEVICE_PTRS     64u  /* row_ptr and col_idx are device pointers on the current
                                    device (e.g. the data of PyTorch tensors) instead of host
                                    arrays; they are read once, on `stream`, and not kept.
@@ -250,7 +252,9 @@ typedef struct {
                                 are reused; the graph is rebuilt when the batch shape changes) */
     int32_t  chunk_pairs;    /* (probe, replica) pairs per chunk, also the replica-part size of
                                 a split probe (BATCHED); 0 = one per work-group thread (PLAIN:
-                                256, or 1024 on the hubs-first layouts) / 4096 (BATCHED) */
+                                256, or 2048 on the hubs-first layouts with two pairs per
+                                thread, but at most the probes that give each compute unit a
+                                chunk) / 4096 (BATCHED) */
     int32_t  queues;         /* BATCHED: chunk queues of the persistent launch, 1..8. A query's
                                 chunks stay in one queue and a work group takes chunks from the
                                 queue of the XCD it runs on before the others, so they share

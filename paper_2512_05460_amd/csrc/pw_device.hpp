@@ -192,7 +192,7 @@ struct DevGraph {
     const uint32_t* hub4;   // LDS copy of rp[0 .. nhub] (probe on storage ids)
     const uint32_t* runtab; // code 8: the run table (global memory), staged in LDS as hub4
     const float* inv;       // code 8: LDS table of 1.0f/d for d = 0 .. d_max
-    uint32_t run_h1, run_words, run_ninv;
+    uint32_t run_h1, run_words, run_ninv, run_shift;
     uint32_t rec_word;      // code 8: word index of the run records in hub4
     uint32_t nhub;
     Domain dom;
@@ -256,7 +256,7 @@ __device__ __forceinline__ void hubid_row(const DevGraph& G, uint32_t x, WalkSta
 }
 
 // Node x with every node resolved from LDS (code 8): the row offsets of the
-// first nhub storage ids, then one record per block of kRunBlock storage ids
+// first nhub storage ids, then one record per block of 2^run_shift storage ids
 // past them (the layout is described with kLayoutHubRuns). Without the
 // records (a kernel that did not stage them) the global row offsets give the
 // same values.
@@ -266,10 +266,10 @@ __device__ __forceinline__ void runs_row(const DevGraph& G, uint32_t x, WalkStat
     // x's block record, both decoded and the right one selected
     const bool direct = x < G.nhub;
     const uint32_t i = x - G.nhub;
-    const uint32_t at = direct ? x : G.rec_word + 2u * (i / kRunBlock);
+    const uint32_t at = direct ? x : G.rec_word + 2u * (i >> G.run_shift);
     const uint32_t w0 = G.hub4[at], w1 = G.hub4[at + 1];
-    const uint32_t j = i % kRunBlock;
-    const uint32_t dA = w1 & kRunMaxDeg, dB = (w1 >> 12) & kRunMaxDeg, bnd = w1 >> 24;
+    const uint32_t j = i & ((1u << G.run_shift) - 1u);
+    const uint32_t dA = w1 & kRunMaxDeg, dB = (w1 >> 11) & kRunMaxDeg, bnd = w1 >> 22;
     const uint32_t ja = min(j, bnd);
     const uint32_t d = direct ? w1 - w0 : (j < bnd ? dA : dB);
     w.x = x;

@@ -157,11 +157,13 @@ struct bd_graph {
     int32_t kernel_layout = 0;  // the kernels' layout code: layout, 6 for fat with non-temporal
                                 // loads, 7 or 8 for layout 5 (kLayout* of the kernels)
     int device = 0;
+    uint32_t cus = 0;                // compute units of the device
     std::vector<int32_t> deg;        // host copy for the planner, by caller id
     std::vector<uint32_t> internal;  // caller id -> storage id (empty: identity)
     std::vector<uint32_t> external;  // storage id -> caller id where walks see storage ids (layout 5)
     DevBuf node, col, adj, rp32, col24, node8, runtab;
     uint32_t run_h1 = 0, run_words = 0, run_ninv = 0;  // code 8: direct row offsets, words of runtab, d_max + 1
+    uint32_t run_shift = 0;                            // code 8: log2 of the storage ids per record
     DomainParams dom{};
     int64_t device_bytes = 0;
     std::mutex mu;  // serialises calls that use the per-graph work buffers
@@ -188,32 +190,33 @@ DomainParams make_domain(uint32_t n)
 }
 
 // The degree-run table of kernel code 8 from the row offsets rp[0..n] of a
-// graph stored in descending-degree order: h1 is the end of the last run of
-// equal degree that is shorter than kRunBlock or whose degree exceeds
-// kRunMaxDeg, so each block of kRunBlock storage ids past it holds at most two
+// graph stored in descending-degree order, for blocks of 2^shift storage ids:
+// h1 is the end of the last run of equal degree that is shorter than a block
+// or whose degree exceeds kRunMaxDeg, so each block past it holds at most two
 // runs. The table is rp[0..h1], padding to an even word, then per block
-// {rp of its first node, dA | dB << 12 | bnd << 24}. False if it and the
+// {rp of its first node, dA | dB << 11 | bnd << 22}. False if it and the
 // ninv reciprocals the kernels place after it (from a 4-word boundary) would
 // not fit their LDS.
-bool build_run_table(const std::vector<uint32_t>& rp, uint32_t ninv, uint32_t* h1_out, std::vector<uint32_t>* out)
+bool build_run_table(const std::vector<uint32_t>& rp, uint32_t shift, uint32_t ninv, uint32_t* h1_out,
+                     std::vector<uint32_t>* out)
 {
-    const size_t n = rp.size() - 1;
+    const size_t n = rp.size() - 1, block = size_t(1) << shift;
     auto deg = [&](size_t i) { return rp[i + 1] - rp[i]; };
     size_t h1 = 0;
     for (size_t i = 0; i < n;) {
         size_t j = i + 1;
         while (j < n && deg(j) == deg(i)) ++j;
-        if (j - i < kRunBlock || deg(i) > kRunMaxDeg) h1 = j;
+        if (j - i < block || deg(i) > kRunMaxDeg) h1 = j;
         i = j;
     }
-    const size_t blocks = (n - h1 + kRunBlock - 1) / kRunBlock;
+    const size_t blocks = (n - h1 + block - 1) / block;
     const size_t at = run_records_at((uint32_t)h1);
     const size_t words = at + 2 * blocks;
     if (((words + 3) & ~(size_t)3) + ninv > hub_words(1024, kLayoutHubRuns)) return false;
     out->assign(words, 0u);
     for (size_t i = 0; i <= h1; ++i) (*out)[i] = rp[i];
     for (size_t b = 0; b < blocks; ++b) {
-        const size_t f = h1 + b * kRunBlock, len = std::min<size_t>(kRunBlock, n - f);
+        const size_t f = h1 + b * block, len = std::min<size_t>(block, n - f);
         const uint32_t dA = deg(f);
         size_t bnd = 0;
         while (bnd < len && deg(f + bnd) == dA) ++bnd;
@@ -221,7 +224,7 @@ bool build_run_table(const std::vector<uint32_t>& rp, uint32_t ninv, uint32_t* h
         for (size_t k = bnd; k < len; ++k)
             if (deg(f + k) != dB) return false;  // three runs in one block: cannot happen past h1
         (*out)[at + 2 * b] = rp[f];
-        (*out)[at + 2 * b + 1] = dA | (dB << 12) | ((uint32_t)bnd << 24);
+        (*out)[at + 2 * b + 1] = dA | (dB << 11) | ((uint32_t)bnd << 22);
     }
     *h1_out = (uint32_t)h1;
     return true;
@@ -404,6 +407,11 @@ extern "C" int graph_load_csr(int64_t n, const int64_t* row_ptr, const int32_t* 
         if (nt) g->kernel_layout = 6;
     }
     g->device = dev;
+    {
+        int cu = 0;
+        if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cu = 256;
+        g->cus = (uint32_t)std::max(cu, 1);
+    }
     g->dom = make_domain((uint32_t)n);
     g->deg.resize((size_t)n);
     for (int64_t v = 0; v < n; ++v) g->deg[(size_t)v] = (int32_t)(row_ptr[v + 1] - row_ptr[v]);
@@ -529,9 +537,14 @@ extern "C" int graph_load_csr(int64_t n, const int64_t* row_ptr, const int32_t* 
     }
     if (g->kernel_layout == 7 && !(flags & BD_DIRECT_HUBS)) {
         std::vector<uint32_t> runtab;
-        if (build_run_table(rp32, (uint32_t)dmax + 1u, &g->run_h1, &runtab)) {
+        // the smallest block that fits: smaller blocks let shorter runs in
+        uint32_t shift = kRunShiftMin;
+        while (shift <= kRunShiftMax && !build_run_table(rp32, shift, (uint32_t)dmax + 1u, &g->run_h1, &runtab))
+            ++shift;
+        if (shift <= kRunShiftMax) {
             g->run_words = (uint32_t)runtab.size();
             g->run_ninv = (uint32_t)dmax + 1u;
+            g->run_shift = shift;
             if (g->runtab.alloc(runtab.size() * 4) != BD_OK ||
                 hipMemcpyAsync(g->runtab.p, runtab.data(), runtab.size() * 4, hipMemcpyHostToDevice, st) !=
                     hipSuccess ||
@@ -692,6 +705,7 @@ GraphTables tables(const bd_graph* g)
     t.run_h1 = g->run_h1;
     t.run_words = g->run_words;
     t.run_ninv = g->run_ninv;
+    t.run_shift = g->run_shift;
     t.dom = g->dom;
     return t;
 }
@@ -707,7 +721,8 @@ int resident_wgs(const bd_graph* g, int uniform, int share = 1)
 
 // How the probes of one query are cut into work-group chunks.
 //   plain:   one chunk holds whole probes (all R replicas), at least one pair
-//            per thread of the layout's work group (256, or 1,024 hubs first);
+//            per thread of the layout's work group (256, or 1,024 hubs first),
+//            but no more probes than give every compute unit a chunk;
 //   batched / served: whole probes up to kSplitReplicas pairs per chunk, and a
 //   probe with R > kSplitReplicas is cut into replica parts (multiples of 64)
 //   so that no chunk runs much longer than the others.
@@ -735,7 +750,7 @@ struct Groups {
     uint32_t size(uint32_t gi) const { return std::min(M, B - (gi % per_block) * M); }
 };
 
-ChunkPlan chunk_plan(const bd_exec& ex, const QueryDesc& d, int layout)
+ChunkPlan chunk_plan(const bd_exec& ex, const QueryDesc& d, int layout, uint32_t spread = 0)
 {
     ChunkPlan cp;
     const Groups grp(d);
@@ -754,6 +769,10 @@ ChunkPlan chunk_plan(const bd_exec& ex, const QueryDesc& d, int layout)
         gc = std::max<uint32_t>(1u, (uint32_t)ex.chunk_probes / grp.M);
     } else if (ex.mode == BD_MODE_PLAIN) {
         gc = (uint32_t)std::max<uint64_t>(1, ((uint64_t)pairs + R - 1) / R);
+        // a query too small to give each of `spread` compute units a chunk is
+        // spread over more of them: its launch is bound by the walks' step
+        // latency, and compute units left idle are lost to it
+        if (spread > 0) gc = std::min<uint32_t>(gc, std::max<uint32_t>(1u, (grp.n + spread - 1) / spread));
     } else {
         // at most `pairs` lane slots per chunk, counted as the kernels lay the
         // pairs out (probes with R >= kUniformMinR in blocks of 64 replicas, one
@@ -776,8 +795,8 @@ struct ChunkCursor {
     ChunkPlan plan;
     uint32_t next_g = 0, next_p = 0;
     ChunkCursor() = default;
-    ChunkCursor(uint32_t q_, const QueryDesc& d, const bd_exec& ex, int layout)
-        : q(q_), R(d.R), grp(d), plan(chunk_plan(ex, d, layout))
+    ChunkCursor(uint32_t q_, const QueryDesc& d, const bd_exec& ex, int layout, uint32_t spread = 0)
+        : q(q_), R(d.R), grp(d), plan(chunk_plan(ex, d, layout, spread))
     {
     }
     bool done() const { return next_g >= grp.n; }
@@ -1154,7 +1173,7 @@ void build_batch(const bd_graph* g, int64_t nq, const int32_t* s, const int32_t*
     b.chunk_begin.assign(b.qd.size(), 0);
     auto emit = [&](size_t q) {
         QueryDesc& d = b.qd[q];
-        ChunkCursor cur((uint32_t)q, d, ex, g->kernel_layout);
+        ChunkCursor cur((uint32_t)q, d, ex, g->kernel_layout, ex.mode == BD_MODE_PLAIN ? g->cus : 0u);
         if (cur.plan.part) {
             d.psum_base = b.split_probes;
             b.split_probes += d.K;

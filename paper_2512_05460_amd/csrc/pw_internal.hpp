@@ -50,6 +50,7 @@ struct GraphTables {
     const uint2* node8;
     const uint32_t* runtab;  // code 8: rp[0 .. run_h1], then the run records (run_words words)
     uint32_t run_h1, run_words, run_ninv;  // run_ninv: d_max + 1 reciprocals
+    uint32_t run_shift;                    // log2 of the storage ids per run record
     DomainParams dom;
 };
 
@@ -116,16 +117,17 @@ constexpr int kLayoutHubIdX2 = 7;
 // LDS, so that a walk step issues one global load (the neighbour id) instead
 // of two. Storage order is descending degree: the first h1 storage ids (the
 // high-degree nodes, whose degrees are nearly all distinct) keep their row
-// offsets; past h1 the degrees form runs of equal value at least kRunBlock
-// long, so each block of kRunBlock storage ids holds at most two runs and one
+// offsets; past h1 the degrees form runs of equal value at least as long as
+// a block (2^shift storage ids, shift from kRunShiftMin to kRunShiftMax: the
+// smallest whose table fits), so each block holds at most two runs and one
 // 8-byte record describes it: {row offset of its first node,
-// dA | dB << 12 | bnd << 24}, its nodes before bnd having degree dA and the
+// dA | dB << 11 | bnd << 22}, its nodes before bnd having degree dA and the
 // rest dB. After the table the LDS holds 1.0f/d for d = 0 .. d_max, so a step
 // reads the reciprocal instead of dividing. The launch shape is code 7's; the
 // results are layout 5's. Walk sharing runs code 7's kernels on these tables.
 constexpr int kLayoutHubRuns = 8;
-constexpr uint32_t kRunBlock = 64;
-constexpr uint32_t kRunMaxDeg = 0xFFFu;
+constexpr uint32_t kRunShiftMin = 6, kRunShiftMax = 9;
+constexpr uint32_t kRunMaxDeg = 0x7FFu;
 // the kernel that runs a layout code with a walk-sharing class
 constexpr int walk_layout(int layout, int share) { return layout == kLayoutHubRuns && share > 1 ? 7 : layout; }
 constexpr bool hubid_layout(int layout)

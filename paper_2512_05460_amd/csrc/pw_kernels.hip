@@ -38,6 +38,7 @@ __device__ __forceinline__ DevGraph make_graph(const GraphTables& g)
     G.run_h1 = g.run_h1;
     G.run_words = g.run_words;
     G.run_ninv = g.run_ninv;
+    G.run_shift = g.run_shift;
     G.nhub = 0;
     G.dom.n = g.dom.n;
     G.dom.rb = g.dom.rb;
