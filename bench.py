@@ -490,11 +490,12 @@ def scale_cl40m_default(B, torch, stream, pairs=32, thr_queries=65536):
     err = np.abs(r["beta"] - ref["beta_cg"][:pairs]) / ref["beta_cg"][:pairs]
     steps = r["walk_steps"].astype(float)
     sps = steps.sum() / dt
-    # the L = 10000 half priced at the same policy shape: the calibrated c_R scaled
-    # by the growth of the walk variance (about L) over Algorithm 1's (L+1)^2
+    # the L = 10000 half at its own calibrated walk counts, priced by the
+    # planner (a query takes ~1.7e12 walk steps, ~30 s of the GPU: run by the
+    # calibration tool, not here)
     c_B, c_R, how = BUDGETS["cl40m@1000"]
-    pol10 = B.policy("scaled", c_B=c_B, c_R=c_R * 10.0 * (1001.0 / 10001.0) ** 2)
-    p10 = B.bd_plan(dg, s, t, 0.05, 10000, pol10)["walk_steps"].astype(float)
+    c_B10, c_R10, how10 = BUDGETS["cl40m@10000"]
+    p10 = B.bd_plan(dg, s, t, 0.05, 10000, budget_policy("cl40m@10000"))["walk_steps"].astype(float)
     calibrated = {
         "walk_counts": "calibrated against binary64 CG distances (tests/golden): eps-accurate",
         "policy": {"kind": "scaled", "c_B": c_B, "c_R": c_R, "calibration": how},
@@ -504,10 +505,11 @@ def scale_cl40m_default(B, torch, stream, pairs=32, thr_queries=65536):
         "walk_steps_per_query": {"mean": float(steps.mean()), "max": float(steps.max())},
         "queries_per_s": pairs / dt, "walk_steps_per_s": sps,
         "kernel_walk_steps_per_s": steps.sum() / (st["walk_kernel_ms"] / 1e3),
-        "L10000_projection": {"walk_steps_per_query_mean": float(p10.mean()),
-                              "seconds_per_query_at_measured_rate": float(p10.mean() / sps),
-                              "note": ("planner only: the walk variance grows about like L after mixing, so "
-                                       "R at L=10000 is ~10x and walk steps ~100x those at L=1000")}}
+        "L10000": {"policy": {"kind": "scaled", "c_B": c_B10, "c_R": c_R10, "calibration": how10},
+                   "walk_steps_per_query_mean": float(p10.mean()),
+                   "seconds_per_query_at_measured_rate": float(p10.mean() / sps),
+                   "note": ("planner: these pairs at L=10000; accuracy from the calibration tool's runs "
+                            "(budgets.py), not run here")}}
     s2, t2, eps2, L2 = queries.workload_batch("cl40m", g.n, thr_queries)
     tpol = budget_policy("cl40m")
     tplan = B.bd_plan(dg, s2, t2, eps2, L2, tpol)

@@ -121,6 +121,7 @@ def main(argv=None):
     ap.add_argument("--eps", type=float, default=0.05)
     ap.add_argument("--L", type=int, default=0, help="run every pair at this L (0: the file's L column)")
     ap.add_argument("--pairs", type=int, default=0, help="use the first this many pairs (0: all)")
+    ap.add_argument("--offset", type=int, default=0, help="skip this many of the selected pairs first")
     ap.add_argument("--only-L", type=int, default=0, help="use only the pairs whose L column equals this")
     ap.add_argument("--c-B", type=float, nargs="+", required=True)
     ap.add_argument("--c-R", type=float, nargs="+", required=True)
@@ -137,7 +138,7 @@ def main(argv=None):
     sel = np.ones(ref["index"].size, dtype=bool)
     if a.only_L:
         sel &= ref["L"] == a.only_L
-    idx = np.flatnonzero(sel)
+    idx = np.flatnonzero(sel)[a.offset:]
     if a.pairs:
         idx = idx[:a.pairs]
     s = ref["s"][idx].astype(np.int32)

@@ -101,6 +101,23 @@ def relabel(g: Csr, perm: np.ndarray, name: str | None = None) -> Csr:
     return csr_from_edges(g.n, u, v, name=name if name is not None else g.name)
 
 
+def storage_order(g: Csr):
+    """The graph as a library that stores nodes in descending-degree order
+    (ties by ascending id) holds it: node i of the result is the node of rank
+    i, and each row keeps the given neighbour order with the ids renamed (not
+    re-sorted). Returns (graph, order, internal): order[i] is the original id
+    of node i, internal the inverse permutation."""
+    order = np.argsort(-g.deg, kind="stable")
+    internal = np.empty(g.n, dtype=np.int64)
+    internal[order] = np.arange(g.n)
+    deg = g.deg[order]
+    rp = np.zeros(g.n + 1, dtype=np.int64)
+    np.cumsum(deg, out=rp[1:])
+    src = np.repeat(g.row_ptr[:-1][order], deg) + (np.arange(g.nnz) - np.repeat(rp[:-1], deg))
+    col = internal[g.col[src]].astype(np.int32)
+    return Csr(n=g.n, row_ptr=rp, col=col, name=g.name + "-storage"), order, internal
+
+
 # --------------------------------------------------------------------------- #
 # Small textbook graphs (closed forms for the exact distance exist on these)
 # --------------------------------------------------------------------------- #

@@ -1,9 +1,9 @@
 """The hubs-first layout with the probe on storage ids (BD_PROBE_STORAGE_IDS,
 layout code 5) against the oracle run on the relabelled graph.
 
-The relabelled graph is built here with numpy: node i of it is the caller's
-node of rank i in descending degree (ties by ascending id), each row keeps the
-caller's neighbour order with the ids renamed. On that graph the library's
+The relabelled graph is built with numpy (synth.graphs.storage_order): node i
+of it is the caller's node of rank i in descending degree (ties by ascending
+id), each row keeps the caller's neighbour order with the ids renamed. On that graph the library's
 results must equal the oracle's bit for bit (Algorithm 1: probe values,
 walks, per-probe Q, block means, estimates, in every mode, with split probes
 and with walk sharing), and its walks, reported in caller ids, are the same
@@ -30,15 +30,7 @@ FLAGS = B.BD_LAYOUT_COMPACT | B.BD_RELABEL_DEGREE | B.BD_PROBE_STORAGE_IDS
 
 
 def relabelled(g):
-    order = np.argsort(-g.deg, kind="stable")  # storage id -> caller id
-    internal = np.empty(g.n, dtype=np.int64)
-    internal[order] = np.arange(g.n)
-    deg = g.deg[order]
-    rp = np.zeros(g.n + 1, dtype=np.int64)
-    np.cumsum(deg, out=rp[1:])
-    src = np.repeat(g.row_ptr[:-1][order], deg) + (np.arange(g.nnz) - np.repeat(rp[:-1], deg))
-    col = internal[g.col[src]].astype(np.int32)
-    return graphs.Csr(n=g.n, row_ptr=rp, col=col, name=g.name + "-storage"), order, internal
+    return graphs.storage_order(g)
 
 
 @pytest.fixture(scope="module", params=[(key, kernel) for kernel in (0, B.BD_DIRECT_HUBS, B.BD_NARROW_HUBS)
