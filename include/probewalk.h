@@ -121,13 +121,14 @@ typedef struct bd_graph bd_graph;
                                    the degree-run table fits. Without it (and without
                                    BD_NARROW_HUBS) the walks resolve every node in LDS when
                                    they can: the offsets of the first h1 storage ids, past
-                                   which every run of equal degree is at least a block long
-                                   and of degree at most 2,047, then one 8-byte record per
-                                   block (64 to 512 storage ids, the smallest that fits)
-                                   and 1/d for every degree (layout code 8), if those take
-                                   at most 144 KB (on the Chung-Lu n=1e5 graph h1 = 1,934
-                                   and 24 KB); a walk step then makes one global load
-                                   instead of two. Same results */
+                                   which every block of storage ids holds nodes of at most
+                                   two degrees (runs, in descending-degree order), each at
+                                   most 2,047, then one 8-byte record per block (64 to 512
+                                   storage ids, the smallest that fits) and 1/d for every
+                                   degree (layout code 8), if those take at most 144 KB
+                                   (on the Chung-Lu n=1e5 graph h1 = 1,571 and 22 KB); a
+                                   walk step then makes one global load instead of two.
+                                   Same results */
 #define BD_DEVICE_PTRS     64u  /* row_ptr and col_idx are device pointers on the current
                                    device (e.g. the data of PyTorch tensors) instead of host
                                    arrays; they are read once, on `stream`, and not kept.

@@ -180,3 +180,38 @@ def test_run_table_with_large_blocks():
         other.free()
         direct.free()
         dg.free()
+
+
+def test_run_table_with_short_last_run():
+    # A full 2,200 x 2,200 grid (4.8e6 nodes): degree 4 inside, 3 on the
+    # border and 2 at the four corners, whose run of 4 storage ids comes last.
+    # Its table needs blocks of 512 storage ids and a block that ends in that
+    # short run; every node entry against layout 3, corners included, and
+    # estimates against the per-node-offset kernel
+    side = 2200
+    g = graphs.grid_minus_edges(side, 0.0, 5)
+    dg = B.graph_load_csr(g.n, g.row_ptr, g.col, FLAGS)
+    direct = B.graph_load_csr(g.n, g.row_ptr, g.col, FLAGS | B.BD_DIRECT_HUBS)
+    other = B.graph_load_csr(g.n, g.row_ptr, g.col, B.BD_LAYOUT_COMPACT | B.BD_RELABEL_DEGREE)
+    try:
+        assert dg.info()["lds_hubs"] == g.n
+        corners = np.array([0, side - 1, g.n - side, g.n - 1])
+        near = np.array([1, side - 2, g.n - side + 1, g.n - 2])
+        starts = np.concatenate([np.arange(0, g.n, 7), corners, near]).astype(np.int32)
+        z = np.zeros(starts.size, dtype=np.int64)
+        side_bit = np.arange(starts.size) % 2
+        tr, _ = B.bd_walk_trace(dg, starts, z + 3, z, np.arange(starts.size) % 5, side_bit, 2, SEED)
+        tr3, _ = B.bd_walk_trace(other, starts, z + 3, z, np.arange(starts.size) % 5, side_bit, 2, SEED)
+        assert np.array_equal(tr, tr3)
+        s = np.concatenate([corners, queries.uniform_pairs(g.n, 8, 43)[0]])
+        t = np.concatenate([corners[::-1], queries.uniform_pairs(g.n, 8, 43)[1]])
+        L = np.array([4, 50, 400, 3000] * 3, dtype=np.int32)
+        pol = B.policy("fixed", B=2, R=80)
+        for mode in ("plain", "batched"):
+            a = B.bd_query_batch(dg, s, t, 0.1, L, SEED, pol, B.exec_cfg(mode))
+            b = B.bd_query_batch(direct, s, t, 0.1, L, SEED, pol, B.exec_cfg(mode))
+            assert np.all(a["status"] == 0) and np.array_equal(a["beta"], b["beta"]), mode
+    finally:
+        other.free()
+        direct.free()
+        dg.free()
