@@ -164,6 +164,7 @@ struct bd_graph {
     DevBuf node, col, adj, rp32, col24, node8, runtab;
     uint32_t run_h1 = 0, run_words = 0, run_ninv = 0;  // code 8: direct row offsets, words of runtab, d_max + 1
     uint32_t run_shift = 0;                            // code 8: log2 of the storage ids per record
+    bool runs_shared = false;                          // code 8: the table fits the walk-sharing kernels
     DomainParams dom{};
     int64_t device_bytes = 0;
     std::mutex mu;  // serialises calls that use the per-graph work buffers
@@ -557,14 +558,19 @@ extern "C" int graph_load_csr(int64_t n, const int64_t* row_ptr, const int32_t* 
             g->run_words = (uint32_t)runtab.size();
             g->run_ninv = (uint32_t)dmax + 1u;
             g->run_shift = shift;
-            if (g->runtab.alloc(runtab.size() * 4) != BD_OK ||
-                hipMemcpyAsync(g->runtab.p, runtab.data(), runtab.size() * 4, hipMemcpyHostToDevice, st) !=
+            const int arc = g->runtab.alloc(runtab.size() * 4);
+            if (arc != BD_OK) {
+                delete g;
+                return arc;
+            }
+            if (hipMemcpyAsync(g->runtab.p, runtab.data(), runtab.size() * 4, hipMemcpyHostToDevice, st) !=
                     hipSuccess ||
                 hipStreamSynchronize(st) != hipSuccess) {
                 delete g;
                 return BD_E_HIP;
             }
             g->kernel_layout = kLayoutHubRuns;
+            g->runs_shared = ((runtab.size() + 3) & ~(size_t)3) + g->run_ninv <= kRunWordsShared;
         }
     }
     g->device_bytes = (int64_t)(g->node.bytes + g->col.bytes + g->adj.bytes + g->rp32.bytes + g->col24.bytes +
@@ -722,10 +728,18 @@ GraphTables tables(const bd_graph* g)
     return t;
 }
 
+// The kernel code that runs walks of sharing class `share` on g: the graph's,
+// except that the walk-sharing kernels of code 8 hold a smaller table and fall
+// back to code 7 (the same tables and results) where it does not fit them.
+int run_kernel(const bd_graph* g, int share)
+{
+    return g->kernel_layout == kLayoutHubRuns && share > 1 && !g->runs_shared ? kLayoutHubIdX2 : g->kernel_layout;
+}
+
 int resident_wgs(const bd_graph* g, int uniform, int share = 1)
 {
     int per_cu = 0;
-    if (walk_occupancy(g->kernel_layout, uniform, share, &per_cu) != 0 || per_cu < 1) per_cu = 1;
+    if (walk_occupancy(run_kernel(g, share), uniform, share, &per_cu) != 0 || per_cu < 1) per_cu = 1;
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, g->device) != hipSuccess) return per_cu * 256;
     return per_cu * prop.multiProcessorCount;
@@ -972,7 +986,7 @@ int run_batch(bd_graph* g, const Batch& b, const bd_exec& ex, hipStream_t user_s
     a.q_debug = q_dbg_host ? static_cast<double*>(w.qdbg) : nullptr;
     a.ybar_debug = y_dbg_host ? static_cast<double*>(w.ydbg) : nullptr;
     a.abort_flag = watch ? g->ws.abort_dev : nullptr;
-    const int layout = g->kernel_layout;
+    const int layout = run_kernel(g, b.share);
 
     // the zeroing every launch needs
     auto zero_all = [&](hipStream_t s2) -> int {
@@ -2206,7 +2220,8 @@ int launch_slice(bd_server* S, Slice& sl)
         ap.qoff[0] = 0;
         ap.qoff[1] = ap.nchunks;
         const uint32_t grid = std::min<uint32_t>((uint32_t)S->resident[part == 0], ap.nchunks);
-        if (grid && launch_walk(ap, S->g->kernel_layout, part == 0, share_class(policy_share(S->pol)), grid, st) !=
+        if (grid && launch_walk(ap, run_kernel(S->g, share_class(policy_share(S->pol))), part == 0,
+                                share_class(policy_share(S->pol)), grid, st) !=
                         hipSuccess)
             return BD_E_HIP;
     }

@@ -124,12 +124,15 @@ constexpr int kLayoutHubIdX2 = 7;
 // dA | dB << 11 | bnd << 22}, its nodes before bnd having degree dA and the
 // rest dB. After the table the LDS holds 1.0f/d for d = 0 .. d_max, so a step
 // reads the reciprocal instead of dividing. The launch shape is code 7's; the
-// results are layout 5's. Walk sharing runs code 7's kernels on these tables.
+// results are layout 5's. The walk-sharing kernels (256-thread groups) hold a
+// smaller copy (kRunWordsShared words); where the table does not fit it,
+// walk sharing runs code 7's kernels on these tables (run_kernel).
 constexpr int kLayoutHubRuns = 8;
 constexpr uint32_t kRunShiftMin = 6, kRunShiftMax = 9;
 constexpr uint32_t kRunMaxDeg = 0x7FFu;
-// the kernel that runs a layout code with a walk-sharing class
-constexpr int walk_layout(int layout, int share) { return layout == kLayoutHubRuns && share > 1 ? 7 : layout; }
+// LDS words of the run table and reciprocals in the walk-sharing kernels of
+// code 8 (24 KB: with their other LDS, four such groups per CU)
+constexpr uint32_t kRunWordsShared = 6144;
 constexpr bool hubid_layout(int layout)
 {
     return layout == kLayoutHubId || layout == kLayoutHubIdX2 || layout == kLayoutHubRuns;
@@ -149,9 +152,8 @@ constexpr bool hub_layout(int layout)
 constexpr uint32_t hub_nodes(int threads, int layout)
 {
     if (layout == kLayoutHubIdX2 && threads >= 1024) return 36864u;  // 144 KB: what the CU's 160 KB leaves
-    // code 8 (1,024-thread groups only): capacity in 32-bit words of the run
-    // table and the reciprocals
-    if (layout == kLayoutHubRuns) return 36864u;
+    // code 8: capacity in 32-bit words of the run table and the reciprocals
+    if (layout == kLayoutHubRuns) return threads >= 1024 ? 36864u : kRunWordsShared - 1u;
     return (threads >= 1024 ? 8192u : 1024u) * (layout == kLayoutHubIdX2 ? 4u : layout == kLayoutHubId ? 2u : 1u);
 }
 // 32-bit words of the LDS hub copy (entries 0 .. hub_nodes, inclusive)

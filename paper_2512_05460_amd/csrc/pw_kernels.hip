@@ -592,18 +592,13 @@ walk_kernel(WalkArgs A)
 template <int kLayout>
 static const void* walk_fn_l(int uniform, int share)
 {
-    if constexpr (kLayout != kLayoutHubRuns) {  // code 8 has no sharing kernels (walk_layout)
-        if (share == 4)
-            return uniform ? (const void*)walk_kernel<kLayout, 1, 4> : (const void*)walk_kernel<kLayout, 0, 4>;
-        if (share == 2)
-            return uniform ? (const void*)walk_kernel<kLayout, 1, 2> : (const void*)walk_kernel<kLayout, 0, 2>;
-    }
+    if (share == 4) return uniform ? (const void*)walk_kernel<kLayout, 1, 4> : (const void*)walk_kernel<kLayout, 0, 4>;
+    if (share == 2) return uniform ? (const void*)walk_kernel<kLayout, 1, 2> : (const void*)walk_kernel<kLayout, 0, 2>;
     return uniform ? (const void*)walk_kernel<kLayout, 1, 1> : (const void*)walk_kernel<kLayout, 0, 1>;
 }
 
 static const void* walk_fn(int layout, int uniform, int share)
 {
-    layout = walk_layout(layout, share);
     if (layout == kLayoutFat) return walk_fn_l<kLayoutFat>(uniform, share);
     if (layout == kLayoutFatNT) return walk_fn_l<kLayoutFatNT>(uniform, share);
     if (layout == kLayoutCompact) return walk_fn_l<kLayoutCompact>(uniform, share);
@@ -618,26 +613,17 @@ static const void* walk_fn(int layout, int uniform, int share)
 template <int kLayout, int kUniform>
 static void launch_l(const WalkArgs& a, int share, uint32_t grid, hipStream_t st)
 {
-    if constexpr (kLayout == kLayoutHubRuns) {  // no sharing kernels (walk_layout)
-        (void)share;
+    if (share == 4)
+        hipLaunchKernelGGL((walk_kernel<kLayout, kUniform, 4>), dim3(grid), dim3(block_threads(kLayout, 4)), 0, st, a);
+    else if (share == 2)
+        hipLaunchKernelGGL((walk_kernel<kLayout, kUniform, 2>), dim3(grid), dim3(block_threads(kLayout, 2)), 0, st, a);
+    else
         hipLaunchKernelGGL((walk_kernel<kLayout, kUniform, 1>), dim3(grid), dim3(block_threads(kLayout, 1)), 0, st, a);
-    } else {
-        if (share == 4)
-            hipLaunchKernelGGL((walk_kernel<kLayout, kUniform, 4>), dim3(grid), dim3(block_threads(kLayout, 4)), 0, st,
-                               a);
-        else if (share == 2)
-            hipLaunchKernelGGL((walk_kernel<kLayout, kUniform, 2>), dim3(grid), dim3(block_threads(kLayout, 2)), 0, st,
-                               a);
-        else
-            hipLaunchKernelGGL((walk_kernel<kLayout, kUniform, 1>), dim3(grid), dim3(block_threads(kLayout, 1)), 0, st,
-                               a);
-    }
 }
 
 hipError_t launch_walk(const WalkArgs& a, int layout, int uniform, int share, uint32_t grid, hipStream_t st)
 {
     if (grid == 0) return hipSuccess;
-    layout = walk_layout(layout, share);
     if (layout == kLayoutFat) {
         if (uniform) launch_l<kLayoutFat, 1>(a, share, grid, st);
         else launch_l<kLayoutFat, 0>(a, share, grid, st);
@@ -673,7 +659,7 @@ int walk_occupancy(int layout, int uniform, int share, int* wgs_per_cu)
 {
     int nb = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, walk_fn(layout, uniform, share),
-                                                     block_threads(walk_layout(layout, share), share), 0) !=
+                                                     block_threads(layout, share), 0) !=
         hipSuccess)
         return -1;
     *wgs_per_cu = nb;
