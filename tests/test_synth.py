@@ -116,3 +116,20 @@ def test_native_chung_lu():
     assert 0.9 * 50_000 < a.n <= 50_000 and 22 < a.nnz / a.n < 26
     c = graphs.chung_lu_native(50_000, 25.0, 2.2, 4, threads=2)
     assert not np.array_equal(a.col[:1000], c.col[:1000])
+
+
+def test_storage_order():
+    # node i of the result is the node of rank i in descending degree (ties by
+    # ascending id); each row keeps the given neighbour order, renamed
+    g = graphs.barabasi_albert(300, 3, 11)
+    gs, order, internal = graphs.storage_order(g)
+    assert sorted(order.tolist()) == list(range(g.n))
+    assert np.array_equal(internal[order], np.arange(g.n))
+    d = g.deg[order]
+    assert np.all(np.diff(d) <= 0)
+    ties = (d[1:] == d[:-1])
+    assert np.all(order[1:][ties] > order[:-1][ties])
+    for i in range(g.n):
+        v = order[i]
+        row = gs.col[gs.row_ptr[i]:gs.row_ptr[i + 1]]
+        assert np.array_equal(order[row], g.col[g.row_ptr[v]:g.row_ptr[v + 1]])
