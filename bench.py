@@ -42,7 +42,7 @@ HBM_PEAK_GBS = 8000.0
 L2_PEAK_REQ_PER_S = 8 * 16 * 2.4e9   # one request per L2 channel per clock, 16 channels per XCD
 COUNTERS = os.path.join(ROOT, "profiles", "walk_kernel_cl100k_counters.txt")
 FAT_SCALE_COUNTERS = os.path.join(ROOT, "profiles", "walk_kernel_fat_cl40m_counters.txt")
-KERNEL_SOURCES = ["pw_kernels.hip", "pw_device.hpp", "pw_internal.hpp"]
+KERNEL_SOURCES = ["pw_kernels.hip", "pw_device.hpp", "pw_internal.hpp", "pw_runs.hpp"]
 LAYOUT_NAMES = {0: "csr", 1: "fat", 2: "compact", 3: "compact, hubs first", 4: "hubs first, 4-byte ids",
                 5: "hubs first, probe on storage ids"}
 

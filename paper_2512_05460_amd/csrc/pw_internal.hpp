@@ -6,6 +6,8 @@
 
 #include <mutex>
 
+#include "pw_runs.hpp"
+
 namespace pw {
 
 // One query as the device sees it (Algorithm 1 inputs and parameters).
@@ -127,9 +129,7 @@ constexpr int kLayoutHubIdX2 = 7;
 // results are layout 5's. The walk-sharing kernels (256-thread groups) hold a
 // smaller copy (kRunWordsShared words); where the table does not fit it,
 // walk sharing runs code 7's kernels on these tables (run_kernel).
-constexpr int kLayoutHubRuns = 8;
-constexpr uint32_t kRunShiftMin = 6, kRunShiftMax = 9;
-constexpr uint32_t kRunMaxDeg = 0x7FFu;
+constexpr int kLayoutHubRuns = 8;  // constants and builder: pw_runs.hpp
 // LDS words of the run table and reciprocals in the walk-sharing kernels of
 // code 8 (24 KB: with their other LDS, four such groups per CU)
 constexpr uint32_t kRunWordsShared = 6144;
@@ -139,8 +139,6 @@ constexpr bool hubid_layout(int layout)
 }
 // replica pairs a lane runs at once
 constexpr int lane_pairs(int layout) { return layout == kLayoutHubIdX2 || layout == kLayoutHubRuns ? 2 : 1; }
-// first 32-bit word of the run records in the LDS copy of code 8 (8-byte aligned)
-constexpr uint32_t run_records_at(uint32_t h1) { return (h1 + 2u) & ~1u; }
 constexpr bool hub_layout(int layout)
 {
     return layout == kLayoutCompactHub || layout == kLayoutHub32 || hubid_layout(layout);
