@@ -215,3 +215,37 @@ def test_run_table_with_short_last_run():
         other.free()
         direct.free()
         dg.free()
+
+
+@pytest.mark.parametrize("kernel", [0, B.BD_DIRECT_HUBS])
+@pytest.mark.parametrize("make", [lambda: graphs.complete_graph(5), lambda: graphs.path_graph(2),
+                                  lambda: graphs.cycle_graph(6), lambda: graphs.random_connected(37, 0.1, 4)],
+                         ids=["K5", "P2", "C6", "G37"])
+def test_tiny_graphs(make, kernel):
+    # graphs of one or a few runs, fewer nodes than a block: estimates in both
+    # modes against the oracle on the graph in storage order, walks against
+    # layout 3
+    g = make()
+    gs, order, internal = relabelled(g)
+    dg = B.graph_load_csr(g.n, g.row_ptr, g.col, FLAGS | kernel)
+    try:
+        assert dg.info()["lds_hubs"] == (g.n if kernel == 0 else min(g.n, 36864))
+        s = np.array([0, 1, g.n - 1, 1], dtype=np.int32)
+        t = np.array([1, g.n - 1, 0, 0], dtype=np.int32)
+        keep = s != t
+        s, t = s[keep], t[keep]
+        L = np.array([0, 3, 40, 200][:s.size], dtype=np.int32)
+        pol = B.policy("fixed", B=2, R=70)
+        ref = E.estimate(gs, internal[s], internal[t], L, _plans(L, 2, 70, 1), SEED, threads=4)
+        for mode in ("plain", "batched"):
+            res = B.bd_query_batch(dg, s, t, 0.1, L, SEED, pol, B.exec_cfg(mode))
+            assert np.all(res["status"] == 0) and np.array_equal(res["beta"], ref), mode
+        starts = np.arange(g.n, dtype=np.int32)
+        z = np.zeros(g.n, dtype=np.int64)
+        tr, _ = B.bd_walk_trace(dg, starts, z + 1, z + 2, z, np.arange(g.n) % 2, 30, SEED)
+        other = B.graph_load_csr(g.n, g.row_ptr, g.col, B.BD_LAYOUT_COMPACT | B.BD_RELABEL_DEGREE)
+        tr3, _ = B.bd_walk_trace(other, starts, z + 1, z + 2, z, np.arange(g.n) % 2, 30, SEED)
+        other.free()
+        assert np.array_equal(tr, tr3)
+    finally:
+        dg.free()
