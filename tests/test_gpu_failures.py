@@ -23,10 +23,16 @@ pytestmark = pytest.mark.gpu
 SEED = graphs.PHILOX_SEED
 
 
-@pytest.fixture(scope="module")
-def cl():
+@pytest.fixture(scope="module", params=["hubs", "storage-ids"])
+def cl(request):
+    # compact hubs first, and the storage-id layout with the degree-run kernel
     g = graphs.workload_graph("cl100k")
-    dg = B.graph_load_csr(g.n, g.row_ptr, g.col, B.BD_LAYOUT_COMPACT | B.BD_RELABEL_DEGREE)
+    flags = B.BD_LAYOUT_COMPACT | B.BD_RELABEL_DEGREE
+    if request.param == "storage-ids":
+        flags |= B.BD_PROBE_STORAGE_IDS
+    dg = B.graph_load_csr(g.n, g.row_ptr, g.col, flags)
+    if request.param == "storage-ids":
+        assert dg.info()["lds_hubs"] == g.n
     yield g, dg
     dg.free()
 
