@@ -25,7 +25,8 @@ pytestmark = pytest.mark.gpu
 
 SEED = graphs.PHILOX_SEED
 LAYOUTS = [B.BD_LAYOUT_CSR, B.BD_LAYOUT_FAT | B.BD_RELABEL_DEGREE, B.BD_LAYOUT_COMPACT,
-           B.BD_LAYOUT_COMPACT | B.BD_RELABEL_DEGREE, B.BD_LAYOUT_COMPACT | B.BD_RELABEL_DEGREE | B.BD_WIDE_IDS]
+           B.BD_LAYOUT_COMPACT | B.BD_RELABEL_DEGREE, B.BD_LAYOUT_COMPACT | B.BD_RELABEL_DEGREE | B.BD_WIDE_IDS,
+           B.BD_LAYOUT_COMPACT | B.BD_RELABEL_DEGREE | B.BD_PROBE_STORAGE_IDS]
 
 
 def _oracle(g, s, t, L, b, r):
@@ -48,7 +49,11 @@ def test_device_csr_through_torch_memory(flags):
     pol = B.policy("fixed", B=2, R=80)
     res = B.bd_query_batch(dg, s, t, 0.1, 30, SEED, pol)
     assert np.all(res["status"] == 0)
-    assert np.array_equal(res["beta"], _oracle(g, s, t, 30, 2, 80))
+    if flags & B.BD_PROBE_STORAGE_IDS:  # Algorithm 1 on the graph in storage order
+        gs, _, internal = graphs.storage_order(g)
+        assert np.array_equal(res["beta"], _oracle(gs, internal[s], internal[t], 30, 2, 80))
+    else:
+        assert np.array_equal(res["beta"], _oracle(g, s, t, 30, 2, 80))
     dg.free()
     torch.cuda.synchronize()
     assert torch.cuda.memory_allocated() == before

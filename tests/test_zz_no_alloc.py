@@ -21,10 +21,14 @@ def _same(a, b):
     assert np.array_equal(a["beta"], b["beta"])  # bit for bit (exact sums)
 
 
-@pytest.fixture(scope="module")
-def ba():
+@pytest.fixture(scope="module", params=["hubs", "storage-ids"])
+def ba(request):
+    # compact hubs first, and the storage-id layout with the degree-run kernel
     g = graphs.workload_graph("ba1k")
-    dg = B.graph_load_csr(g.n, g.row_ptr, g.col, B.BD_LAYOUT_COMPACT | B.BD_RELABEL_DEGREE)
+    flags = B.BD_LAYOUT_COMPACT | B.BD_RELABEL_DEGREE
+    if request.param == "storage-ids":
+        flags |= B.BD_PROBE_STORAGE_IDS
+    dg = B.graph_load_csr(g.n, g.row_ptr, g.col, flags)
     yield g, dg
     dg.free()
 
