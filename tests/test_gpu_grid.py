@@ -9,7 +9,9 @@ paper_2512_05460_amd/budgets.py (scaled policy of Algorithm 1).
   * sampled parity at full size: beta-hat of two queries of every (eps, L)
     pair equals the oracle's bit for bit (all sums are exact fixed point);
   * graph replays equal the eager persistent launch, any number of chunk
-    queues, the plain mode and the compact layout.
+    queues, the plain mode and the compact layout;
+  * the same launch on the benchmark's tables (the probe on storage ids, the
+    degree-run kernel) against the oracle on the grid in storage order.
 """
 
 import sys
@@ -124,3 +126,38 @@ def test_grid_replay_equals_eager_and_plain(grid):
         assert np.array_equal(r["beta"], eager["beta"])
     finally:
         dc.free()
+
+
+@pytest.mark.timeout(600)
+def test_grid_storage_ids_graph_sampled_parity():
+    # the benchmark's grid tables: hubs first with the probe on storage ids and
+    # the degree-run kernel (blocks of 128 storage ids); autotuned chunking,
+    # the whole set from a captured hipGraph, replayed with eager work between;
+    # sampled estimates against the oracle on the grid in storage order
+    g = graphs.workload_graph("grid1414")
+    dg = B.graph_load_csr(g.n, g.row_ptr, g.col,
+                          B.BD_LAYOUT_COMPACT | B.BD_RELABEL_DEGREE | B.BD_PROBE_STORAGE_IDS)
+    try:
+        assert dg.info()["lds_hubs"] == g.n
+        gs, _, internal = graphs.storage_order(g)
+        s, t, eps, L = queries.workload_batch("grid1414", g.n)
+        pol = budget_policy("grid1414")
+        best, _ = B.bd_autotune(dg, s[:2048], t[:2048], eps[:2048], L[:2048], SEED, pol)
+        ex = B.exec_cfg("batched", chunk_pairs=best.chunk_pairs, use_graph=True, queues=best.queues)
+        res = B.bd_query_batch(dg, s, t, eps, L, SEED, pol, ex)
+        assert np.all(res["status"] == 0)
+        _say(f"[grid] storage ids: chunk_pairs={best.chunk_pairs} queues={best.queues}")
+        idx = _sample(eps, L)
+        plans = _oracle_plans(gs, internal[s[idx]], internal[t[idx]], eps[idx], L[idx])
+        ref = E.estimate(gs, internal[s[idx]], internal[t[idx]], L[idx], plans, SEED, uid=idx.astype(np.uint32),
+                         threads=16)
+        assert np.array_equal(res["beta"][idx], ref), (idx, res["beta"][idx] - ref)
+        sub = slice(0, 4096)
+        first = B.bd_query_batch(dg, s[sub], t[sub], eps[sub], L[sub], SEED, pol, ex)
+        assert np.array_equal(first["beta"], res["beta"][sub])
+        for rep in range(2):
+            B.bd_query_batch(dg, s[:4], t[:4], eps[:4], L[:4], SEED + rep, pol, B.exec_cfg("batched"))
+            again = B.bd_query_batch(dg, s[sub], t[sub], eps[sub], L[sub], SEED, pol, ex)
+            assert np.array_equal(again["beta"], first["beta"]), rep
+    finally:
+        dg.free()
