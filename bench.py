@@ -673,14 +673,16 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--queries", type=int, default=32, help="queries per step")
-    ap.add_argument("--layout", choices=["hubs", "hubsid", "hubsidd", "hubsidn", "compact", "csr", "fat", "auto"],
+    ap.add_argument("--layout", choices=["hubs", "hubsid", "hubsidw", "hubsidd", "hubsidn", "compact", "csr", "fat",
+                                         "auto"],
                     default="hubsid",
                     help="hubs: compact layout with nodes in descending-degree order and hub entries in LDS; "
-                         "hubsid: the same with the probe on storage ids (one work group per CU with two replica "
-                         "pairs per thread and every node's row offset and degree in LDS from the degree-run "
-                         "table); hubsidd: hubsid with the row offsets of the 36,864 highest-degree nodes in LDS "
-                         "instead; hubsidn: hubsid with two work groups per CU and 16,384 offsets each; auto: the "
-                         "library's choice (hubs at this size)")
+                         "hubsid: the same with the probe on storage ids (every node's row offset and degree in "
+                         "LDS from the degree-run table; two work groups per CU, one replica pair per thread, "
+                         "at this size); hubsidw: hubsid with one work group per CU and two pairs per thread; "
+                         "hubsidd: hubsid with the row offsets of the 36,864 highest-degree nodes in LDS instead; "
+                         "hubsidn: hubsid forced to two work groups per CU; auto: the library's choice (hubs at "
+                         "this size)")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--no-roofline", action="store_true")
@@ -725,6 +727,7 @@ def main():
     s, t = s_all[:nq], t_all[:nq]
     flags = {"hubs": B.BD_LAYOUT_COMPACT | B.BD_RELABEL_DEGREE,
              "hubsid": B.BD_LAYOUT_COMPACT | B.BD_RELABEL_DEGREE | B.BD_PROBE_STORAGE_IDS,
+             "hubsidw": B.BD_LAYOUT_COMPACT | B.BD_RELABEL_DEGREE | B.BD_PROBE_STORAGE_IDS | B.BD_WIDE_HUBS,
              "hubsidd": B.BD_LAYOUT_COMPACT | B.BD_RELABEL_DEGREE | B.BD_PROBE_STORAGE_IDS | B.BD_DIRECT_HUBS,
              "hubsidn": B.BD_LAYOUT_COMPACT | B.BD_RELABEL_DEGREE | B.BD_PROBE_STORAGE_IDS | B.BD_NARROW_HUBS,
              "compact": B.BD_LAYOUT_COMPACT,

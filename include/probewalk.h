@@ -100,35 +100,37 @@ typedef struct bd_graph bd_graph;
                                    rows keep the caller's neighbour order, so the walks are
                                    the same, and a uniformly random probe composed with a
                                    fixed relabelling is again one, but the bits of every
-                                   result follow the relabelled ids. Node entries shrink to
-                                   the 4-byte row offset and 36,864 (BD_NARROW_HUBS: 16,384)
-                                   of the highest-degree ones are staged in LDS (layout code
-                                   5). bd_walk_trace still reports caller ids */
+                                   result follow the relabelled ids. A node entry is its
+                                   4-byte row offset, and the walk kernels read every node's
+                                   row offset and degree from LDS where the degree-run table
+                                   fits (BD_DIRECT_HUBS). bd_walk_trace still reports caller
+                                   ids */
 #define BD_NONTEMPORAL    256u  /* with BD_LAYOUT_FAT: read the adjacency entries with
                                    non-temporal loads at any size (same results) */
 #define BD_TEMPORAL       512u  /* with BD_LAYOUT_FAT: ordinary loads at any size. Without
                                    either flag the fat layout uses non-temporal loads when
                                    its tables take at least 4 GiB (16x the Infinity Cache:
                                    measured +9.5% at 20.7 GB, -3.5% at 2.2 GB) */
-#define BD_NARROW_HUBS   1024u  /* with BD_PROBE_STORAGE_IDS: two 1,024-thread work groups per
-                                   CU, each staging the 16,384 highest-degree row offsets
-                                   (64 KB), one replica pair per thread. Without it the walks
-                                   of this layout run one 1,024-thread work group per CU that
-                                   stages 36,864 offsets (144 KB of the CU's 160 KB of LDS)
-                                   with two replica pairs per thread. Same results */
-#define BD_DIRECT_HUBS   2048u  /* with BD_PROBE_STORAGE_IDS: stage the row offsets of the
-                                   36,864 highest-degree nodes (layout code 7) even where
-                                   the degree-run table fits. Without it (and without
-                                   BD_NARROW_HUBS) the walks resolve every node in LDS when
-                                   they can: the offsets of the first h1 storage ids, past
-                                   which every block of storage ids holds nodes of at most
-                                   two degrees (runs, in descending-degree order), each at
-                                   most 2,047, then one 8-byte record per block (64 to 512
-                                   storage ids, the smallest that fits) and 1/d for every
-                                   degree (layout code 8), if those take at most 144 KB
-                                   (on the Chung-Lu n=1e5 graph h1 = 1,571 and 22 KB); a
-                                   walk step then makes one global load instead of two.
-                                   Same results */
+/* Kernels of the BD_PROBE_STORAGE_IDS layout (same tables, same results). By
+ * default the walks resolve every node in LDS through the degree-run table:
+ * the row offsets of the first h1 storage ids, past which every block of
+ * storage ids holds nodes of at most two degrees (runs, in descending-degree
+ * order), each at most 2,047, then one 8-byte record per block (64 to 512
+ * storage ids, the smallest that fits) and 1/d for every degree; a walk step
+ * then makes one global load instead of two (on the Chung-Lu n=1e5 graph
+ * h1 = 1,571 and 22 KB). Where the table fits 64 KB two 1,024-thread work
+ * groups per CU run one replica pair per thread (layout code 9); where it
+ * fits 144 KB one group per CU runs two pairs per thread (code 8); else one
+ * group per CU stages the row offsets of the 36,864 highest-degree nodes
+ * (code 7). The flags below force a choice. */
+#define BD_NARROW_HUBS   1024u  /* two work groups per CU, one pair per thread: the table
+                                   where it fits 64 KB (code 9), else the 16,384
+                                   highest-degree row offsets (code 5) */
+#define BD_DIRECT_HUBS   2048u  /* no degree-run table: the highest-degree row offsets
+                                   (code 7; code 5 with BD_NARROW_HUBS) */
+#define BD_WIDE_HUBS     4096u  /* one work group per CU, two pairs per thread: the table
+                                   where it fits 144 KB (code 8), else code 7. Not with
+                                   BD_NARROW_HUBS */
 #define BD_DEVICE_PTRS     64u  /* row_ptr and col_idx are device pointers on the current
                                    device (e.g. the data of PyTorch tensors) instead of host
                                    arrays; they are read once, on `stream`, and not kept.

@@ -61,6 +61,7 @@ BD_NONTEMPORAL = 256
 BD_TEMPORAL = 512
 BD_NARROW_HUBS = 1024
 BD_DIRECT_HUBS = 2048
+BD_WIDE_HUBS = 4096
 
 BD_POLICY_PAPER = 0
 BD_POLICY_SCALED = 1

@@ -292,7 +292,7 @@ __device__ __forceinline__ WalkState start_at(const DevGraph& G, uint32_t x)
         hub_row(G, x, w);
         return w;
     }
-    if (kLayout == kLayoutHubRuns) {
+    if (runs_layout(kLayout)) {
         WalkState w;
         runs_row(G, x, w);
         return w;
@@ -332,7 +332,7 @@ __device__ __forceinline__ void step(WalkState& w, uint32_t u, const DevGraph& G
         const uint32_t hi = G.col24[wi + 1];
         const uint32_t x = __builtin_amdgcn_alignbit(hi, lo, (o & 3u) * 8u) & 0xFFFFFFu;
         if (kLayout == kLayoutCompact) compact_row(G, x, w);
-        else if (kLayout == kLayoutHubRuns) runs_row(G, x, w);
+        else if (runs_layout(kLayout)) runs_row(G, x, w);
         else if (hubid_layout(kLayout)) hubid_row(G, x, w);
         else hub_row(G, x, w);
     } else if (kLayout == kLayoutHub32) {
@@ -358,7 +358,7 @@ __device__ __forceinline__ void stage_hubs(DevGraph& G, uint32_t* lds, uint32_t 
         __syncthreads();
         G.hub = l2;
         G.nhub = nh;
-    } else if constexpr (kLayout == kLayoutHubRuns) {
+    } else if constexpr (runs_layout(kLayout)) {
         // the run table, then 1.0f/d for every degree 0 .. d_max (the same
         // correctly rounded quotients a step would compute); the host takes
         // this layout only where both fit `capacity` + 1 words

@@ -155,7 +155,7 @@ struct bd_graph {
     int32_t bipartite = 0;
     int32_t layout = 0;  // 0 CSR, 1 fat, 2 compact, ... (kLayout* of the kernels)
     int32_t kernel_layout = 0;  // the kernels' layout code: layout, 6 for fat with non-temporal
-                                // loads, 7 or 8 for layout 5 (kLayout* of the kernels)
+                                // loads, 7, 8 or 9 for layout 5 (kLayout* of the kernels)
     int device = 0;
     uint32_t cus = 0;                // compute units of the device
     std::vector<int32_t> deg;        // host copy for the planner, by caller id
@@ -329,6 +329,7 @@ extern "C" int graph_load_csr(int64_t n, const int64_t* row_ptr, const int32_t* 
     if ((flags & BD_NONTEMPORAL) && (flags & BD_TEMPORAL)) return BD_E_INVALID;
     if ((flags & BD_NARROW_HUBS) && !(flags & BD_PROBE_STORAGE_IDS)) return BD_E_INVALID;
     if ((flags & BD_DIRECT_HUBS) && !(flags & BD_PROBE_STORAGE_IDS)) return BD_E_INVALID;
+    if ((flags & BD_WIDE_HUBS) && (!(flags & BD_PROBE_STORAGE_IDS) || (flags & BD_NARROW_HUBS))) return BD_E_INVALID;
     if ((flags & (BD_NONTEMPORAL | BD_TEMPORAL)) && !(flags & BD_LAYOUT_FAT)) return BD_E_INVALID;
     if (flags & BD_LAYOUT_COMPACT) {
         if (flags & BD_LAYOUT_FAT) return BD_E_INVALID;
@@ -495,15 +496,26 @@ extern "C" int graph_load_csr(int64_t n, const int64_t* row_ptr, const int32_t* 
         delete g;
         return BD_E_HIP;
     }
-    if (g->kernel_layout == 7 && !(flags & BD_DIRECT_HUBS)) {
+    if (g->layout == 5 && !(flags & BD_DIRECT_HUBS)) {
+        // the degree-run table: two work groups per CU where it fits 64 KB,
+        // else one per CU with two pairs per thread (flags may force either)
         std::vector<uint32_t> runtab;
-        // the smallest block that fits: smaller blocks let shorter runs in
+        int code = 0;
         uint32_t shift = kRunShiftMin;
-        while (shift <= kRunShiftMax &&
-               !build_run_table(rp32, shift, (uint32_t)dmax + 1u, hub_words(1024, kLayoutHubRuns), &g->run_h1,
-                                &runtab))
-            ++shift;
-        if (shift <= kRunShiftMax) {
+        for (const int c : {kLayoutHubRunsNarrow, kLayoutHubRuns}) {
+            if ((c == kLayoutHubRunsNarrow && (flags & BD_WIDE_HUBS)) ||
+                (c == kLayoutHubRuns && (flags & BD_NARROW_HUBS)))
+                continue;
+            // the smallest block that fits: smaller blocks let shorter runs in
+            for (shift = kRunShiftMin; shift <= kRunShiftMax; ++shift)
+                if (build_run_table(rp32, shift, (uint32_t)dmax + 1u, hub_words(1024, c), &g->run_h1, &runtab))
+                    break;
+            if (shift <= kRunShiftMax) {
+                code = c;
+                break;
+            }
+        }
+        if (code != 0) {
             g->run_words = (uint32_t)runtab.size();
             g->run_ninv = (uint32_t)dmax + 1u;
             g->run_shift = shift;
@@ -518,7 +530,7 @@ extern "C" int graph_load_csr(int64_t n, const int64_t* row_ptr, const int32_t* 
                 delete g;
                 return BD_E_HIP;
             }
-            g->kernel_layout = kLayoutHubRuns;
+            g->kernel_layout = code;
             g->runs_shared = ((runtab.size() + 3) & ~(size_t)3) + g->run_ninv <= kRunWordsShared;
         }
     }
@@ -543,7 +555,7 @@ extern "C" int bd_graph_get_info(const bd_graph* g, bd_graph_info* info)
     info->bipartite = g->bipartite;
     info->layout = g->layout;
     info->nontemporal = g->kernel_layout == 6 ? 1 : 0;
-    info->lds_hubs = g->kernel_layout == kLayoutHubRuns ? (int32_t)g->n
+    info->lds_hubs = runs_layout(g->kernel_layout) ? (int32_t)g->n
                      : hub_layout(g->kernel_layout)
                          ? (int32_t)std::min<int64_t>(hub_nodes(1024, g->kernel_layout), g->n)
                          : 0;
@@ -678,11 +690,13 @@ GraphTables tables(const bd_graph* g)
 }
 
 // The kernel code that runs walks of sharing class `share` on g: the graph's,
-// except that the walk-sharing kernels of code 8 hold a smaller table and fall
-// back to code 7 (the same tables and results) where it does not fit them.
+// except that walk sharing on the degree-run table runs code 8's sharing
+// kernels, which hold a smaller copy, or code 7's (the same tables and
+// results) where it does not fit them.
 int run_kernel(const bd_graph* g, int share)
 {
-    return g->kernel_layout == kLayoutHubRuns && share > 1 && !g->runs_shared ? kLayoutHubIdX2 : g->kernel_layout;
+    if (runs_layout(g->kernel_layout) && share > 1) return g->runs_shared ? kLayoutHubRuns : kLayoutHubIdX2;
+    return g->kernel_layout;
 }
 
 int resident_wgs(const bd_graph* g, int uniform, int share = 1)

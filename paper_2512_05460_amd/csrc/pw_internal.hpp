@@ -130,12 +130,16 @@ constexpr int kLayoutHubIdX2 = 7;
 // smaller copy (kRunWordsShared words); where the table does not fit it,
 // walk sharing runs code 7's kernels on these tables (run_kernel).
 constexpr int kLayoutHubRuns = 8;  // constants and builder: pw_runs.hpp
+// The same table in two 1,024-thread work groups per CU, one replica pair per
+// thread, 8 waves per SIMD (the table in at most 64 KB: BD_NARROW_HUBS).
+constexpr int kLayoutHubRunsNarrow = 9;
+constexpr bool runs_layout(int layout) { return layout == kLayoutHubRuns || layout == kLayoutHubRunsNarrow; }
 // LDS words of the run table and reciprocals in the walk-sharing kernels of
 // code 8 (24 KB: with their other LDS, four such groups per CU)
 constexpr uint32_t kRunWordsShared = 6144;
 constexpr bool hubid_layout(int layout)
 {
-    return layout == kLayoutHubId || layout == kLayoutHubIdX2 || layout == kLayoutHubRuns;
+    return layout == kLayoutHubId || layout == kLayoutHubIdX2 || runs_layout(layout);
 }
 // replica pairs a lane runs at once
 constexpr int lane_pairs(int layout) { return layout == kLayoutHubIdX2 || layout == kLayoutHubRuns ? 2 : 1; }
@@ -152,6 +156,7 @@ constexpr uint32_t hub_nodes(int threads, int layout)
     if (layout == kLayoutHubIdX2 && threads >= 1024) return 36864u;  // 144 KB: what the CU's 160 KB leaves
     // code 8: capacity in 32-bit words of the run table and the reciprocals
     if (layout == kLayoutHubRuns) return threads >= 1024 ? 36864u : kRunWordsShared - 1u;
+    if (layout == kLayoutHubRunsNarrow) return threads >= 1024 ? 16383u : kRunWordsShared - 1u;
     return (threads >= 1024 ? 8192u : 1024u) * (layout == kLayoutHubIdX2 ? 4u : layout == kLayoutHubId ? 2u : 1u);
 }
 // 32-bit words of the LDS hub copy (entries 0 .. hub_nodes, inclusive)

@@ -592,8 +592,12 @@ walk_kernel(WalkArgs A)
 template <int kLayout>
 static const void* walk_fn_l(int uniform, int share)
 {
-    if (share == 4) return uniform ? (const void*)walk_kernel<kLayout, 1, 4> : (const void*)walk_kernel<kLayout, 0, 4>;
-    if (share == 2) return uniform ? (const void*)walk_kernel<kLayout, 1, 2> : (const void*)walk_kernel<kLayout, 0, 2>;
+    if constexpr (kLayout != kLayoutHubRunsNarrow) {  // code 9 shares code 8's sharing kernels
+        if (share == 4)
+            return uniform ? (const void*)walk_kernel<kLayout, 1, 4> : (const void*)walk_kernel<kLayout, 0, 4>;
+        if (share == 2)
+            return uniform ? (const void*)walk_kernel<kLayout, 1, 2> : (const void*)walk_kernel<kLayout, 0, 2>;
+    }
     return uniform ? (const void*)walk_kernel<kLayout, 1, 1> : (const void*)walk_kernel<kLayout, 0, 1>;
 }
 
@@ -607,18 +611,27 @@ static const void* walk_fn(int layout, int uniform, int share)
     if (layout == kLayoutHubId) return walk_fn_l<kLayoutHubId>(uniform, share);
     if (layout == kLayoutHubIdX2) return walk_fn_l<kLayoutHubIdX2>(uniform, share);
     if (layout == kLayoutHubRuns) return walk_fn_l<kLayoutHubRuns>(uniform, share);
+    if (layout == kLayoutHubRunsNarrow) return walk_fn_l<kLayoutHubRunsNarrow>(uniform, share);
     return walk_fn_l<kLayoutCsr>(uniform, share);
 }
 
 template <int kLayout, int kUniform>
 static void launch_l(const WalkArgs& a, int share, uint32_t grid, hipStream_t st)
 {
-    if (share == 4)
-        hipLaunchKernelGGL((walk_kernel<kLayout, kUniform, 4>), dim3(grid), dim3(block_threads(kLayout, 4)), 0, st, a);
-    else if (share == 2)
-        hipLaunchKernelGGL((walk_kernel<kLayout, kUniform, 2>), dim3(grid), dim3(block_threads(kLayout, 2)), 0, st, a);
-    else
+    if constexpr (kLayout == kLayoutHubRunsNarrow) {  // code 9 shares code 8's sharing kernels
+        (void)share;
         hipLaunchKernelGGL((walk_kernel<kLayout, kUniform, 1>), dim3(grid), dim3(block_threads(kLayout, 1)), 0, st, a);
+    } else {
+        if (share == 4)
+            hipLaunchKernelGGL((walk_kernel<kLayout, kUniform, 4>), dim3(grid), dim3(block_threads(kLayout, 4)), 0, st,
+                               a);
+        else if (share == 2)
+            hipLaunchKernelGGL((walk_kernel<kLayout, kUniform, 2>), dim3(grid), dim3(block_threads(kLayout, 2)), 0, st,
+                               a);
+        else
+            hipLaunchKernelGGL((walk_kernel<kLayout, kUniform, 1>), dim3(grid), dim3(block_threads(kLayout, 1)), 0, st,
+                               a);
+    }
 }
 
 hipError_t launch_walk(const WalkArgs& a, int layout, int uniform, int share, uint32_t grid, hipStream_t st)
@@ -648,6 +661,9 @@ hipError_t launch_walk(const WalkArgs& a, int layout, int uniform, int share, ui
     } else if (layout == kLayoutHubRuns) {
         if (uniform) launch_l<kLayoutHubRuns, 1>(a, share, grid, st);
         else launch_l<kLayoutHubRuns, 0>(a, share, grid, st);
+    } else if (layout == kLayoutHubRunsNarrow) {
+        if (uniform) launch_l<kLayoutHubRunsNarrow, 1>(a, share, grid, st);
+        else launch_l<kLayoutHubRunsNarrow, 0>(a, share, grid, st);
     } else {
         if (uniform) launch_l<kLayoutCsr, 1>(a, share, grid, st);
         else launch_l<kLayoutCsr, 0>(a, share, grid, st);
@@ -714,7 +730,7 @@ __global__ void trace_kernel(GraphTables gt, uint32_t count, const int32_t* star
 {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     DevGraph G = make_graph(gt);
-    if constexpr (kLayout == kLayoutHubRuns) {
+    if constexpr (runs_layout(kLayout)) {
         // the run table in LDS, as the walk kernels read it
         __shared__ __align__(16) uint32_t lds[hub_words(1024, kLayout)];
         stage_hubs<kLayout>(G, lds, hub_nodes(1024, kLayout));
@@ -754,6 +770,7 @@ hipError_t launch_trace(const GraphTables& g, int layout, uint32_t count, const 
     else if (layout == kLayoutHubId) PW_TRACE(5);
     else if (layout == kLayoutHubIdX2) PW_TRACE(7);
     else if (layout == kLayoutHubRuns) PW_TRACE(8);
+    else if (layout == kLayoutHubRunsNarrow) PW_TRACE(9);
     else PW_TRACE(0);
 #undef PW_TRACE
     return hipGetLastError();
@@ -849,6 +866,7 @@ hipError_t launch_gather(const GraphTables& g, int layout, int chains, uint32_t 
     else if (layout == kLayoutHubId) PW_GATHER_C(5);
     else if (layout == kLayoutHubIdX2) PW_GATHER_C(7);
     else if (layout == kLayoutHubRuns) PW_GATHER_C(8);
+    else if (layout == kLayoutHubRunsNarrow) PW_GATHER_C(9);
     else PW_GATHER_C(0);
 #undef PW_GATHER_C
 #undef PW_GATHER

@@ -113,7 +113,9 @@ def test_storage_probe_flag_combinations():
                 full | binding.BD_WIDE_IDS, binding.BD_PROBE_STORAGE_IDS | binding.BD_LAYOUT_AUTO,
                 binding.BD_PROBE_STORAGE_IDS | binding.BD_LAYOUT_FAT | binding.BD_RELABEL_DEGREE,
                 binding.BD_LAYOUT_COMPACT | binding.BD_RELABEL_DEGREE | binding.BD_DIRECT_HUBS,
-                binding.BD_LAYOUT_COMPACT | binding.BD_RELABEL_DEGREE | binding.BD_NARROW_HUBS):
+                binding.BD_LAYOUT_COMPACT | binding.BD_RELABEL_DEGREE | binding.BD_NARROW_HUBS,
+                binding.BD_LAYOUT_COMPACT | binding.BD_RELABEL_DEGREE | binding.BD_WIDE_HUBS,
+                full | binding.BD_WIDE_HUBS | binding.BD_NARROW_HUBS):
         h = ctypes.c_void_p()
         rc = binding.lib().graph_load_csr(g.n, g.row_ptr.ctypes.data_as(ctypes.c_void_p),
                                           g.col.ctypes.data_as(ctypes.c_void_p), bad, None, ctypes.byref(h))

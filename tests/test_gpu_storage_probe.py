@@ -7,12 +7,12 @@ id), each row keeps the caller's neighbour order with the ids renamed. On that g
 results must equal the oracle's bit for bit (Algorithm 1: probe values,
 walks, per-probe Q, block means, estimates, in every mode, with split probes
 and with walk sharing), and its walks, reported in caller ids, are the same
-walks as every other layout's. The same holds for its three kernels: one
-work group per CU with two replica pairs per thread and every node's row
-offset and degree in LDS (the degree-run table, the default where it fits),
-the same with the row offsets of the 36,864 highest-degree nodes in LDS
-(BD_DIRECT_HUBS), and two work groups per CU with one pair per thread and
-16,384 offsets each (BD_NARROW_HUBS).
+walks as every other layout's. The same holds for its kernels: every node's
+row offset and degree in LDS (the degree-run table) in two work groups per CU
+with one replica pair per thread (the default where the table fits 64 KB,
+and BD_NARROW_HUBS) or in one group per CU with two pairs per thread
+(BD_WIDE_HUBS), and the row offsets of the highest-degree nodes instead
+(BD_DIRECT_HUBS: 36,864 in one group per CU, 16,384 in two).
 """
 
 import numpy as np
@@ -33,8 +33,10 @@ def relabelled(g):
     return graphs.storage_order(g)
 
 
-@pytest.fixture(scope="module", params=[(key, kernel) for kernel in (0, B.BD_DIRECT_HUBS, B.BD_NARROW_HUBS)
-                                        for key in ("ba1k", "cl100k")])
+KERNELS = (0, B.BD_WIDE_HUBS, B.BD_DIRECT_HUBS, B.BD_NARROW_HUBS, B.BD_NARROW_HUBS | B.BD_DIRECT_HUBS)
+
+
+@pytest.fixture(scope="module", params=[(key, kernel) for kernel in KERNELS for key in ("ba1k", "cl100k")])
 def pair(request):
     key, kernel = request.param
     g = graphs.workload_graph(key)
@@ -43,8 +45,8 @@ def pair(request):
     info = dg.info()
     assert info["layout"] == 5
     # nodes resolved in LDS: all with the run table, else the staged offsets
-    assert info["lds_hubs"] == {0: g.n, B.BD_DIRECT_HUBS: min(g.n, 36864),
-                                B.BD_NARROW_HUBS: min(g.n, 16384)}[kernel]
+    assert info["lds_hubs"] == {0: g.n, B.BD_WIDE_HUBS: g.n, B.BD_DIRECT_HUBS: min(g.n, 36864), B.BD_NARROW_HUBS: g.n,
+                                B.BD_NARROW_HUBS | B.BD_DIRECT_HUBS: min(g.n, 16384)}[kernel]
     yield g, g5, order, internal, dg
     dg.free()
 
