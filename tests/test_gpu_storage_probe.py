@@ -156,31 +156,37 @@ def test_bench_shape_sampled_probes(pair, mode):
 
 
 def test_run_table_with_large_blocks():
-    # The grid (2e6 nodes, degrees 1-4) needs blocks of 128 storage ids for its
-    # run table to fit: every node's entry through one-step walks against
-    # layout 3, and estimates equal to the per-node-offset kernel's
+    # The grid (2e6 nodes, degrees 1-4) needs blocks of 256 storage ids for its
+    # run table to fit two work groups per CU (128 for one): every node's entry
+    # through one-step walks against layout 3, and estimates equal to the
+    # per-node-offset kernel's, in both
     g = graphs.workload_graph("grid1414")
     dg = B.graph_load_csr(g.n, g.row_ptr, g.col, FLAGS)
+    wide = B.graph_load_csr(g.n, g.row_ptr, g.col, FLAGS | B.BD_WIDE_HUBS)
     direct = B.graph_load_csr(g.n, g.row_ptr, g.col, FLAGS | B.BD_DIRECT_HUBS)
     other = B.graph_load_csr(g.n, g.row_ptr, g.col, B.BD_LAYOUT_COMPACT | B.BD_RELABEL_DEGREE)
     try:
-        assert dg.info()["lds_hubs"] == g.n and direct.info()["lds_hubs"] == 36864
+        assert dg.info()["lds_hubs"] == g.n and wide.info()["lds_hubs"] == g.n
+        assert direct.info()["lds_hubs"] == 36864
         starts = np.arange(0, g.n, 3, dtype=np.int32)
         z = np.zeros(starts.size, dtype=np.int64)
         side = np.arange(starts.size) % 2
-        tr, _ = B.bd_walk_trace(dg, starts, z + 2, z, np.arange(starts.size) % 5, side, 2, SEED)
         tr3, _ = B.bd_walk_trace(other, starts, z + 2, z, np.arange(starts.size) % 5, side, 2, SEED)
-        assert np.array_equal(tr, tr3)
+        for h in (dg, wide):
+            tr, _ = B.bd_walk_trace(h, starts, z + 2, z, np.arange(starts.size) % 5, side, 2, SEED)
+            assert np.array_equal(tr, tr3)
         s, t = queries.uniform_pairs(g.n, 16, 41)
         L = np.array([10, 300, 2000, 5000] * 4, dtype=np.int32)
         pol = B.policy("fixed", B=2, R=100)
         for mode in ("plain", "batched"):
-            a = B.bd_query_batch(dg, s, t, 0.1, L, SEED, pol, B.exec_cfg(mode))
             b = B.bd_query_batch(direct, s, t, 0.1, L, SEED, pol, B.exec_cfg(mode))
-            assert np.array_equal(a["beta"], b["beta"]), mode
+            for h in (dg, wide):
+                a = B.bd_query_batch(h, s, t, 0.1, L, SEED, pol, B.exec_cfg(mode))
+                assert np.array_equal(a["beta"], b["beta"]), mode
     finally:
         other.free()
         direct.free()
+        wide.free()
         dg.free()
 
 
