@@ -211,7 +211,7 @@ def small_queries(B, torch, stream):
     return out
 
 
-def grid_batched(B, torch, stream, plain_sample=512, layout="hubsid"):
+def grid_batched(B, torch, stream, plain_sample=512, layout="hubsid", profile_chunk_pairs=0):
     """Mixed eps and L in one persistent launch: the 1,414 x 1,414 grid (5% of
     edges removed), 65,536 queries, eps over {0.02, 0.05, 0.1}, L over {500,
     2000, 5000}, throughput walk counts; tables hubs first with the probe on
@@ -219,7 +219,9 @@ def grid_batched(B, torch, stream, plain_sample=512, layout="hubsid"):
     layout="auto" the library's choice (fat at this size); chunking from the
     autotuner, the launches captured into a hipGraph and run from it. The
     plain mode (one query per launch) runs the first `plain_sample` queries
-    of the same set on the same tables."""
+    of the same set on the same tables. With profile_chunk_pairs > 0 only one
+    eager batched launch of the whole set runs, with that chunking and eight
+    queues (for a profiler's counters on exactly that launch)."""
     from paper_2512_05460_amd.budgets import BUDGETS, budget_policy
     from synth import graphs, queries
 
@@ -234,6 +236,17 @@ def grid_batched(B, torch, stream, plain_sample=512, layout="hubsid"):
     seed = graphs.PHILOX_SEED
     plan = B.bd_plan(dg, s, t, eps, Ls, pol)
     steps = float(plan["walk_steps"].sum())
+    if profile_chunk_pairs > 0:
+        ex = B.exec_cfg("batched", chunk_pairs=profile_chunk_pairs, queues=8)
+        log(f"grid: one batched launch of {nq} queries, {steps:.3e} walk steps, chunk_pairs={profile_chunk_pairs}")
+        r, st = B.bd_query_batch(dg, s, t, eps, Ls, seed, pol, ex, stream=stream, with_stats=True)
+        torch.cuda.synchronize()
+        assert np.all(r["status"] == 0)
+        dg.free()
+        return {"profile_launch": {"chunk_pairs": profile_chunk_pairs, "queues": 8, "walk_steps": steps,
+                                   "walk_kernel_launches": int(st["launches"]), "kernel_ms": st["walk_kernel_ms"],
+                                   "kernel_walk_steps_per_s": steps / (st["walk_kernel_ms"] / 1e3)},
+                "lds_nodes": info["lds_hubs"]}
     na = min(nq, 2048)
     log(f"grid: {nq} queries, {steps:.3e} walk steps; autotune on the first {na}")
     best, times = B.bd_autotune(dg, s[:na], t[:na], eps[:na], Ls[:na], seed, pol, stream=stream)
@@ -688,6 +701,9 @@ def main():
     ap.add_argument("--no-roofline", action="store_true")
     ap.add_argument("--no-small", action="store_true")
     ap.add_argument("--no-grid", action="store_true")
+    ap.add_argument("--grid-profile", type=int, default=0, metavar="CHUNK_PAIRS",
+                    help="grid block: only one eager batched launch of the whole set with this chunking (for "
+                         "profiler counters)")
     ap.add_argument("--grid-layout", choices=["auto", "hubsid"], default="hubsid",
                     help="grid tables: hubs first with the probe on storage ids (the degree-run table in LDS; "
                          "the default), or the library's choice (fat at this size)")
@@ -848,7 +864,8 @@ def main():
     if not args.no_small:
         extra["small_queries"] = small_queries(B, torch, stream)
     if not args.no_grid:
-        extra["grid_batched"] = grid_batched(B, torch, stream, layout=args.grid_layout)
+        extra["grid_batched"] = grid_batched(B, torch, stream, layout=args.grid_layout,
+                                             profile_chunk_pairs=args.grid_profile)
     if not args.no_served_cl10m:
         extra["served_cl10m"] = served_cl10m(B, torch)
     if not args.no_scale_cl40m and not args.scale:
