@@ -173,19 +173,23 @@ def cpu_baseline(g, s, t, plans, seed, target_s=20.0):
                        f"{dt:.1f} s; queries/s = steps/s / mean full-query steps of the batch")}
 
 
-def small_queries(B, torch, stream):
+def small_queries(B, torch, stream, layout="compact"):
     """The regime where one query cannot fill the GPU: BA n=1,000, 256 uniform
     pairs, eps=0.1, L=200 (a few 10^8 walk steps per query), plain vs batched
-    vs batched replayed from a captured hipGraph."""
+    vs batched replayed from a captured hipGraph; tables compact, or
+    layout="hubsid" hubs first with the probe on storage ids."""
     from paper_2512_05460_amd.budgets import budget_policy
     from synth import graphs, queries
 
     g = graphs.workload_graph("ba1k")
     s, t = queries.uniform_pairs(g.n, 256, graphs.GRAPH_SEED + 0 + graphs.QUERY_SEED_OFFSET)
-    dg = B.graph_load_csr(g.n, g.row_ptr, g.col, B.BD_LAYOUT_COMPACT)
+    flags = {"compact": B.BD_LAYOUT_COMPACT,
+             "hubsid": B.BD_LAYOUT_COMPACT | B.BD_RELABEL_DEGREE | B.BD_PROBE_STORAGE_IDS}[layout]
+    dg = B.graph_load_csr(g.n, g.row_ptr, g.col, flags)
     pol = budget_policy("ba1k")
     seed = graphs.PHILOX_SEED
-    out = {"workload": "Barabasi-Albert n=1,000 m=3; 256 uniform pairs; eps=0.1, L=200"}
+    out = {"workload": "Barabasi-Albert n=1,000 m=3; 256 uniform pairs; eps=0.1, L=200",
+           "layout": LAYOUT_NAMES[dg.info()["layout"]], "lds_nodes": dg.info()["lds_hubs"]}
 
     def timed(fn, reps=3):
         fn()
@@ -701,6 +705,8 @@ def main():
     ap.add_argument("--no-roofline", action="store_true")
     ap.add_argument("--no-small", action="store_true")
     ap.add_argument("--no-grid", action="store_true")
+    ap.add_argument("--small-layout", choices=["compact", "hubsid"], default="compact",
+                    help="tables of the small-query block")
     ap.add_argument("--grid-profile", type=int, default=0, metavar="CHUNK_PAIRS",
                     help="grid block: only one eager batched launch of the whole set with this chunking (for "
                          "profiler counters)")
@@ -862,7 +868,7 @@ def main():
             "proxy_rel_error": {"p50": float(np.median(proxy)), "p90": float(np.percentile(proxy, 90)),
                                 "max": float(proxy.max()), "frac_within_eps": float((proxy <= 0.1).mean())}}
     if not args.no_small:
-        extra["small_queries"] = small_queries(B, torch, stream)
+        extra["small_queries"] = small_queries(B, torch, stream, layout=args.small_layout)
     if not args.no_grid:
         extra["grid_batched"] = grid_batched(B, torch, stream, layout=args.grid_layout,
                                              profile_chunk_pairs=args.grid_profile)
