@@ -112,6 +112,17 @@ def load_reference(path: str) -> dict:
     return {name: data[:, i] for i, name in enumerate(names)}
 
 
+def select_pairs(ref: dict, only_L: int = 0, offset: int = 0, pairs: int = 0) -> np.ndarray:
+    """Rows of a reference file to use: those whose L column equals only_L
+    (all when 0), skipping the first `offset` of them, then the first `pairs`
+    (all when 0)."""
+    sel = np.ones(ref["index"].size, dtype=bool)
+    if only_L:
+        sel &= ref["L"] == only_L
+    idx = np.flatnonzero(sel)[offset:]
+    return idx[:pairs] if pairs else idx
+
+
 def main(argv=None):
     from synth import graphs  # seeded workload inputs
 
@@ -135,12 +146,7 @@ def main(argv=None):
         print(*x, flush=True)
 
     ref = load_reference(a.ref)
-    sel = np.ones(ref["index"].size, dtype=bool)
-    if a.only_L:
-        sel &= ref["L"] == a.only_L
-    idx = np.flatnonzero(sel)[a.offset:]
-    if a.pairs:
-        idx = idx[:a.pairs]
+    idx = select_pairs(ref, a.only_L, a.offset, a.pairs)
     s = ref["s"][idx].astype(np.int32)
     t = ref["t"][idx].astype(np.int32)
     beta = ref["beta_cg"][idx]

@@ -42,3 +42,16 @@ def test_reference_columns_by_name():
         assert np.all(ref["beta_cg"] >= (1.0 / ref["d_s"] + 1.0 / ref["d_t"]) ** 2 / 8)
     ref = load_reference(os.path.join(here, "cl40m_cg_reference.txt"))
     assert set(np.unique(ref["L"])) == {1000.0, 10000.0}
+
+
+def test_select_pairs():
+    from paper_2512_05460_amd.calibrate import load_reference, select_pairs
+    import os
+    ref = load_reference(os.path.join(os.path.dirname(__file__), "golden", "cl40m_cg_reference.txt"))
+    all10 = np.flatnonzero(ref["L"] == 10000)
+    assert all10.size == 31 and np.all(np.diff(all10) > 0)
+    assert np.array_equal(select_pairs(ref, 10000), all10)
+    assert np.array_equal(select_pairs(ref, 10000, 0, 16), all10[:16])
+    assert np.array_equal(select_pairs(ref, 10000, 16), all10[16:])
+    assert np.array_equal(select_pairs(ref, 0, 0, 8), np.arange(8))
+    assert np.array_equal(np.sort(np.concatenate([select_pairs(ref, 1000), all10])), np.arange(ref["index"].size))
