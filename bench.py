@@ -306,7 +306,7 @@ def grid_batched(B, torch, stream, plain_sample=512, layout="hubsid", profile_ch
     }
 
 
-def served_cl10m(B, torch, seconds_per_load=10.0, calibrated_queries=8):
+def served_cl10m(B, torch, seconds_per_load=10.0, calibrated_queries=8, profile=False):
     """Continuous batching under Poisson arrivals: Chung-Lu n=10^7 (mean degree
     10, exponent 2.3, largest component, resident on the device in the layout
     the library picks: fat at this size); request batches of 2^U uniform pairs (U uniform
@@ -341,6 +341,12 @@ def served_cl10m(B, torch, seconds_per_load=10.0, calibrated_queries=8):
         assert np.all(out["status"] == 0)
     dt = time.perf_counter() - t0
     cap_qps = nq_burst / dt
+    if profile:  # the capacity burst only (for a profiler's counters on its slices)
+        steps = sum(float(B.bd_plan(dg, x[0], x[1], x[2], Lq, pol)["walk_steps"].sum()) for x in burst)
+        srv.destroy()
+        dg.free()
+        return {"profile_burst": {"requests": len(burst), "queries": nq_burst, "seconds": dt,
+                                  "queries_per_s": cap_qps, "walk_steps": steps, "walk_steps_per_s": steps / dt}}
     out = {"workload": ("Chung-Lu n=10,000,000 mean degree 10 exponent 2.3 LCC; Poisson arrivals of request "
                         "batches of 2^U uniform pairs, U uniform on 0..12; eps per query from {0.02, 0.05, 0.1}; "
                         "L=1000"),
@@ -705,6 +711,8 @@ def main():
     ap.add_argument("--no-roofline", action="store_true")
     ap.add_argument("--no-small", action="store_true")
     ap.add_argument("--no-grid", action="store_true")
+    ap.add_argument("--served-profile", action="store_true",
+                    help="n=1e7 served block: only the capacity burst (for profiler counters on its slices)")
     ap.add_argument("--small-layout", choices=["compact", "hubsid"], default="compact",
                     help="tables of the small-query block")
     ap.add_argument("--grid-profile", type=int, default=0, metavar="CHUNK_PAIRS",
@@ -873,7 +881,7 @@ def main():
         extra["grid_batched"] = grid_batched(B, torch, stream, layout=args.grid_layout,
                                              profile_chunk_pairs=args.grid_profile)
     if not args.no_served_cl10m:
-        extra["served_cl10m"] = served_cl10m(B, torch)
+        extra["served_cl10m"] = served_cl10m(B, torch, profile=args.served_profile)
     if not args.no_scale_cl40m and not args.scale:
         extra["scale_cl40m"] = scale_cl40m_default(B, torch, stream)
     if args.scale:
